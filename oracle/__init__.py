@@ -81,6 +81,7 @@ def lib():
             "ref_qaoa_grad_fd": (None, [c_int, c_int, _c_i32_p, vp, c_int, _c_f64_p, c_double, _c_f64_p]),
             "ref_depol_threshold": (c_u32, [c_double]),
             "ref_traj_run_one": (c_int, [_c_cplx_p, c_int, vp, c_int, c_double, c_u64, c_u32, vp, c_int]),
+            "ref_threads": (c_int, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -115,6 +116,11 @@ def _nq(psi: np.ndarray) -> int:
     n = int(psi.size).bit_length() - 1
     assert psi.size == 1 << n and psi.dtype == np.complex128 and psi.flags.c_contiguous
     return n
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's element-wise loops use."""
+    return int(lib().ref_threads())
 
 
 # ---------------------------------------------------------------- RNG

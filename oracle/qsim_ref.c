@@ -536,3 +536,11 @@ EXPORT int ref_traj_run_one(cplx *psi, int n, const ref_gate *g, int count, doub
     }
     return nins;
 }
+
+/* Threads an OpenMP loop of the oracle runs on (reported with CPU timings). */
+#ifdef _OPENMP
+#include <omp.h>
+EXPORT int ref_threads(void) { return omp_get_max_threads(); }
+#else
+EXPORT int ref_threads(void) { return 1; }
+#endif

@@ -1,0 +1,172 @@
+// Internal header of the HIP library: amplitude types, small device helpers,
+// error plumbing shared by the translation units of libqsim_hip.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "../../include/qsim.h"
+
+namespace qs {
+
+using u64 = uint64_t;
+using u32 = uint32_t;
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *where);
+
+#define QS_HIP(call)                                          \
+    do {                                                      \
+        hipError_t _e = (call);                               \
+        if (_e != hipSuccess) return ::qs::hip_fail(_e, #call); \
+    } while (0)
+
+#define QS_LAUNCH_CHECK(where)                                   \
+    do {                                                         \
+        hipError_t _e = hipGetLastError();                       \
+        if (_e != hipSuccess) return ::qs::hip_fail(_e, where);  \
+    } while (0)
+
+// ------------------------------------------------------------------ amplitude types
+// Amplitudes are clang ext-vector pairs (x = re, y = im): 16-byte aligned for
+// c128 so one global_load_dwordx4 moves one amplitude.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <typename R> struct Vec2;
+template <> struct Vec2<double> { using T = d2v; };
+template <> struct Vec2<float> { using T = f2v; };
+template <typename R> using cx = typename Vec2<R>::T;
+
+// 2x2 matrix, row-major, interleaved (re, im); row = output.
+template <typename R> struct Mat2 {
+    R m[8];
+};
+
+template <typename R> __host__ Mat2<R> to_mat(const double *u) {
+    Mat2<R> o;
+    for (int k = 0; k < 8; ++k) o.m[k] = (R)u[k];
+    return o;
+}
+
+template <typename R> __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    cx<R> r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+// (u_r0 * a + u_r1 * b) for row r of a Mat2.
+template <typename R> __device__ __forceinline__ cx<R> row_apply(const R *m, cx<R> a, cx<R> b) {
+    cx<R> r;
+    r.x = m[0] * a.x - m[1] * a.y + m[2] * b.x - m[3] * b.y;
+    r.y = m[0] * a.y + m[1] * a.x + m[2] * b.y + m[3] * b.x;
+    return r;
+}
+
+template <typename R> __device__ __forceinline__ void apply2(const Mat2<R> &u, cx<R> &a, cx<R> &b) {
+    const cx<R> na = row_apply<R>(u.m, a, b);
+    const cx<R> nb = row_apply<R>(u.m + 4, a, b);
+    a = na;
+    b = nb;
+}
+
+template <typename R> __device__ __forceinline__ double norm2d(cx<R> a) {
+    return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+}
+
+// Insert a zero bit at position b of k.
+__device__ __forceinline__ u64 insert0(u64 k, int b) {
+    const u64 lo = k & ((1ull << b) - 1);
+    return ((k >> b) << (b + 1)) | lo;
+}
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): ten rounds of the 4x32 Philox bijection;
+// multipliers 0xD2511F53 / 0xCD9E8D57, key schedule bumped by the Weyl
+// constants 0x9E3779B9 / 0xBB67AE85 between rounds.
+struct Philox4 {
+    u32 v[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(u32 c0, u32 c1, u32 c2, u32 c3, u32 k0, u32 k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const u32 lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const u32 lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const u32 n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Philox4{{c0, c1, c2, c3}};
+}
+
+// Counter-word-2 stream tags (one per use of a seed).
+constexpr u32 kTagInitRandom = 1, kTagSample = 2, kTagTraj = 3;
+
+// 53-bit uniform in [0,1) from (lo, hi) words.
+__device__ __forceinline__ double u53(u32 lo, u32 hi) {
+    const u64 v = ((u64)hi << 32) | lo;
+    return (double)(v >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------------------ Max-Cut graph (kernel argument)
+constexpr int kMaxEdges = 256;
+struct Graph {
+    int ne;
+    int weighted;
+    uint8_t u[kMaxEdges], v[kMaxEdges];
+};
+struct Weights {
+    double w[kMaxEdges];
+};
+
+// C(k) for unit weights: number of edges cut by bipartition k.
+__device__ __forceinline__ int cut_count(u64 k, const Graph &g) {
+    int c = 0;
+    for (int e = 0; e < g.ne; ++e) c += (int)(((k >> g.u[e]) ^ (k >> g.v[e])) & 1u);
+    return c;
+}
+
+__device__ __forceinline__ double cut_weighted(u64 k, const Graph &g, const double *w) {
+    double c = 0.0;
+    for (int e = 0; e < g.ne; ++e)
+        if (((k >> g.u[e]) ^ (k >> g.v[e])) & 1u) c += w[e];
+    return c;
+}
+
+// ------------------------------------------------------------------ launch geometry
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(u64 work, u64 per_block) {
+    u64 g = (work + per_block - 1) / per_block;
+    return (unsigned)(g ? g : 1);
+}
+
+}  // namespace qs
+
+// ------------------------------------------------------------------ handle
+struct qs_state {
+    int n;
+    int dtype;
+    void *buf;
+    size_t bytes;
+    hipStream_t stream;
+    int device;
+    double *scratch;        // device: partial sums (kScratchDoubles)
+    size_t scratch_doubles;
+    void *plan_cache;       // host-side cache of uploaded block plans
+};
+
+namespace qs {
+constexpr size_t kScratchDoubles = (size_t)1 << 20;  // 8 MiB of partials per handle
+inline size_t amp_bytes(int dtype) { return dtype == QS_C128 ? 16 : 8; }
+}  // namespace qs

@@ -1,0 +1,337 @@
+// Streaming kernels: state initialisation and single gates applied as one
+// read+write pass over the amplitudes that the gate touches.
+//
+// A one-qubit gate (eq. 3) couples amplitude i (bit q clear) with i + 2^q and
+// nothing else, so every pair is independent.  Pair k of the 2^{n-1} pairs is
+// i0 = k with a zero inserted at bit q; consecutive lanes take consecutive k,
+// so for q >= 6 a wavefront touches two contiguous 1 KiB runs (c128) and for
+// q < 6 the two partners of a lane sit in the same 128-byte line.  Each thread
+// keeps PPT pairs in flight to cover HBM latency.
+#include "launch.h"
+#include "vec.h"
+
+namespace qs {
+
+// ------------------------------------------------------------------ initialisation
+
+template <typename R> __global__ __launch_bounds__(kBlock) void k_fill_basis(cx<R> *psi, u64 N, u64 index) {
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
+        cx<R> v;
+        v.x = (i == index) ? (R)1 : (R)0;
+        v.y = (R)0;
+        st_nt(psi + i, v);
+    }
+}
+
+template <typename R> __global__ __launch_bounds__(kBlock) void k_fill_uniform(cx<R> *psi, u64 N, double amp) {
+    cx<R> v;
+    v.x = (R)amp;
+    v.y = (R)0;
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) st_nt(psi + i, v);
+}
+
+// Unnormalised draw: (2u - 1) + i (2v - 1), u, v from Philox(seed; i_lo, i_hi, tag, 0).
+template <typename R> __global__ __launch_bounds__(kBlock) void k_fill_random(cx<R> *psi, u64 N, u32 k0, u32 k1) {
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
+        const Philox4 x = philox4x32_10((u32)i, (u32)(i >> 32), kTagInitRandom, 0u, k0, k1);
+        cx<R> v;
+        v.x = (R)(2.0 * u53(x.v[0], x.v[1]) - 1.0);
+        v.y = (R)(2.0 * u53(x.v[2], x.v[3]) - 1.0);
+        st_nt(psi + i, v);
+    }
+}
+
+// psi *= 1 / sqrt(*norm_dev), factor read on the device (stream-ordered).
+template <typename R> __global__ __launch_bounds__(kBlock) void k_scale_inv_sqrt(cx<R> *psi, u64 N, const double *norm_dev) {
+    const double f = 1.0 / sqrt(*norm_dev);
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
+        cx<R> v = psi[i];
+        v.x = (R)((double)v.x * f);
+        v.y = (R)((double)v.y * f);
+        psi[i] = v;
+    }
+}
+
+static unsigned stream_grid(u64 N) {
+    // Grid-stride fill kernels: enough blocks to fill 256 CUs many times over.
+    u64 g = (N + kBlock - 1) / kBlock;
+    return (unsigned)(g < 65536 ? (g ? g : 1) : 65536);
+}
+
+int launch_init_basis(qs_state *s, u64 index) {
+    const u64 N = 1ull << s->n;
+    if (s->dtype == QS_C128)
+        hipLaunchKernelGGL(k_fill_basis<double>, dim3(stream_grid(N)), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, N, index);
+    else
+        hipLaunchKernelGGL(k_fill_basis<float>, dim3(stream_grid(N)), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, N, index);
+    QS_LAUNCH_CHECK("init_basis");
+    return QS_OK;
+}
+
+int launch_init_uniform(qs_state *s) {
+    const u64 N = 1ull << s->n;
+    const double amp = 1.0 / sqrt((double)N);
+    if (s->dtype == QS_C128)
+        hipLaunchKernelGGL(k_fill_uniform<double>, dim3(stream_grid(N)), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, N, amp);
+    else
+        hipLaunchKernelGGL(k_fill_uniform<float>, dim3(stream_grid(N)), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, N, amp);
+    QS_LAUNCH_CHECK("init_uniform");
+    return QS_OK;
+}
+
+int launch_init_random(qs_state *s, u64 seed) {
+    const u64 N = 1ull << s->n;
+    const u32 k0 = (u32)seed, k1 = (u32)(seed >> 32);
+    if (s->dtype == QS_C128)
+        hipLaunchKernelGGL(k_fill_random<double>, dim3(stream_grid(N)), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, N, k0, k1);
+    else
+        hipLaunchKernelGGL(k_fill_random<float>, dim3(stream_grid(N)), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, N, k0, k1);
+    QS_LAUNCH_CHECK("init_random");
+    // Normalise: FP64 norm into the handle's result slot, then scale on device.
+    double *norm = s->scratch + kScratchDoubles - 8;
+    int rc = launch_marginals(s, kMargNorm, 0, norm);
+    if (rc != QS_OK) return rc;
+    return launch_scale(s, norm);
+}
+
+int launch_scale(qs_state *s, const double *norm_dev) {
+    const u64 N = 1ull << s->n;
+    if (s->dtype == QS_C128)
+        hipLaunchKernelGGL(k_scale_inv_sqrt<double>, dim3(stream_grid(N)), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, N, norm_dev);
+    else
+        hipLaunchKernelGGL(k_scale_inv_sqrt<float>, dim3(stream_grid(N)), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, N, norm_dev);
+    QS_LAUNCH_CHECK("scale");
+    return QS_OK;
+}
+
+// ------------------------------------------------------------------ one-qubit gate (eq. 3)
+
+template <typename R, int PPT, bool NT>
+__global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u64 npairs, int q, Mat2<R> u) {
+    const u64 s = 1ull << q;
+    const u64 first = (u64)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+    cx<R> a[PPT], b[PPT];
+    u64 i0[PPT];
+    if ((u64)(blockIdx.x + 1) * (kBlock * PPT) <= npairs) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            i0[j] = insert0(first + (u64)j * kBlock, q);
+            a[j] = ld<NT>(psi + i0[j]);
+            b[j] = ld<NT>(psi + i0[j] + s);
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            apply2<R>(u, a[j], b[j]);
+            st<NT>(psi + i0[j], a[j]);
+            st<NT>(psi + i0[j] + s, b[j]);
+        }
+    } else {
+        for (int j = 0; j < PPT; ++j) {
+            const u64 k = first + (u64)j * kBlock;
+            if (k >= npairs) break;
+            const u64 i = insert0(k, q);
+            cx<R> x = psi[i], y = psi[i + s];
+            apply2<R>(u, x, y);
+            psi[i] = x;
+            psi[i + s] = y;
+        }
+    }
+}
+
+// Variant selection (pairs per thread, non-temporal hints).  The default was
+// chosen by measuring 32-qubit sweeps; QSIM_1Q_VARIANT overrides it for tuning.
+static int variant_1q() {
+    static int v = [] {
+        const char *e = getenv("QSIM_1Q_VARIANT");
+        return e ? atoi(e) : 2;
+    }();
+    return v;
+}
+
+template <typename R> static int launch_1q_t(qs_state *s, int q, const double *u) {
+    const u64 npairs = 1ull << (s->n - 1);
+    const Mat2<R> m = to_mat<R>(u);
+    cx<R> *psi = (cx<R> *)s->buf;
+    switch (variant_1q()) {
+    case 1: hipLaunchKernelGGL((k_apply_1q<R, 1, false>), dim3(grid_for(npairs, kBlock * 1)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
+    case 3: hipLaunchKernelGGL((k_apply_1q<R, 4, false>), dim3(grid_for(npairs, kBlock * 4)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
+    case 4: hipLaunchKernelGGL((k_apply_1q<R, 2, true>), dim3(grid_for(npairs, kBlock * 2)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
+    case 5: hipLaunchKernelGGL((k_apply_1q<R, 4, true>), dim3(grid_for(npairs, kBlock * 4)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
+    case 6: hipLaunchKernelGGL((k_apply_1q<R, 1, true>), dim3(grid_for(npairs, kBlock * 1)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
+    default: hipLaunchKernelGGL((k_apply_1q<R, 2, false>), dim3(grid_for(npairs, kBlock * 2)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
+    }
+    QS_LAUNCH_CHECK("apply_1q");
+    return QS_OK;
+}
+
+int launch_apply_1q(qs_state *s, int q, const double *u) {
+    return s->dtype == QS_C128 ? launch_1q_t<double>(s, q, u) : launch_1q_t<float>(s, q, u);
+}
+
+// ------------------------------------------------------------------ controlled one-qubit gate
+// Only the 2^{n-2} pairs whose control bit is 1 are read and written.
+
+template <typename R, int PPT>
+__global__ __launch_bounds__(kBlock) void k_apply_c1q(cx<R> *__restrict__ psi, u64 nquads, int c, int t, Mat2<R> u) {
+    const int lo = c < t ? c : t, hi = c < t ? t : c;
+    const u64 sc = 1ull << c, st_ = 1ull << t;
+    const u64 first = (u64)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+    cx<R> a[PPT], b[PPT];
+    u64 i0[PPT];
+    bool ok[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const u64 k = first + (u64)j * kBlock;
+        ok[j] = k < nquads;
+        i0[j] = insert0(insert0(k, lo), hi) | sc;
+        if (ok[j]) {
+            a[j] = psi[i0[j]];
+            b[j] = psi[i0[j] | st_];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (ok[j]) {
+            apply2<R>(u, a[j], b[j]);
+            psi[i0[j]] = a[j];
+            psi[i0[j] | st_] = b[j];
+        }
+    }
+}
+
+template <typename R> static int launch_c1q_t(qs_state *s, int c, int t, const double *u) {
+    const u64 nquads = 1ull << (s->n - 2);
+    hipLaunchKernelGGL((k_apply_c1q<R, 2>), dim3(grid_for(nquads, kBlock * 2)), dim3(kBlock), 0, s->stream, (cx<R> *)s->buf, nquads, c, t,
+                       to_mat<R>(u));
+    QS_LAUNCH_CHECK("apply_c1q");
+    return QS_OK;
+}
+
+int launch_apply_c1q(qs_state *s, int c, int t, const double *u) {
+    return s->dtype == QS_C128 ? launch_c1q_t<double>(s, c, t, u) : launch_c1q_t<float>(s, c, t, u);
+}
+
+// ------------------------------------------------------------------ two-qubit diagonal and SWAP
+// Both enumerate the 2^{n-2} quads (bits q0, q1 cleared).  A diagonal entry
+// equal to exactly 1 is skipped (touch mask), so CZ and controlled phases read
+// and write only the |11> quarter of the state.
+
+template <typename R> struct Diag4 {
+    R d[8];
+};
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_apply_diag2(cx<R> *__restrict__ psi, u64 nquads, int q0, int q1, Diag4<R> d, int touch) {
+    const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
+    const u64 k = (u64)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= nquads) return;
+    const u64 base = insert0(insert0(k, lo), hi);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (!((touch >> e) & 1)) continue;
+        const u64 i = base | ((u64)(e & 1) << q0) | ((u64)(e >> 1) << q1);
+        cx<R> f;
+        f.x = d.d[2 * e];
+        f.y = d.d[2 * e + 1];
+        psi[i] = cmul<R>(psi[i], f);
+    }
+}
+
+template <typename R> __global__ __launch_bounds__(kBlock) void k_apply_swap(cx<R> *__restrict__ psi, u64 nquads, int a, int b) {
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    const u64 k = (u64)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= nquads) return;
+    const u64 base = insert0(insert0(k, lo), hi);
+    const u64 i = base | (1ull << a), j = base | (1ull << b);
+    const cx<R> x = psi[i], y = psi[j];
+    psi[i] = y;
+    psi[j] = x;
+}
+
+template <typename R> static int launch_diag2_t(qs_state *s, int q0, int q1, const double *d) {
+    const u64 nquads = 1ull << (s->n - 2);
+    Diag4<R> dd;
+    int touch = 0;
+    for (int e = 0; e < 4; ++e) {
+        dd.d[2 * e] = (R)d[2 * e];
+        dd.d[2 * e + 1] = (R)d[2 * e + 1];
+        if (!(d[2 * e] == 1.0 && d[2 * e + 1] == 0.0)) touch |= 1 << e;
+    }
+    if (!touch) return QS_OK;
+    hipLaunchKernelGGL(k_apply_diag2<R>, dim3(grid_for(nquads, kBlock)), dim3(kBlock), 0, s->stream, (cx<R> *)s->buf, nquads, q0, q1, dd, touch);
+    QS_LAUNCH_CHECK("apply_diag2");
+    return QS_OK;
+}
+
+int launch_apply_diag2(qs_state *s, int q0, int q1, const double *d) {
+    return s->dtype == QS_C128 ? launch_diag2_t<double>(s, q0, q1, d) : launch_diag2_t<float>(s, q0, q1, d);
+}
+
+int launch_apply_swap(qs_state *s, int a, int b) {
+    const u64 nquads = 1ull << (s->n - 2);
+    if (s->dtype == QS_C128)
+        hipLaunchKernelGGL(k_apply_swap<double>, dim3(grid_for(nquads, kBlock)), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, nquads, a, b);
+    else
+        hipLaunchKernelGGL(k_apply_swap<float>, dim3(grid_for(nquads, kBlock)), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, nquads, a, b);
+    QS_LAUNCH_CHECK("apply_swap");
+    return QS_OK;
+}
+
+// ------------------------------------------------------------------ QAOA cost layer exp(-i gamma C)
+// Unit weights: C(k) is an integer in [0, E]; each block builds the table
+// exp(-i gamma c) for c = 0..E in LDS and then streams its amplitudes.
+// Weighted edges: the phase is evaluated per amplitude.
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cut_phase(cx<R> *__restrict__ psi, u64 N, Graph g, double gamma) {
+    __shared__ double2 tab[kMaxEdges + 1];
+    for (int c = threadIdx.x; c <= g.ne; c += kBlock) {
+        double sn, cs;
+        sincos(gamma * (double)c, &sn, &cs);
+        tab[c] = make_double2(cs, -sn);
+    }
+    __syncthreads();
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
+        const double2 f = tab[cut_count(i, g)];
+        cx<R> a = psi[i];
+        cx<R> r;
+        r.x = (R)(a.x * f.x - a.y * f.y);
+        r.y = (R)(a.x * f.y + a.y * f.x);
+        psi[i] = r;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cut_phase_w(cx<R> *__restrict__ psi, u64 N, Graph g, Weights w, double gamma) {
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
+        double sn, cs;
+        sincos(gamma * cut_weighted(i, g, w.w), &sn, &cs);
+        cx<R> a = psi[i];
+        cx<R> r;
+        r.x = (R)(a.x * cs + a.y * sn);
+        r.y = (R)(a.y * cs - a.x * sn);
+        psi[i] = r;
+    }
+}
+
+int launch_cut_phase(qs_state *s, const Graph &g, const Weights *w, double gamma) {
+    const u64 N = 1ull << s->n;
+    u64 blocks = (N + kBlock * 16 - 1) / (kBlock * 16);
+    if (blocks > 16384) blocks = 16384;
+    const dim3 grid((unsigned)(blocks ? blocks : 1));
+    if (w) {
+        if (s->dtype == QS_C128)
+            hipLaunchKernelGGL(k_cut_phase_w<double>, grid, dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, N, g, *w, gamma);
+        else
+            hipLaunchKernelGGL(k_cut_phase_w<float>, grid, dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, N, g, *w, gamma);
+    } else {
+        if (s->dtype == QS_C128)
+            hipLaunchKernelGGL(k_cut_phase<double>, grid, dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, N, g, gamma);
+        else
+            hipLaunchKernelGGL(k_cut_phase<float>, grid, dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, N, g, gamma);
+    }
+    QS_LAUNCH_CHECK("cut_phase");
+    return QS_OK;
+}
+
+}  // namespace qs

@@ -1,0 +1,221 @@
+// Fused gate blocks: several consecutive gates applied per read+write pass.
+//
+// A pass works on tiles.  The pass owns a set T of tb qubits (tb <= 12 for
+// c128, 13 for c64, i.e. a 64 KiB tile); each workgroup loads the 2^tb
+// amplitudes that share one value of the other n - tb bits into LDS, applies
+// every gate of the pass there (one barrier per gate) and writes the tile
+// back.  T always contains the lowest qubits so that each load/store
+// instruction covers whole 128-byte lines.  A gate can join a pass when its
+// target qubits lie in T: one-qubit and controlled gates need their target in
+// T (a control outside T is constant over the tile and is resolved per tile);
+// diagonal gates need nothing; SWAP needs both qubits in T.
+//
+// The sequential order of the gate list is kept: a pass takes the longest
+// prefix of the remaining gates whose targets fit, so the result equals
+// applying the gates one after the other.
+#include <algorithm>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "launch.h"
+
+namespace qs {
+
+struct DGate {
+    int32_t kind;
+    int8_t p0, p1;  // tile-bit positions of q0 / q1, -1 when outside the tile
+    int8_t q0, q1;
+    int32_t pad;
+    double u[8];
+};
+
+struct DPass {
+    int tb;
+    int nrest;
+    uint8_t T[16];     // tile bit -> qubit (ascending)
+    uint8_t rest[40];  // remaining bits -> qubit (ascending)
+    int gate_begin, gate_count;
+};
+
+template <typename R> __device__ __forceinline__ Mat2<R> load_mat(const double *u) {
+    Mat2<R> m;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m.m[k] = (R)u[k];
+    return m;
+}
+
+template <typename R, int TBMAX>
+__global__ __launch_bounds__(kBlock) void k_tile_pass(cx<R> *__restrict__ psi, DPass P, const DGate *__restrict__ gates) {
+    __shared__ cx<R> sh[1 << TBMAX];
+    const int tb = P.tb;
+    const u64 TS = 1ull << tb;
+    u64 base = 0;
+    for (int b = 0; b < P.nrest; ++b) base |= (((u64)blockIdx.x >> b) & 1ull) << P.rest[b];
+
+    for (u64 m = threadIdx.x; m < TS; m += kBlock) {
+        u64 off = base;
+        for (int b = 0; b < tb; ++b) off |= ((m >> b) & 1ull) << P.T[b];
+        sh[m] = psi[off];
+    }
+    __syncthreads();
+
+    for (int gi = 0; gi < P.gate_count; ++gi) {
+        const DGate &g = gates[P.gate_begin + gi];
+        if (g.kind == QS_G_1Q || (g.kind == QS_G_C1Q && g.p0 < 0)) {
+            const int p = g.kind == QS_G_1Q ? g.p0 : g.p1;
+            const bool on = g.kind == QS_G_1Q || ((base >> g.q0) & 1ull);
+            if (on) {
+                const Mat2<R> u = load_mat<R>(g.u);
+                for (u64 k = threadIdx.x; k < TS / 2; k += kBlock) {
+                    const u64 m0 = insert0(k, p), m1 = m0 | (1ull << p);
+                    cx<R> a = sh[m0], b = sh[m1];
+                    apply2<R>(u, a, b);
+                    sh[m0] = a;
+                    sh[m1] = b;
+                }
+            }
+        } else if (g.kind == QS_G_C1Q) {
+            const Mat2<R> u = load_mat<R>(g.u);
+            const int lo = g.p0 < g.p1 ? g.p0 : g.p1, hi = g.p0 < g.p1 ? g.p1 : g.p0;
+            for (u64 k = threadIdx.x; k < TS / 4; k += kBlock) {
+                const u64 m0 = insert0(insert0(k, lo), hi) | (1ull << g.p0), m1 = m0 | (1ull << g.p1);
+                cx<R> a = sh[m0], b = sh[m1];
+                apply2<R>(u, a, b);
+                sh[m0] = a;
+                sh[m1] = b;
+            }
+        } else if (g.kind == QS_G_DIAG2) {
+            for (u64 m = threadIdx.x; m < TS; m += kBlock) {
+                const int b0 = g.p0 >= 0 ? (int)((m >> g.p0) & 1) : (int)((base >> g.q0) & 1);
+                const int b1 = g.p1 >= 0 ? (int)((m >> g.p1) & 1) : (int)((base >> g.q1) & 1);
+                const int e = 2 * b1 + b0;
+                cx<R> f;
+                f.x = (R)g.u[2 * e];
+                f.y = (R)g.u[2 * e + 1];
+                sh[m] = cmul<R>(sh[m], f);
+            }
+        } else if (g.kind == QS_G_SWAP) {
+            const int lo = g.p0 < g.p1 ? g.p0 : g.p1, hi = g.p0 < g.p1 ? g.p1 : g.p0;
+            for (u64 k = threadIdx.x; k < TS / 4; k += kBlock) {
+                const u64 b = insert0(insert0(k, lo), hi);
+                const u64 i = b | (1ull << g.p0), j = b | (1ull << g.p1);
+                const cx<R> x = sh[i], y = sh[j];
+                sh[i] = y;
+                sh[j] = x;
+            }
+        }
+        __syncthreads();
+    }
+
+    for (u64 m = threadIdx.x; m < TS; m += kBlock) {
+        u64 off = base;
+        for (int b = 0; b < tb; ++b) off |= ((m >> b) & 1ull) << P.T[b];
+        psi[off] = sh[m];
+    }
+}
+
+// ------------------------------------------------------------------ planning
+
+struct Plan {
+    std::vector<DPass> passes;
+    DGate *dev_gates = nullptr;
+};
+
+struct PlanCache {
+    std::unordered_map<std::string, Plan> plans;
+};
+
+static int tile_bits_max(int dtype) { return dtype == QS_C128 ? 12 : 13; }
+
+// Split the list into passes (see the file comment) and encode each gate's
+// qubits as tile-bit positions of its pass.
+static void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg) {
+    const int tbmax = std::min(tile_bits_max(dtype), n);
+    const int r = std::min(dtype == QS_C128 ? 3 : 4, tbmax);  // contiguous low qubits: 128-byte rows
+    int k = 0;
+    while (k < count) {
+        u64 T = (1ull << r) - 1;
+        int begin = k;
+        for (; k < count; ++k) {
+            u64 need = 0;
+            const qs_gate &x = g[k];
+            if (x.kind == QS_G_1Q) need = 1ull << x.q0;
+            else if (x.kind == QS_G_C1Q) need = 1ull << x.q1;
+            else if (x.kind == QS_G_SWAP) need = (1ull << x.q0) | (1ull << x.q1);
+            if (__builtin_popcountll(T | need) > tbmax) break;
+            T |= need;
+        }
+        // Fill the tile up to tbmax with the lowest unused qubits.
+        for (int q = 0; q < n && __builtin_popcountll(T) < tbmax; ++q) T |= 1ull << q;
+        DPass P{};
+        P.tb = 0;
+        int pos[64];
+        for (int q = 0; q < n; ++q) {
+            if ((T >> q) & 1) {
+                pos[q] = P.tb;
+                P.T[P.tb++] = (uint8_t)q;
+            } else {
+                pos[q] = -1;
+                P.rest[P.nrest++] = (uint8_t)q;
+            }
+        }
+        P.gate_begin = (int)dg.size();
+        P.gate_count = k - begin;
+        for (int j = begin; j < k; ++j) {
+            DGate d{};
+            d.kind = g[j].kind;
+            d.q0 = (int8_t)g[j].q0;
+            d.q1 = (int8_t)(g[j].kind == QS_G_1Q ? 0 : g[j].q1);
+            d.p0 = (int8_t)pos[g[j].q0];
+            d.p1 = (int8_t)(g[j].kind == QS_G_1Q ? -1 : pos[g[j].q1]);
+            memcpy(d.u, g[j].u, sizeof(d.u));
+            dg.push_back(d);
+        }
+        passes.push_back(P);
+    }
+}
+
+static std::mutex g_plan_mu;
+
+int run_block(qs_state *s, const qs_gate *gates, int count) {
+    if (count == 0) return QS_OK;
+    std::string key((const char *)gates, (size_t)count * sizeof(qs_gate));
+    key.append((const char *)&s->n, sizeof(int));
+    key.append((const char *)&s->dtype, sizeof(int));
+    Plan *plan = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        if (!s->plan_cache) s->plan_cache = new PlanCache();
+        auto *cache = (PlanCache *)s->plan_cache;
+        auto it = cache->plans.find(key);
+        if (it == cache->plans.end()) {
+            Plan p;
+            std::vector<DGate> dg;
+            make_plan(s->n, s->dtype, gates, count, p.passes, dg);
+            QS_HIP(hipMalloc(&p.dev_gates, dg.size() * sizeof(DGate)));
+            QS_HIP(hipMemcpy(p.dev_gates, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice));
+            it = cache->plans.emplace(std::move(key), std::move(p)).first;
+        }
+        plan = &it->second;
+    }
+    for (const DPass &P : plan->passes) {
+        const unsigned grid = 1u << P.nrest;
+        if (s->dtype == QS_C128)
+            hipLaunchKernelGGL((k_tile_pass<double, 12>), dim3(grid), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, P, plan->dev_gates);
+        else
+            hipLaunchKernelGGL((k_tile_pass<float, 13>), dim3(grid), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, P, plan->dev_gates);
+        QS_LAUNCH_CHECK("tile_pass");
+    }
+    return QS_OK;
+}
+
+void free_plan_cache(qs_state *s) {
+    if (!s->plan_cache) return;
+    auto *cache = (PlanCache *)s->plan_cache;
+    for (auto &kv : cache->plans) (void)hipFree(kv.second.dev_gates);
+    delete cache;
+    s->plan_cache = nullptr;
+}
+
+}  // namespace qs

@@ -246,9 +246,16 @@ typedef struct qs_traj_out {
     int log_cap;
 } qs_traj_out;
 
-int qs_traj_workspace_bytes(int n, int dtype, int n_traj, size_t *bytes);
+/* Device workspace for qs_traj_run: n_traj + 1 states (the extra one is the
+ * noiseless reference for the fidelity) plus per-gate Pauli frames. */
+int qs_traj_workspace_bytes(int n, int dtype, int count, int n_traj, size_t *bytes);
 
-/* gates: host list (1Q, C1Q, DIAG2, SWAP), 1 <= count <= 4096; 1 <= n <= 20. */
+/* gates: host list (1Q, C1Q, DIAG2, SWAP), 1 <= count <= 4096; 1 <= n <= 20;
+ * 0 <= p_depol <= 1.  Inserted Paulis are tracked as a per-trajectory Pauli
+ * frame (conjugating later gates and undone in the read-outs), so they add no
+ * pass over the state.  The gate list is uploaded and the call waits for that
+ * copy before returning (not capturable).  Outputs are trajectory-resolved;
+ * means and convergence curves are reductions of them. */
 int qs_traj_run(int n, int dtype, const qs_gate *gates, int count, uint64_t basis_index, int n_traj,
                 double p_depol, uint64_t seed, const qs_traj_out *out, void *ws, size_t ws_bytes, void *stream);
 

@@ -106,13 +106,23 @@ int launch_scale(qs_state *s, const double *norm_dev) {
 
 // ------------------------------------------------------------------ one-qubit gate (eq. 3)
 
-template <typename R, int PPT, bool NT>
+// Block-index remap: hardware hands consecutive workgroups to the 8 XCDs in
+// turn; with XCD = true each XCD instead walks one contiguous eighth of the
+// pairs.
+__device__ __forceinline__ u64 logical_block(bool xcd) {
+    const u64 b = blockIdx.x, nb = gridDim.x;
+    if (!xcd || (nb & 7)) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <typename R, int PPT, bool NT, bool XCD>
 __global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u64 npairs, int q, Mat2<R> u) {
     const u64 s = 1ull << q;
-    const u64 first = (u64)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+    const u64 lb = logical_block(XCD);
+    const u64 first = lb * (kBlock * PPT) + threadIdx.x;
     cx<R> a[PPT], b[PPT];
     u64 i0[PPT];
-    if ((u64)(blockIdx.x + 1) * (kBlock * PPT) <= npairs) {
+    if ((lb + 1) * (kBlock * PPT) <= npairs) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             i0[j] = insert0(first + (u64)j * kBlock, q);
@@ -138,28 +148,79 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u6
     }
 }
 
-// Variant selection (pairs per thread, non-temporal hints).  The default was
-// chosen by measuring 32-qubit sweeps; QSIM_1Q_VARIANT overrides it for tuning.
+// Low targets (q < 6): the partner of amplitude i sits in the same wavefront
+// when lanes hold consecutive amplitudes, so every load and store instruction
+// covers one contiguous 1 KiB (c128) run and the partner arrives by a lane
+// shuffle (lane xor 2^q).  Lane with bit q clear computes U00 a + U01 b, the
+// other U10 a + U11 b.  Requires 2^n to be a multiple of 256 * APT.
+template <typename R, int APT, bool NT>
+__global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ psi, int q, Mat2<R> u) {
+    const u64 first = (u64)blockIdx.x * (kBlock * APT) + threadIdx.x;
+    const int lane = threadIdx.x & 63, mask = 1 << q;
+    const bool upper = lane & mask;
+    // own coefficient (diagonal) and partner coefficient (off-diagonal) of this lane's row
+    const R own_re = upper ? u.m[6] : u.m[0], own_im = upper ? u.m[7] : u.m[1];
+    const R oth_re = upper ? u.m[4] : u.m[2], oth_im = upper ? u.m[5] : u.m[3];
+    cx<R> a[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) a[j] = ld<NT>(psi + first + (u64)j * kBlock);
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        cx<R> b;
+        b.x = __shfl_xor(a[j].x, mask, 64);
+        b.y = __shfl_xor(a[j].y, mask, 64);
+        cx<R> r;
+        r.x = own_re * a[j].x - own_im * a[j].y + oth_re * b.x - oth_im * b.y;
+        r.y = own_re * a[j].y + own_im * a[j].x + oth_re * b.y + oth_im * b.x;
+        st<NT>(psi + first + (u64)j * kBlock, r);
+    }
+}
+
+// Kernel choice for the one-qubit gate: (low-q method, high-q method).  The
+// default was picked by timing every target of a 32-qubit complex128 sweep;
+// QSIM_1Q_VARIANT selects the alternatives for tuning runs.
 static int variant_1q() {
     static int v = [] {
         const char *e = getenv("QSIM_1Q_VARIANT");
-        return e ? atoi(e) : 2;
+        return e ? atoi(e) : 0;
     }();
     return v;
 }
 
 template <typename R> static int launch_1q_t(qs_state *s, int q, const double *u) {
-    const u64 npairs = 1ull << (s->n - 1);
+    const u64 N = 1ull << s->n, npairs = N >> 1;
     const Mat2<R> m = to_mat<R>(u);
     cx<R> *psi = (cx<R> *)s->buf;
-    switch (variant_1q()) {
-    case 1: hipLaunchKernelGGL((k_apply_1q<R, 1, false>), dim3(grid_for(npairs, kBlock * 1)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
-    case 3: hipLaunchKernelGGL((k_apply_1q<R, 4, false>), dim3(grid_for(npairs, kBlock * 4)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
-    case 4: hipLaunchKernelGGL((k_apply_1q<R, 2, true>), dim3(grid_for(npairs, kBlock * 2)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
-    case 5: hipLaunchKernelGGL((k_apply_1q<R, 4, true>), dim3(grid_for(npairs, kBlock * 4)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
-    case 6: hipLaunchKernelGGL((k_apply_1q<R, 1, true>), dim3(grid_for(npairs, kBlock * 1)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
-    default: hipLaunchKernelGGL((k_apply_1q<R, 2, false>), dim3(grid_for(npairs, kBlock * 2)), dim3(kBlock), 0, s->stream, psi, npairs, q, m); break;
+    const int v = variant_1q();
+    hipStream_t st = s->stream;
+#define PAIR(PPT, NT, XCD) \
+    hipLaunchKernelGGL((k_apply_1q<R, PPT, NT, XCD>), dim3(grid_for(npairs, kBlock * PPT)), dim3(kBlock), 0, st, psi, npairs, q, m)
+#define LANE(APT, NT) hipLaunchKernelGGL((k_apply_1q_lane<R, APT, NT>), dim3((unsigned)(N / (kBlock * APT))), dim3(kBlock), 0, st, psi, q, m)
+    const bool lane_ok = q < 6 && N >= (u64)kBlock * 4;
+    switch (v) {
+    case 1: PAIR(1, false, false); break;
+    case 2: PAIR(2, false, false); break;
+    case 3: PAIR(4, false, false); break;
+    case 4: PAIR(2, true, false); break;
+    case 5: PAIR(4, true, false); break;
+    case 6: PAIR(1, true, false); break;
+    case 7: PAIR(2, true, true); break;
+    case 8: PAIR(1, true, true); break;
+    case 9:
+        if (lane_ok) LANE(2, true); else PAIR(2, true, false);
+        break;
+    case 10:
+        if (lane_ok) LANE(4, true); else PAIR(2, true, true);
+        break;
+    case 11:
+        if (lane_ok) LANE(2, false); else PAIR(2, true, true);
+        break;
+    default:
+        if (lane_ok) LANE(2, true); else PAIR(2, true, false);
+        break;
     }
+#undef PAIR
+#undef LANE
     QS_LAUNCH_CHECK("apply_1q");
     return QS_OK;
 }

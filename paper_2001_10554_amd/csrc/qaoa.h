@@ -1,0 +1,70 @@
+// QAOA pass plans and batched launches, shared by the single-graph entry
+// point (qaoa.hip) and the pool (pool.hip).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace qs {
+
+constexpr int kQThreads = 256;   // 8 thread-index bits per tile
+constexpr int kQMaxEdges = 128;
+
+enum { QF_FIRST = 1, QF_PHASE_END = 2, QF_LAST = 4 };
+
+// Edge classes by where the endpoints sit for a pass's thread map: tile bits
+// 0..7 are thread-index bits ("t"), higher tile bits register-index bits
+// ("j"), other qubits fixed per tile ("r").
+enum { EC_TT = 0, EC_TR, EC_TJ, EC_JJ, EC_JR, EC_RR, EC_N };
+
+struct QEdge {
+    uint8_t a, b, wi, pad;
+};
+
+struct QPass {
+    int tb, nrest, layer, flags, pidx;
+    uint32_t rx_mask;  // tile bits that receive RX
+    uint8_t T[16];
+    uint8_t rest[40];
+    uint16_t cnt[EC_N];
+    QEdge e[kQMaxEdges];
+};
+
+struct QWeights {
+    double w[kQMaxEdges];
+};
+
+struct QGeom {
+    int n, p, P, tb, G, glog, num_edges, weighted;
+};
+
+// Where circuit c of a launch keeps its data: ws + c * circ_bytes + offset
+// (offsets < 0 mean "absent"); its angles are theta + c * 2p.
+struct QBatch {
+    char *ws;
+    u64 circ_bytes;
+    long long in_off, out_off, lam_off, part_off, epart_off;
+    const double *theta;
+};
+
+struct QPlan {
+    int TB;
+    QGeom geo;
+    std::vector<QPass> passes;  // forward order: pass (l, g) at index l*P + g
+    QWeights W;
+};
+
+// Per-circuit workspace layout (byte offsets; -1 = unused).
+struct QLayout {
+    long long ckpt, lam, part, epart;
+    size_t bytes;
+};
+
+int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double *w, int TB, QPlan &plan);
+QLayout qaoa_layout(const QGeom &g, int with_grad);
+int launch_qaoa_batch(const QPlan &plan, const double *theta, int nb, double *E_out, double *grad_out, char *ws, size_t circ_bytes, hipStream_t st);
+int check_edges(int n, int ne, const int32_t *edges);
+int qaoa_default_tb(int n);
+
+}  // namespace qs

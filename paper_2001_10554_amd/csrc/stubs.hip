@@ -3,15 +3,7 @@
 
 #define QS_API extern "C" __attribute__((visibility("default")))
 
-QS_API int qs_qaoa_workspace_bytes(const qs_qaoa_desc *, int, size_t *) { return qs::fail(QS_ERR_UNSUPPORTED, "qaoa not built"); }
-QS_API int qs_qaoa_run(const qs_qaoa_desc *, const double *, int, double *, double *, void *, size_t, void *) {
-    return qs::fail(QS_ERR_UNSUPPORTED, "qaoa not built");
-}
 QS_API int qs_pool_workspace_bytes(const qs_pool_desc *, size_t *) { return qs::fail(QS_ERR_UNSUPPORTED, "pool not built"); }
 QS_API int qs_pool_run(const qs_pool_desc *, const double *, double *, double *, void *, size_t, void *) {
     return qs::fail(QS_ERR_UNSUPPORTED, "pool not built");
-}
-QS_API int qs_traj_workspace_bytes(int, int, int, size_t *) { return qs::fail(QS_ERR_UNSUPPORTED, "traj not built"); }
-QS_API int qs_traj_run(int, int, const qs_gate *, int, uint64_t, int, double, uint64_t, const qs_traj_out *, void *, size_t, void *) {
-    return qs::fail(QS_ERR_UNSUPPORTED, "traj not built");
 }

@@ -19,31 +19,9 @@
 #include <vector>
 
 #include "launch.h"
+#include "tile.h"
 
 namespace qs {
-
-struct DGate {
-    int32_t kind;
-    int8_t p0, p1;  // tile-bit positions of q0 / q1, -1 when outside the tile
-    int8_t q0, q1;
-    int32_t pad;
-    double u[8];
-};
-
-struct DPass {
-    int tb;
-    int nrest;
-    uint8_t T[16];     // tile bit -> qubit (ascending)
-    uint8_t rest[40];  // remaining bits -> qubit (ascending)
-    int gate_begin, gate_count;
-};
-
-template <typename R> __device__ __forceinline__ Mat2<R> load_mat(const double *u) {
-    Mat2<R> m;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) m.m[k] = (R)u[k];
-    return m;
-}
 
 template <typename R, int TBMAX>
 __global__ __launch_bounds__(kBlock) void k_tile_pass(cx<R> *__restrict__ psi, DPass P, const DGate *__restrict__ gates) {
@@ -62,50 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_pass(cx<R> *__restrict__ psi, D
 
     for (int gi = 0; gi < P.gate_count; ++gi) {
         const DGate &g = gates[P.gate_begin + gi];
-        if (g.kind == QS_G_1Q || (g.kind == QS_G_C1Q && g.p0 < 0)) {
-            const int p = g.kind == QS_G_1Q ? g.p0 : g.p1;
-            const bool on = g.kind == QS_G_1Q || ((base >> g.q0) & 1ull);
-            if (on) {
-                const Mat2<R> u = load_mat<R>(g.u);
-                for (u64 k = threadIdx.x; k < TS / 2; k += kBlock) {
-                    const u64 m0 = insert0(k, p), m1 = m0 | (1ull << p);
-                    cx<R> a = sh[m0], b = sh[m1];
-                    apply2<R>(u, a, b);
-                    sh[m0] = a;
-                    sh[m1] = b;
-                }
-            }
-        } else if (g.kind == QS_G_C1Q) {
-            const Mat2<R> u = load_mat<R>(g.u);
-            const int lo = g.p0 < g.p1 ? g.p0 : g.p1, hi = g.p0 < g.p1 ? g.p1 : g.p0;
-            for (u64 k = threadIdx.x; k < TS / 4; k += kBlock) {
-                const u64 m0 = insert0(insert0(k, lo), hi) | (1ull << g.p0), m1 = m0 | (1ull << g.p1);
-                cx<R> a = sh[m0], b = sh[m1];
-                apply2<R>(u, a, b);
-                sh[m0] = a;
-                sh[m1] = b;
-            }
-        } else if (g.kind == QS_G_DIAG2) {
-            for (u64 m = threadIdx.x; m < TS; m += kBlock) {
-                const int b0 = g.p0 >= 0 ? (int)((m >> g.p0) & 1) : (int)((base >> g.q0) & 1);
-                const int b1 = g.p1 >= 0 ? (int)((m >> g.p1) & 1) : (int)((base >> g.q1) & 1);
-                const int e = 2 * b1 + b0;
-                cx<R> f;
-                f.x = (R)g.u[2 * e];
-                f.y = (R)g.u[2 * e + 1];
-                sh[m] = cmul<R>(sh[m], f);
-            }
-        } else if (g.kind == QS_G_SWAP) {
-            const int lo = g.p0 < g.p1 ? g.p0 : g.p1, hi = g.p0 < g.p1 ? g.p1 : g.p0;
-            for (u64 k = threadIdx.x; k < TS / 4; k += kBlock) {
-                const u64 b = insert0(insert0(k, lo), hi);
-                const u64 i = b | (1ull << g.p0), j = b | (1ull << g.p1);
-                const cx<R> x = sh[i], y = sh[j];
-                sh[i] = y;
-                sh[j] = x;
-            }
-        }
-        __syncthreads();
+        lds_apply_gate<R, kBlock>(sh, TS, base, g.kind, g.p0, g.p1, g.q0, g.q1, 1, g.u);
     }
 
     for (u64 m = threadIdx.x; m < TS; m += kBlock) {
@@ -126,11 +61,9 @@ struct PlanCache {
     std::unordered_map<std::string, Plan> plans;
 };
 
-static int tile_bits_max(int dtype) { return dtype == QS_C128 ? 12 : 13; }
-
 // Split the list into passes (see the file comment) and encode each gate's
 // qubits as tile-bit positions of its pass.
-static void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg) {
+void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg) {
     const int tbmax = std::min(tile_bits_max(dtype), n);
     const int r = std::min(dtype == QS_C128 ? 3 : 4, tbmax);  // contiguous low qubits: 128-byte rows
     int k = 0;

@@ -1,0 +1,355 @@
+// Noise trajectories: stochastic Pauli insertion (depolarizing channel)
+// averaged over an ensemble of pure-state runs.
+//
+// Pauli frames.  An inserted Pauli is not applied to the amplitudes.  Each
+// trajectory keeps a frame F = X^a Z^b (n-bit masks a, b; global phases are
+// irrelevant to every read-out) with psi_true = F psi_stored.  A gate G then
+// acts on the stored state as F^dagger G F:
+//   1Q U on q:        U' = P^dagger U P with P = X^{a_q} Z^{b_q};
+//   C1Q (c, t, U):    control value 1 xor a_c, target matrix conjugated as above;
+//   DIAG2 (q0, q1):   entries permuted by the X part on q0 / q1;
+//   SWAP (x, y):      applied as is, and the frame's bits x and y are exchanged.
+// An insertion of X, Y or Z on q flips a_q, a_q and b_q, or b_q.  So every
+// trajectory runs the same fused pass schedule as the noiseless circuit and an
+// insertion costs no extra pass.  Read-outs undo the frame:
+//   <Z_q> = (-1)^{a_q} <Z_q>_stored, <X_q> = (-1)^{b_q} <X_q>_stored,
+//   p(k) = |psi_stored(k xor a)|^2,
+//   <ideal|psi> = sum_j conj(ideal(j xor a)) (-1)^{popc(b & j)} psi_stored(j).
+//
+// Draws.  Draw `slot` of trajectory t is Philox4x32-10(key = seed, counter =
+// (t, slot, 3, 0)); after each gate one draw per touched qubit (q0, then q1);
+// insert iff x0 < floor(p 2^32); Pauli = 1 + floor(3 x1 / 2^32).  The frames
+// kernel replays these integer decisions once per trajectory and stores the
+// frame seen by every gate, so the decisions are bit-exact by construction.
+#include <vector>
+
+#include "launch.h"
+#include "tile.h"
+#include "vec.h"
+
+#define QS_API extern "C" __attribute__((visibility("default")))
+
+namespace qs {
+
+constexpr int kTrajMaxQubits = 20;
+constexpr int kTrajMaxGates = 4096;
+
+struct TGate {  // gate list on the device (kind, q0, q1, u)
+    int32_t kind, q0, q1, pad;
+    double u[8];
+};
+
+// frames[t * count + g] = (a | b << 32) before gate g; final[t] after all gates.
+__global__ void k_traj_frames(const TGate *__restrict__ gates, int count, int n_traj, u32 thr, u32 k0, u32 k1, uint64_t *__restrict__ frames,
+                              uint64_t *__restrict__ final_frame, int32_t *__restrict__ counts, uint32_t *__restrict__ log, int log_cap) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > n_traj) return;
+    u32 a = 0, b = 0, slot = 0;
+    int nins = 0;
+    const bool ideal = t == n_traj;  // the extra noiseless trajectory
+    for (int g = 0; g < count; ++g) {
+        frames[(u64)t * count + g] = (u64)a | ((u64)b << 32);
+        const TGate G = gates[g];
+        if (G.kind == QS_G_SWAP) {
+            const u32 x = 1u << G.q0, y = 1u << G.q1;
+            if (((a & x) != 0) != ((a & y) != 0)) a ^= x | y;
+            if (((b & x) != 0) != ((b & y) != 0)) b ^= x | y;
+        }
+        const int nt = G.kind == QS_G_1Q ? 1 : 2;
+        for (int k = 0; k < nt; ++k, ++slot) {
+            if (ideal) continue;
+            const Philox4 r = philox4x32_10((u32)t, slot, kTagTraj, 0u, k0, k1);
+            if (r.v[0] < thr) {
+                const int pauli = 1 + (int)(((u64)r.v[1] * 3u) >> 32);
+                const u32 m = 1u << (k == 0 ? G.q0 : G.q1);
+                if (pauli == 1 || pauli == 2) a ^= m;
+                if (pauli == 2 || pauli == 3) b ^= m;
+                if (log && nins < log_cap) log[(u64)t * log_cap + nins] = (slot << 2) | (u32)pauli;
+                ++nins;
+            }
+        }
+    }
+    final_frame[t] = (u64)a | ((u64)b << 32);
+    if (counts && !ideal) counts[t] = nins;
+}
+
+// U' = P^dagger U P for P = X^xa Z^zb (row-major interleaved u[8]).
+__device__ __forceinline__ void conj_pauli(double *u, int xa, int zb) {
+    if (xa) {  // X U X: swap rows and columns
+        double t[8];
+        for (int k = 0; k < 8; ++k) t[k] = u[k];
+        u[0] = t[6]; u[1] = t[7]; u[2] = t[4]; u[3] = t[5];
+        u[4] = t[2]; u[5] = t[3]; u[6] = t[0]; u[7] = t[1];
+    }
+    if (zb) {  // Z U Z: negate the off-diagonal
+        u[2] = -u[2]; u[3] = -u[3]; u[4] = -u[4]; u[5] = -u[5];
+    }
+}
+
+template <typename R, int TBMAX>
+__global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states, u64 N, int tiles_log2, DPass P, const DGate *__restrict__ gates,
+                                                      const uint64_t *__restrict__ frames, int count, int first_pass, u64 basis) {
+    __shared__ cx<R> sh[1 << TBMAX];
+    const u64 tile = blockIdx.x & ((1ull << tiles_log2) - 1);
+    const u64 t = blockIdx.x >> tiles_log2;
+    cx<R> *psi = states + t * N;
+    const u64 TS = 1ull << P.tb;
+    const u64 base = pass_base(P, tile);
+    for (u64 m = threadIdx.x; m < TS; m += kBlock) {
+        const u64 idx = base | pass_off(P, m);
+        cx<R> v;
+        if (first_pass) {
+            v.x = idx == basis ? (R)1 : (R)0;
+            v.y = (R)0;
+        } else {
+            v = ld<true>(psi + idx);
+        }
+        sh[m] = v;
+    }
+    __syncthreads();
+    for (int gi = 0; gi < P.gate_count; ++gi) {
+        const int gidx = P.gate_begin + gi;
+        const DGate &g = gates[gidx];
+        const u64 f = frames[t * count + gidx];
+        const u32 a = (u32)f, b = (u32)(f >> 32);
+        double u[8];
+        for (int k = 0; k < 8; ++k) u[k] = g.u[k];
+        int cval = 1;
+        if (g.kind == QS_G_1Q) {
+            conj_pauli(u, (a >> g.q0) & 1, (b >> g.q0) & 1);
+        } else if (g.kind == QS_G_C1Q) {
+            cval = 1 ^ (int)((a >> g.q0) & 1);
+            conj_pauli(u, (a >> g.q1) & 1, (b >> g.q1) & 1);
+        } else if (g.kind == QS_G_DIAG2) {
+            const int x0 = (a >> g.q0) & 1, x1 = (a >> g.q1) & 1;
+            for (int e = 0; e < 4; ++e) {
+                const int src = ((((e >> 1) ^ x1) << 1) | ((e & 1) ^ x0));
+                u[2 * e] = g.u[2 * src];
+                u[2 * e + 1] = g.u[2 * src + 1];
+            }
+        }
+        lds_apply_gate<R, kBlock>(sh, TS, base, g.kind, g.p0, g.p1, g.q0, g.q1, cval, u);
+    }
+    for (u64 m = threadIdx.x; m < TS; m += kBlock) st<true>(psi + (base | pass_off(P, m)), sh[m]);
+}
+
+__device__ __forceinline__ double tblock_sum(double v, double *red) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+// Per-trajectory partial sums over one chunk of amplitudes:
+// [0, n): sum (-1)^{k_q} |psi_k|^2; [n, 2n): <X_q>_stored; 2n, 2n+1: <ideal|F psi> (re, im).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_traj_obs(const cx<R> *__restrict__ states, int n, int chunk_log2, int chunks_log2,
+                                                     const uint64_t *__restrict__ final_frame, int ideal_index, double *__restrict__ partial) {
+    __shared__ double red[kBlock / 64];
+    const u64 N = 1ull << n;
+    const u64 c = blockIdx.x & ((1ull << chunks_log2) - 1);
+    const u64 t = blockIdx.x >> chunks_log2;
+    const cx<R> *psi = states + t * N;
+    const cx<R> *ideal = states + (u64)ideal_index * N;
+    const u64 f = final_frame[t];
+    const u32 fa = (u32)f, fb = (u32)(f >> 32);
+    double z[kTrajMaxQubits], x[kTrajMaxQubits], fre = 0.0, fim = 0.0;
+#pragma unroll
+    for (int q = 0; q < kTrajMaxQubits; ++q) z[q] = x[q] = 0.0;
+    const u64 lo = c << chunk_log2, hi = lo + (1ull << chunk_log2);
+    for (u64 i = lo + threadIdx.x; i < hi; i += kBlock) {
+        const cx<R> v = psi[i];
+        const double p = (double)v.x * v.x + (double)v.y * v.y;
+#pragma unroll
+        for (int q = 0; q < kTrajMaxQubits; ++q) {
+            if (q < n) {
+                z[q] += ((i >> q) & 1) ? -p : p;
+                if (!((i >> q) & 1)) {
+                    const cx<R> w = psi[i | (1ull << q)];
+                    x[q] += 2.0 * ((double)v.x * w.x + (double)v.y * w.y);
+                }
+            }
+        }
+        const cx<R> id = ideal[i ^ fa];
+        const double sgn = (__popcll(i & fb) & 1) ? -1.0 : 1.0;
+        fre += sgn * ((double)id.x * v.x + (double)id.y * v.y);
+        fim += sgn * ((double)id.x * v.y - (double)id.y * v.x);
+    }
+    const int nv = 2 * n + 2;
+    double *out = partial + (u64)blockIdx.x * nv;
+#pragma unroll
+    for (int q = 0; q < kTrajMaxQubits; ++q) {
+        if (q >= n) break;
+        const double tz = tblock_sum(z[q], red);
+        if (threadIdx.x == 0) out[q] = tz;
+        const double tx = tblock_sum(x[q], red);
+        if (threadIdx.x == 0) out[n + q] = tx;
+    }
+    const double tre = tblock_sum(fre, red);
+    const double tim = tblock_sum(fim, red);
+    if (threadIdx.x == 0) {
+        out[2 * n] = tre;
+        out[2 * n + 1] = tim;
+    }
+}
+
+// One thread per (trajectory, value): sum the chunk partials in order, undo the frame.
+__global__ void k_traj_final(const double *__restrict__ partial, int n, int chunks, int n_traj, const uint64_t *__restrict__ final_frame,
+                             double *__restrict__ z, double *__restrict__ x, double *__restrict__ fid) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nv = 2 * n + 2;
+    const int per = n + n + 1;  // z values, x values, fidelity
+    if (id >= n_traj * per) return;
+    const int t = id / per, v = id % per;
+    const u64 f = final_frame[t];
+    const u32 a = (u32)f, b = (u32)(f >> 32);
+    const double *p = partial + (u64)t * chunks * nv;
+    if (v < 2 * n) {
+        double s = 0.0;
+        for (int c = 0; c < chunks; ++c) s += p[(u64)c * nv + v];
+        if (v < n) {
+            if (z) z[(u64)t * n + v] = ((a >> v) & 1) ? -s : s;
+        } else {
+            const int q = v - n;
+            if (x) x[(u64)t * n + q] = ((b >> q) & 1) ? -s : s;
+        }
+    } else {
+        double re = 0.0, im = 0.0;
+        for (int c = 0; c < chunks; ++c) {
+            re += p[(u64)c * nv + 2 * n];
+            im += p[(u64)c * nv + 2 * n + 1];
+        }
+        if (fid) fid[t] = re * re + im * im;
+    }
+}
+
+// p_mean(k) = (1/T) sum_t |psi_t(k xor a_t)|^2, trajectories summed in order.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restrict__ states, u64 N, int n_traj, const uint64_t *__restrict__ final_frame,
+                                                           double *__restrict__ out) {
+    const u64 k = (u64)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= N) return;
+    double s = 0.0;
+    for (int t = 0; t < n_traj; ++t) {
+        const u32 a = (u32)final_frame[t];
+        const cx<R> v = states[(u64)t * N + (k ^ a)];
+        s += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    out[k] = s / (double)n_traj;
+}
+
+// ------------------------------------------------------------------ host side
+
+struct TrajLayout {
+    size_t states, frames, final_frame, partial, gates, dgates, total;
+    int chunk_log2, chunks_log2;
+};
+
+static TrajLayout traj_layout(int n, int dtype, int count, int n_traj) {
+    TrajLayout L{};
+    const u64 N = 1ull << n;
+    auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    L.chunk_log2 = n < 12 ? n : 12;
+    L.chunks_log2 = n - L.chunk_log2;
+    size_t off = 0;
+    L.states = off;
+    off = align(off + (size_t)(n_traj + 1) * N * amp_bytes(dtype));
+    L.frames = off;
+    off = align(off + (size_t)(n_traj + 1) * count * sizeof(uint64_t));
+    L.final_frame = off;
+    off = align(off + (size_t)(n_traj + 1) * sizeof(uint64_t));
+    L.partial = off;
+    off = align(off + (size_t)(n_traj + 1) * ((size_t)1 << L.chunks_log2) * (2 * n + 2) * sizeof(double));
+    L.gates = off;
+    off = align(off + (size_t)count * sizeof(TGate));
+    L.dgates = off;
+    off = align(off + (size_t)count * sizeof(DGate));
+    L.total = off;
+    return L;
+}
+
+template <typename R, int TBMAX>
+static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 basis, int n_traj, double p, u64 seed, const qs_traj_out *out,
+                      char *ws, hipStream_t st) {
+    const TrajLayout L = traj_layout(n, dtype, count, n_traj);
+    const u64 N = 1ull << n;
+    std::vector<DPass> passes;
+    std::vector<DGate> dg;
+    make_plan(n, dtype, gates, count, passes, dg);
+    // The planner keeps the list order, so dg[i] is gate i with tile positions per pass.
+    QS_HIP(hipMemcpyAsync(ws + L.gates, gates, (size_t)count * sizeof(TGate), hipMemcpyHostToDevice, st));
+    QS_HIP(hipMemcpyAsync(ws + L.dgates, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice, st));
+    QS_HIP(hipStreamSynchronize(st));  // host arrays are released when this call returns
+    u32 thr = 0;
+    if (p >= 1.0) thr = 0xFFFFFFFFu;
+    else if (p > 0.0) thr = (u32)floor(p * 4294967296.0);
+    uint64_t *frames = (uint64_t *)(ws + L.frames), *final_frame = (uint64_t *)(ws + L.final_frame);
+    hipLaunchKernelGGL(k_traj_frames, dim3((n_traj + 1 + 63) / 64), dim3(64), 0, st, (const TGate *)(ws + L.gates), count, n_traj, thr,
+                       (u32)seed, (u32)(seed >> 32), frames, final_frame, out->counts, out->log, out->log ? out->log_cap : 0);
+    QS_LAUNCH_CHECK("traj_frames");
+    cx<R> *states = (cx<R> *)(ws + L.states);
+    const int T1 = n_traj + 1;
+    bool first = true;
+    for (const DPass &P : passes) {
+        const int tiles_log2 = P.nrest;
+        const u64 blocks = (u64)T1 << tiles_log2;
+        hipLaunchKernelGGL((k_traj_pass<R, TBMAX>), dim3((unsigned)blocks), dim3(kBlock), 0, st, states, N, tiles_log2, P, (const DGate *)(ws + L.dgates),
+                           (const uint64_t *)frames, count, first ? 1 : 0, basis);
+        QS_LAUNCH_CHECK("traj_pass");
+        first = false;
+    }
+    double *partial = (double *)(ws + L.partial);
+    if (out->z || out->x || out->fid) {
+        const u64 blocks = (u64)T1 << L.chunks_log2;
+        hipLaunchKernelGGL(k_traj_obs<R>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<R> *)states, n, L.chunk_log2, L.chunks_log2,
+                           (const uint64_t *)final_frame, n_traj, partial);
+        QS_LAUNCH_CHECK("traj_obs");
+        const int work = n_traj * (2 * n + 1);
+        hipLaunchKernelGGL(k_traj_final, dim3((work + 255) / 256), dim3(256), 0, st, (const double *)partial, n, 1 << L.chunks_log2, n_traj,
+                           (const uint64_t *)final_frame, out->z, out->x, out->fid);
+        QS_LAUNCH_CHECK("traj_final");
+    }
+    if (out->prob_mean) {
+        hipLaunchKernelGGL(k_traj_prob_mean<R>, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, (const cx<R> *)states, N, n_traj,
+                           (const uint64_t *)final_frame, out->prob_mean);
+        QS_LAUNCH_CHECK("traj_prob_mean");
+    }
+    return QS_OK;
+}
+
+int validate_gates(int n, const qs_gate *gates, int count);
+
+}  // namespace qs
+
+using namespace qs;
+
+QS_API int qs_traj_workspace_bytes(int n, int dtype, int count, int n_traj, size_t *bytes) {
+    if (!bytes) return fail(QS_ERR_ARG, "null output");
+    if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_ERR_DTYPE, "dtype must be QS_C64 or QS_C128");
+    if (n < 1 || n > kTrajMaxQubits) return fail(QS_ERR_ARG, "trajectories need 1 <= n <= 20");
+    if (count < 1 || count > kTrajMaxGates || n_traj < 1) return fail(QS_ERR_ARG, "bad gate or trajectory count");
+    *bytes = traj_layout(n, dtype, count, n_traj).total;
+    return QS_OK;
+}
+
+QS_API int qs_traj_run(int n, int dtype, const qs_gate *gates, int count, uint64_t basis_index, int n_traj, double p_depol, uint64_t seed,
+                       const qs_traj_out *out, void *ws, size_t ws_bytes, void *stream) {
+    try {
+        if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_ERR_DTYPE, "dtype must be QS_C64 or QS_C128");
+        if (n < 1 || n > kTrajMaxQubits) return fail(QS_ERR_ARG, "trajectories need 1 <= n <= 20");
+        if (count < 1 || count > kTrajMaxGates || n_traj < 1) return fail(QS_ERR_ARG, "bad gate or trajectory count");
+        if (!out || !ws) return fail(QS_ERR_ARG, "null output struct or workspace");
+        if (out->log && out->log_cap < 1) return fail(QS_ERR_ARG, "log_cap must be >= 1 with a log buffer");
+        if (basis_index >= (1ull << n)) return fail(QS_ERR_ARG, "basis index >= 2^n");
+        if (!(p_depol >= 0.0 && p_depol <= 1.0)) return fail(QS_ERR_ARG, "p must be in [0, 1]");
+        if (int rc = validate_gates(n, gates, count)) return rc;
+        if (ws_bytes < traj_layout(n, dtype, count, n_traj).total) return fail(QS_ERR_SIZE, "trajectory workspace too small");
+        hipStream_t st = (hipStream_t)stream;
+        return dtype == QS_C128 ? traj_run_t<double, 12>(n, dtype, gates, count, basis_index, n_traj, p_depol, seed, out, (char *)ws, st)
+                                : traj_run_t<float, 13>(n, dtype, gates, count, basis_index, n_traj, p_depol, seed, out, (char *)ws, st);
+    } catch (...) {
+        return fail(QS_ERR_UNSUPPORTED, "unexpected internal error");
+    }
+}

@@ -86,7 +86,7 @@ def lib():
             "qs_qaoa_run": [vp, vp, i, vp, vp, vp, sz, vp],
             "qs_pool_workspace_bytes": [vp, vp],
             "qs_pool_run": [vp, vp, vp, vp, vp, sz, vp],
-            "qs_traj_workspace_bytes": [i, i, i, vp],
+            "qs_traj_workspace_bytes": [i, i, i, i, vp],
             "qs_traj_run": [i, i, vp, i, u64, i, d, u64, vp, vp, sz, vp],
         }
         for name, args in sigs.items():
@@ -246,3 +246,81 @@ class State:
         o = self._out(max(shots, 1), torch.int64)
         check(lib().qs_sample(self._h, shots, seed, ctypes.c_void_p(o.data_ptr())))
         return o[:shots]
+
+
+# ---------------------------------------------------------------- QAOA Max-Cut
+class Qaoa:
+    """QAOA Max-Cut instance on one graph: energies and adjoint gradients for
+    batches of angle vectors [gamma_1..gamma_p, beta_1..beta_p] held on the GPU."""
+
+    def __init__(self, n: int, edges, p: int, w=None, device="cuda"):
+        self.n, self.p = n, p
+        self._edges = _edges(edges)
+        self._w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        self._desc = QaoaDesc(n, p, len(self._edges), self._edges.ctypes.data, None if self._w is None else self._w.ctypes.data)
+        self.device = device
+        self._ws = {}
+
+    def workspace(self, with_grad: bool) -> torch.Tensor:
+        if with_grad not in self._ws:
+            nbytes = ctypes.c_size_t()
+            check(lib().qs_qaoa_workspace_bytes(ctypes.byref(self._desc), int(with_grad), ctypes.byref(nbytes)))
+            self._ws[with_grad] = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        return self._ws[with_grad]
+
+    def run(self, angles: torch.Tensor, grad: bool = True, stream=None):
+        """angles: float64 [B, 2p] or [2p] on the GPU.  Returns (E [B], grad [B, 2p] or None)."""
+        a = angles.reshape(-1, 2 * self.p)
+        assert a.dtype == torch.float64 and a.is_cuda
+        a = a.contiguous()
+        B = a.shape[0]
+        E = torch.empty(B, dtype=torch.float64, device=a.device)
+        G = torch.empty(B, 2 * self.p, dtype=torch.float64, device=a.device) if grad else None
+        ws = self.workspace(grad)
+        check(lib().qs_qaoa_run(ctypes.byref(self._desc), ctypes.c_void_p(a.data_ptr()), B, ctypes.c_void_p(E.data_ptr()),
+                                ctypes.c_void_p(G.data_ptr()) if grad else None, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                ctypes.c_void_p(_stream_ptr(stream))))
+        return E, G
+
+
+def traj_run(n: int, gates: np.ndarray, basis_index: int, n_traj: int, p: float, seed: int, dtype=torch.complex128,
+             log_cap: int = 0, prob_mean: bool = True, device="cuda", stream=None) -> dict:
+    """Noise trajectories with stochastic Pauli insertion.  Returns device tensors:
+    z, x [n_traj, n]; fid [n_traj]; counts [n_traj]; prob_mean [2^n]; log [n_traj, log_cap]."""
+    g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
+    code = QS_C128 if dtype == torch.complex128 else QS_C64
+    nbytes = ctypes.c_size_t()
+    check(lib().qs_traj_workspace_bytes(n, code, len(g), n_traj, ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+    f64 = dict(dtype=torch.float64, device=device)
+    res = {"z": torch.empty(n_traj, n, **f64), "x": torch.empty(n_traj, n, **f64), "fid": torch.empty(n_traj, **f64),
+           "counts": torch.empty(n_traj, dtype=torch.int32, device=device)}
+    if prob_mean:
+        res["prob_mean"] = torch.empty(1 << n, **f64)
+    if log_cap:
+        res["log"] = torch.zeros(n_traj, log_cap, dtype=torch.int32, device=device)
+    out = TrajOut(res["z"].data_ptr(), res["x"].data_ptr(), res["fid"].data_ptr(),
+                  res["prob_mean"].data_ptr() if prob_mean else None, res["counts"].data_ptr(),
+                  res["log"].data_ptr() if log_cap else None, log_cap)
+    check(lib().qs_traj_run(n, code, _ptr(g), len(g), basis_index, n_traj, p, seed, ctypes.byref(out),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream_ptr(stream))))
+    # ws is released to torch's caching allocator in stream order: later work
+    # on this stream cannot overwrite it before the kernels above have run.
+    return res
+
+
+class QAOAEnergy(torch.autograd.Function):
+    """E(theta) = <psi(theta)|C|psi(theta)> with the adjoint gradient as backward."""
+
+    @staticmethod
+    def forward(ctx, angles: torch.Tensor, problem: Qaoa):
+        E, G = problem.run(angles.detach(), grad=True)
+        ctx.save_for_backward(G)
+        ctx.shape = angles.shape
+        return E.reshape(angles.shape[:-1]) if angles.dim() > 1 else E[0]
+
+    @staticmethod
+    def backward(ctx, gE):
+        (G,) = ctx.saved_tensors
+        g = gE.reshape(-1, 1) * G
+        return g.reshape(ctx.shape), None

@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=32, help="qubits of the sweep register")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the QAOA, pool and trajectory measurements")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_1q_32q_c128.json"))
     return ap.parse_args()
@@ -101,6 +102,106 @@ def sweep_bench(n, steps, warmup):
     del s
     torch.cuda.empty_cache()
     return wall, per_1q, per_cx, norm
+
+
+def _time_cuda(fn, reps):
+    import torch
+    st = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        fn()
+    b.record(st)
+    b.synchronize()
+    return a.elapsed_time(b) * 1e-3 / reps
+
+
+def qaoa_bench():
+    """QAOA Max-Cut, 24 qubits, random 3-regular graph, p = 8, angles U[0, pi]:
+    adjoint gradient evaluations/s vs central finite differences (h = 1e-6,
+    2 * 2p forward evaluations per gradient, batched through the same fused
+    forward) on the same GPU."""
+    import numpy as np
+    import torch
+
+    from paper_2001_10554_amd import workloads as W
+    from paper_2001_10554_amd.qsim import Qaoa
+    n, p, h = 24, 8, 1e-6
+    edges = W.random_regular_graph(n, 3, seed=3)
+    theta = torch.tensor(W.qaoa_angles(p, seed=3), device="cuda")
+    prob = Qaoa(n, edges, p)
+    t_adj = _time_cuda(lambda: prob.run(theta, grad=True), 10)
+    E, G = prob.run(theta, grad=True)
+    shifts = theta.repeat(4 * p, 1)
+    idx = torch.arange(2 * p, device="cuda")
+    shifts[2 * idx, idx] += h
+    shifts[2 * idx + 1, idx] -= h
+    # FD forwards in one batched call (workspace for all 4p angle sets at once).
+    prob._ws[False] = torch.empty(prob.workspace(False).numel() * 4 * p, dtype=torch.uint8, device="cuda")
+    t_fd = _time_cuda(lambda: prob.run(shifts, grad=False), 3)
+    Es, _ = prob.run(shifts, grad=False)
+    fd = (Es[0::2] - Es[1::2]) / (2 * h)
+    g = G[0]
+    out = {"workload": "QAOA Max-Cut, 24 qubits, random 3-regular graph (seed 3), p=8, angles U[0,pi] (seed 3), complex128",
+           "adjoint_grads_per_s": round(1.0 / t_adj, 2), "adjoint_ms": round(t_adj * 1e3, 3),
+           "fd_grads_per_s": round(1.0 / t_fd, 2), "fd_ms": round(t_fd * 1e3, 3),
+           "ratio": round(t_fd / t_adj, 2), "E": E.item(), "max_abs_adj_minus_fd": float(torch.max(torch.abs(g - fd)).item())}
+    del prob
+    torch.cuda.empty_cache()
+    return out
+
+
+def pool_bench(reps=2):
+    """Pool: 256 QAOA Max-Cut graphs (qubit counts uniform over {14,...,22},
+    random 3-regular), p = 4, 64 swarm-style angle sets per graph in [0, 2pi):
+    all 16,384 <C> values and adjoint gradients per replay of the captured graph."""
+    import numpy as np
+    import torch
+
+    from paper_2001_10554_amd import workloads as W
+    from paper_2001_10554_amd.qsim import Pool
+    w = W.pool_workload(256, 64, 4, seed=4)
+    pool = Pool(w.graphs, w.n_qubits, 64, 4)
+    a = torch.tensor(np.concatenate(w.angles), device="cuda")
+    t0 = time.perf_counter()
+    pool.run(a)  # plans, autotunes, captures
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    t = _time_cuda(lambda: pool.run(), reps)
+    out = {"workload": "pool: 256 graphs x 64 angle sets, n ~ U{14..22}, p=4, complex128, E + gradients",
+           "circuits": pool.count, "seconds_per_pool": round(t, 4), "circuits_per_s": round(pool.count / t, 1),
+           "gradients_per_s": round(pool.count / t, 1), "setup_s": round(t_setup, 2),
+           "workspace_GiB": round(pool.ws.numel() / 2**30, 2),
+           "finite": bool(torch.isfinite(pool.E).all().item())}
+    del pool
+    torch.cuda.empty_cache()
+    return out
+
+
+def traj_bench():
+    """Noise ensemble: 16-qubit QFT on a seeded basis state, depolarizing p = 1e-3
+    per touched qubit as stochastic Pauli insertions, 1024 trajectories."""
+    import numpy as np
+    import torch
+
+    from paper_2001_10554_amd import workloads as W
+    from paper_2001_10554_amd.qsim import traj_run
+    n, T, p = 16, 1024, 1e-3
+    gates = W.qft_circuit(n)
+    x0 = W.random_basis_index(n, 5)
+    out = {"workload": "16-qubit QFT on a seeded basis state, depolarizing p=1e-3, 1024 trajectories"}
+    for name, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        t = _time_cuda(lambda: traj_run(n, gates, x0, T, p, seed=5, dtype=dt, prob_mean=True), 3)
+        r = traj_run(n, gates, x0, T, p, seed=5, dtype=dt)
+        fid = r["fid"].cpu().numpy()
+        curve = {str(k): float(fid[:k].mean()) for k in (1, 4, 16, 64, 256, 1024)}
+        out[name] = {"trajectories_per_s": round(T / t, 1), "ms": round(t * 1e3, 3), "mean_fidelity": float(fid.mean()),
+                     "fidelity_mean_vs_T": curve, "max_abs_Z": float(r["z"].abs().max().item()),
+                     "max_abs_p_minus_2^-16": float((r["prob_mean"] - 2.0 ** -n).abs().max().item()),
+                     "insertions": int(r["counts"].sum().item())}
+    return out
 
 
 def cpu_baseline(seconds):
@@ -180,6 +281,13 @@ def main():
         "min_1q_frac": round(min(per_q.values()) / PEAK_HBM_GBS, 4),
         "norm_after": norm,
     }
+    if not args.no_extra:
+        log("QAOA adjoint vs finite differences")
+        out["qaoa"] = qaoa_bench()
+        log("pool")
+        out["pool"] = pool_bench()
+        log("trajectories")
+        out["traj"] = traj_bench()
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

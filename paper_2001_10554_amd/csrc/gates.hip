@@ -106,19 +106,30 @@ int launch_scale(qs_state *s, const double *norm_dev) {
 
 // ------------------------------------------------------------------ one-qubit gate (eq. 3)
 
-// Block-index remap: hardware hands consecutive workgroups to the 8 XCDs in
-// turn; with XCD = true each XCD instead walks one contiguous eighth of the
-// pairs.
-__device__ __forceinline__ u64 logical_block(bool xcd) {
+// Block-index remap.  The hardware hands consecutive workgroups to the 8 XCDs
+// in turn, so by default all XCDs stream through one common window of the
+// state.  With chunk = C > 0, XCD x instead takes runs of C consecutive
+// logical blocks (groups of 8C blocks, XCD x owning the x-th run of each
+// group); chunk = ~0 gives each XCD one contiguous eighth of the grid.
+__device__ __forceinline__ u64 logical_block(u32 chunk) {
     const u64 b = blockIdx.x, nb = gridDim.x;
-    if (!xcd || (nb & 7)) return b;
-    return (b & 7) * (nb >> 3) + (b >> 3);
+    if (chunk == 0 || (nb & 7)) return b;
+    if (chunk == ~0u) return (b & 7) * (nb >> 3) + (b >> 3);
+    const u64 C = chunk;
+    if (nb % (8 * C)) return b;
+    const u64 r = b >> 3;
+    return (r / C) * (8 * C) + (b & 7) * C + (r % C);
 }
 
-template <typename R, int PPT, bool NT, bool XCD>
-__global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u64 npairs, int q, Mat2<R> u) {
+// CTRL: a controlled gate whose control qubit c lies inside every 128-byte
+// line (c < 3 for c128, c < 4 for c64).  Such a gate touches half of every
+// line, so the whole line is moved anyway; these kernels then stream all
+// pairs and leave the control-0 ones unchanged, keeping loads and stores
+// full-line.
+template <typename R, int PPT, bool NT, bool CTRL = false>
+__global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u64 npairs, int q, Mat2<R> u, u32 chunk, int c = 0) {
     const u64 s = 1ull << q;
-    const u64 lb = logical_block(XCD);
+    const u64 lb = logical_block(chunk);
     const u64 first = lb * (kBlock * PPT) + threadIdx.x;
     cx<R> a[PPT], b[PPT];
     u64 i0[PPT];
@@ -131,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u6
         }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            apply2<R>(u, a[j], b[j]);
+            if (!CTRL || ((i0[j] >> c) & 1)) apply2<R>(u, a[j], b[j]);
             st<NT>(psi + i0[j], a[j]);
             st<NT>(psi + i0[j] + s, b[j]);
         }
@@ -140,6 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u6
             const u64 k = first + (u64)j * kBlock;
             if (k >= npairs) break;
             const u64 i = insert0(k, q);
+            if (CTRL && !((i >> c) & 1)) continue;
             cx<R> x = psi[i], y = psi[i + s];
             apply2<R>(u, x, y);
             psi[i] = x;
@@ -153,8 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u6
 // covers one contiguous 1 KiB (c128) run and the partner arrives by a lane
 // shuffle (lane xor 2^q).  Lane with bit q clear computes U00 a + U01 b, the
 // other U10 a + U11 b.  Requires 2^n to be a multiple of 256 * APT.
-template <typename R, int APT, bool NT>
-__global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ psi, int q, Mat2<R> u) {
+template <typename R, int APT, bool NT, bool CTRL = false>
+__global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ psi, int q, Mat2<R> u, int c = 0) {
     const u64 first = (u64)blockIdx.x * (kBlock * APT) + threadIdx.x;
     const int lane = threadIdx.x & 63, mask = 1 << q;
     const bool upper = lane & mask;
@@ -172,55 +184,72 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ ps
         cx<R> r;
         r.x = own_re * a[j].x - own_im * a[j].y + oth_re * b.x - oth_im * b.y;
         r.y = own_re * a[j].y + own_im * a[j].x + oth_re * b.y + oth_im * b.x;
+        if (CTRL && !(((first + (u64)j * kBlock) >> c) & 1)) r = a[j];
         st<NT>(psi + first + (u64)j * kBlock, r);
     }
 }
 
-// Kernel choice for the one-qubit gate: (low-q method, high-q method).  The
-// default was picked by timing every target of a 32-qubit complex128 sweep;
-// QSIM_1Q_VARIANT selects the alternatives for tuning runs.
-static int variant_1q() {
-    static int v = [] {
-        const char *e = getenv("QSIM_1Q_VARIANT");
-        return e ? atoi(e) : 0;
+// Launch shape of the one-qubit gate.  Defaults come from timing every target
+// of a 32-qubit complex128 sweep; the QSIM_1Q_* variables override them for
+// tuning runs (PPT: pairs per thread 1/2/4; NT: non-temporal hints 0/1;
+// CHUNK: block remap, 0 = hardware order, -1 = XCD eighths, C = runs of C
+// blocks; LANE: lane-shuffle kernel for q < 6, 0/1).
+struct Shape1q {
+    int ppt, nt, lane;
+    u32 chunk;
+};
+
+static Shape1q shape_1q() {
+    static Shape1q sh = [] {
+        auto env = [](const char *k, long dflt) {
+            const char *e = getenv(k);
+            return e ? atol(e) : dflt;
+        };
+        Shape1q v;
+        v.ppt = (int)env("QSIM_1Q_PPT", 2);
+        v.nt = (int)env("QSIM_1Q_NT", 1);
+        v.lane = (int)env("QSIM_1Q_LANE", 1);
+        v.chunk = (u32)env("QSIM_1Q_CHUNK", 0x7fffffff);  // 0x7fffffff: per-target schedule below
+        return v;
     }();
-    return v;
+    return sh;
+}
+
+// Per-XCD run length (in blocks of 512 pairs) for target q.  Measured on a
+// 32-qubit complex128 sweep: up to q = 17 runs of 128-256 blocks (1-2 MiB of
+// each partner stream per XCD) are best; above, the best run length doubles
+// with q mod 4 (16, 32, 64, 128 blocks for q = 0, 1, 2, 3 mod 4), i.e. it
+// tracks the address bits in which the two partner streams differ.
+static u32 chunk_for_target(int q) {
+    if (q <= 12 || q == 17) return 256;
+    if (q <= 16) return 128;
+    return 16u << ((q - 20) & 3);
 }
 
 template <typename R> static int launch_1q_t(qs_state *s, int q, const double *u) {
     const u64 N = 1ull << s->n, npairs = N >> 1;
     const Mat2<R> m = to_mat<R>(u);
     cx<R> *psi = (cx<R> *)s->buf;
-    const int v = variant_1q();
+    const Shape1q v = shape_1q();
+    const u32 chunk = v.chunk == 0x7fffffffu ? chunk_for_target(q) : v.chunk;
     hipStream_t st = s->stream;
-#define PAIR(PPT, NT, XCD) \
-    hipLaunchKernelGGL((k_apply_1q<R, PPT, NT, XCD>), dim3(grid_for(npairs, kBlock * PPT)), dim3(kBlock), 0, st, psi, npairs, q, m)
-#define LANE(APT, NT) hipLaunchKernelGGL((k_apply_1q_lane<R, APT, NT>), dim3((unsigned)(N / (kBlock * APT))), dim3(kBlock), 0, st, psi, q, m)
-    const bool lane_ok = q < 6 && N >= (u64)kBlock * 4;
-    switch (v) {
-    case 1: PAIR(1, false, false); break;
-    case 2: PAIR(2, false, false); break;
-    case 3: PAIR(4, false, false); break;
-    case 4: PAIR(2, true, false); break;
-    case 5: PAIR(4, true, false); break;
-    case 6: PAIR(1, true, false); break;
-    case 7: PAIR(2, true, true); break;
-    case 8: PAIR(1, true, true); break;
-    case 9:
-        if (lane_ok) LANE(2, true); else PAIR(2, true, false);
-        break;
-    case 10:
-        if (lane_ok) LANE(4, true); else PAIR(2, true, true);
-        break;
-    case 11:
-        if (lane_ok) LANE(2, false); else PAIR(2, true, true);
-        break;
-    default:
-        if (lane_ok) LANE(2, true); else PAIR(2, true, false);
-        break;
+#define PAIR(PPT, NT) \
+    hipLaunchKernelGGL((k_apply_1q<R, PPT, NT>), dim3(grid_for(npairs, kBlock * PPT)), dim3(kBlock), 0, st, psi, npairs, q, m, chunk)
+    if (v.lane && q < 6 && N >= (u64)kBlock * 2) {
+        if (v.nt)
+            hipLaunchKernelGGL((k_apply_1q_lane<R, 2, true>), dim3((unsigned)(N / (kBlock * 2))), dim3(kBlock), 0, st, psi, q, m);
+        else
+            hipLaunchKernelGGL((k_apply_1q_lane<R, 2, false>), dim3((unsigned)(N / (kBlock * 2))), dim3(kBlock), 0, st, psi, q, m);
+    } else if (v.nt) {
+        if (v.ppt == 1) PAIR(1, true);
+        else if (v.ppt == 4) PAIR(4, true);
+        else PAIR(2, true);
+    } else {
+        if (v.ppt == 1) PAIR(1, false);
+        else if (v.ppt == 4) PAIR(4, false);
+        else PAIR(2, false);
     }
 #undef PAIR
-#undef LANE
     QS_LAUNCH_CHECK("apply_1q");
     return QS_OK;
 }
@@ -233,10 +262,10 @@ int launch_apply_1q(qs_state *s, int q, const double *u) {
 // Only the 2^{n-2} pairs whose control bit is 1 are read and written.
 
 template <typename R, int PPT>
-__global__ __launch_bounds__(kBlock) void k_apply_c1q(cx<R> *__restrict__ psi, u64 nquads, int c, int t, Mat2<R> u) {
+__global__ __launch_bounds__(kBlock) void k_apply_c1q(cx<R> *__restrict__ psi, u64 nquads, int c, int t, Mat2<R> u, u32 chunk) {
     const int lo = c < t ? c : t, hi = c < t ? t : c;
     const u64 sc = 1ull << c, st_ = 1ull << t;
-    const u64 first = (u64)blockIdx.x * (kBlock * PPT) + threadIdx.x;
+    const u64 first = logical_block(chunk) * (kBlock * PPT) + threadIdx.x;
     cx<R> a[PPT], b[PPT];
     u64 i0[PPT];
     bool ok[PPT];
@@ -246,24 +275,37 @@ __global__ __launch_bounds__(kBlock) void k_apply_c1q(cx<R> *__restrict__ psi, u
         ok[j] = k < nquads;
         i0[j] = insert0(insert0(k, lo), hi) | sc;
         if (ok[j]) {
-            a[j] = psi[i0[j]];
-            b[j] = psi[i0[j] | st_];
+            a[j] = ld<true>(psi + i0[j]);
+            b[j] = ld<true>(psi + (i0[j] | st_));
         }
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         if (ok[j]) {
             apply2<R>(u, a[j], b[j]);
-            psi[i0[j]] = a[j];
-            psi[i0[j] | st_] = b[j];
+            st<true>(psi + i0[j], a[j]);
+            st<true>(psi + (i0[j] | st_), b[j]);
         }
     }
 }
 
 template <typename R> static int launch_c1q_t(qs_state *s, int c, int t, const double *u) {
-    const u64 nquads = 1ull << (s->n - 2);
-    hipLaunchKernelGGL((k_apply_c1q<R, 2>), dim3(grid_for(nquads, kBlock * 2)), dim3(kBlock), 0, s->stream, (cx<R> *)s->buf, nquads, c, t,
-                       to_mat<R>(u));
+    const u64 N = 1ull << s->n, nquads = N >> 2;
+    const Mat2<R> m = to_mat<R>(u);
+    cx<R> *psi = (cx<R> *)s->buf;
+    hipStream_t st = s->stream;
+    const int line_bits = sizeof(R) == 8 ? 3 : 4;  // amplitudes per 128-byte line
+    if (c < line_bits) {
+        // Control inside the line: stream every pair of target t with full-line
+        // accesses and leave the control-0 pairs unchanged.
+        if (t < 6 && N >= (u64)kBlock * 2)
+            hipLaunchKernelGGL((k_apply_1q_lane<R, 2, true, true>), dim3((unsigned)(N / (kBlock * 2))), dim3(kBlock), 0, st, psi, t, m, c);
+        else
+            hipLaunchKernelGGL((k_apply_1q<R, 2, true, true>), dim3(grid_for(N >> 1, kBlock * 2)), dim3(kBlock), 0, st, psi, N >> 1, t, m,
+                               chunk_for_target(t), c);
+    } else {
+        hipLaunchKernelGGL((k_apply_c1q<R, 2>), dim3(grid_for(nquads, kBlock * 2)), dim3(kBlock), 0, st, psi, nquads, c, t, m, chunk_for_target(t));
+    }
     QS_LAUNCH_CHECK("apply_c1q");
     return QS_OK;
 }

@@ -40,12 +40,18 @@ struct QGeom {
 };
 
 // Where circuit c of a launch keeps its data: ws + c * circ_bytes + offset
-// (offsets < 0 mean "absent"); its angles are theta + c * 2p.
+// (offsets < 0 mean "absent").  Single-graph launches: its angles are
+// theta + c * 2p and its outputs slot c.  Pooled launches: it is circuit
+// circ_map[c0 + c] of the pool (angles and outputs at that index), and its
+// pass-k descriptor is passes[((c0 + c) / sets) * np + k].
 struct QBatch {
     char *ws;
     u64 circ_bytes;
     long long in_off, out_off, lam_off, part_off, epart_off;
     const double *theta;
+    const struct QPass *passes;
+    const int32_t *circ_map;
+    int c0, k, sets, np;
 };
 
 struct QPlan {
@@ -64,6 +70,8 @@ struct QLayout {
 int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double *w, int TB, QPlan &plan);
 QLayout qaoa_layout(const QGeom &g, int with_grad);
 int launch_qaoa_batch(const QPlan &plan, const double *theta, int nb, double *E_out, double *grad_out, char *ws, size_t circ_bytes, hipStream_t st);
+// nb circuits starting at B.c0 of a pooled size class (unit weights).
+int launch_qaoa_pooled(int TB, const QGeom &geo, const QBatch &B, int nb, double *E_out, double *grad_out, hipStream_t st);
 int check_edges(int n, int ne, const int32_t *edges);
 int qaoa_default_tb(int n);
 

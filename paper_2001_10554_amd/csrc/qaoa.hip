@@ -177,17 +177,27 @@ __device__ __forceinline__ double qblock_sum(double v, double *sh) {
 
 // Forward pass.  in_off < 0 only for the first pass (uniform state generated
 // on the fly); out_off < 0 skips the store (E-only last pass).
-template <typename CT, int TB>
-__global__ __launch_bounds__(kQThreads) void k_qaoa_fwd(QPass P, QWeights W, QGeom geo, QBatch B) {
+template <typename CT, int TB, bool POOLED>
+__global__ __launch_bounds__(kQThreads) void k_qaoa_fwd(QPass Parg, QWeights W, QGeom geo, QBatch B) {
     constexpr int JB = TB - 8, R = 1 << JB;
     __shared__ d2v sh[1 << TB];
     __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
     __shared__ double red[kQThreads / 64];
     const u64 c = blockIdx.x >> geo.glog, tile = blockIdx.x & ((1ull << geo.glog) - 1);
+    const QPass *Pp;
+    u64 cid;
+    if constexpr (POOLED) {
+        Pp = B.passes + ((B.c0 + c) / B.sets) * B.np + B.k;
+        cid = (u64)B.circ_map[B.c0 + c];
+    } else {
+        Pp = &Parg;
+        cid = c;
+    }
+    const QPass &P = *Pp;
     char *region = B.ws + c * B.circ_bytes;
     const d2v *in = B.in_off >= 0 ? (const d2v *)(region + B.in_off) : nullptr;
     d2v *out = B.out_off >= 0 ? (d2v *)(region + B.out_off) : nullptr;
-    const double *theta = B.theta + c * 2 * geo.p;
+    const double *theta = B.theta + cid * 2 * geo.p;
     const int TS = 1 << P.tb;
     const int tid = threadIdx.x;
     const int l = P.layer, p = geo.p;
@@ -246,18 +256,28 @@ __global__ __launch_bounds__(kQThreads) void k_qaoa_fwd(QPass P, QWeights W, QGe
 // Backward pass: see the file comment.  partial[pidx][tile][3] = (Im<lam|C|psi>
 // at the end phase, sum_j Im<lam|X_j|psi>, Im<lam|C|phi_1> at the first pass's
 // start phase).  The checkpoint is read from in_off, lambda lives at lam_off.
-template <typename CT, int TB>
-__global__ __launch_bounds__(kQThreads) void k_qaoa_bwd(QPass P, QWeights W, QGeom geo, QBatch B) {
+template <typename CT, int TB, bool POOLED>
+__global__ __launch_bounds__(kQThreads) void k_qaoa_bwd(QPass Parg, QWeights W, QGeom geo, QBatch B) {
     constexpr int JB = TB - 8, R = 1 << JB;
     __shared__ d2v shl[1 << TB], shp[1 << TB];
     __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
     __shared__ double red[kQThreads / 64];
     const u64 c = blockIdx.x >> geo.glog, tile = blockIdx.x & ((1ull << geo.glog) - 1);
+    const QPass *Pp;
+    u64 cid;
+    if constexpr (POOLED) {
+        Pp = B.passes + ((B.c0 + c) / B.sets) * B.np + B.k;
+        cid = (u64)B.circ_map[B.c0 + c];
+    } else {
+        Pp = &Parg;
+        cid = c;
+    }
+    const QPass &P = *Pp;
     char *region = B.ws + c * B.circ_bytes;
     const d2v *ckpt = (const d2v *)(region + B.in_off);
     d2v *lam = (d2v *)(region + B.lam_off);
     double *partial = (double *)(region + B.part_off);
-    const double *theta = B.theta + c * 2 * geo.p;
+    const double *theta = B.theta + cid * 2 * geo.p;
     const int TS = 1 << P.tb;
     const int tid = threadIdx.x;
     const int l = P.layer, p = geo.p;
@@ -342,11 +362,13 @@ __global__ __launch_bounds__(kQThreads) void k_qaoa_bwd(QPass P, QWeights W, QGe
 // E and gradient of circuit blockIdx.y: one block per output, partials summed
 // in a fixed order.  Output k < 2p: gradient component; k = 2p: E.  Without a
 // gradient the grid has one block per circuit, which computes E.
+template <bool POOLED>
 __global__ __launch_bounds__(kQThreads) void k_qaoa_final(QGeom geo, QBatch B, double *__restrict__ E_out, double *__restrict__ grad_out, int with_grad) {
     __shared__ double red[kQThreads / 64];
     const int p = geo.p, P = geo.P, G = geo.G;
     const int k = with_grad ? (int)blockIdx.x : 2 * p;
     const u64 c = blockIdx.y;
+    const u64 cid = POOLED ? (u64)B.circ_map[B.c0 + c] : c;
     const char *region = B.ws + c * B.circ_bytes;
     const double *partial = (const double *)(region + B.part_off);
     const double *e_partial = (const double *)(region + B.epart_off);
@@ -368,9 +390,9 @@ __global__ __launch_bounds__(kQThreads) void k_qaoa_final(QGeom geo, QBatch B, d
     const double t = qblock_sum(a, red);
     if (threadIdx.x == 0) {
         if (k == 2 * p)
-            E_out[c] = t;
+            E_out[cid] = t;
         else
-            grad_out[c * 2 * p + k] = 2.0 * t;
+            grad_out[cid * 2 * p + k] = 2.0 * t;
     }
 }
 
@@ -485,47 +507,76 @@ QLayout qaoa_layout(const QGeom &g, int with_grad) {
     return L;
 }
 
-template <typename CT, int TB>
-static void launch_batch_t(const QPlan &plan, const double *theta, int nb, double *E_out, double *grad_out, char *ws, size_t circ_bytes, hipStream_t st) {
-    const QGeom &g = plan.geo;
+// Forward (+ backward + final) launches for nb circuits.  Single-graph mode
+// takes the pass descriptors by value from `passes`; pooled mode reads them
+// from B.passes on the device.
+template <typename CT, int TB, bool POOLED>
+static void launch_batch_t(const QGeom &g, const QPass *passes, const QWeights &W, QBatch B, int nb, double *E_out, double *grad_out,
+                           hipStream_t st) {
     const QLayout L = qaoa_layout(g, grad_out != nullptr);
     const size_t sb = ((size_t)1 << g.n) * 16;
     const int np = g.p * g.P;
     const dim3 grid((unsigned)((u64)nb << g.glog)), block(kQThreads);
-    QBatch B{ws, circ_bytes, -1, -1, L.lam, L.part, L.epart, theta};
+    B.lam_off = L.lam;
+    B.part_off = L.part;
+    B.epart_off = L.epart;
+    const QPass dummy{};
+    auto pass = [&](int k) -> const QPass & { return POOLED ? dummy : passes[k]; };
     if (grad_out) {
         for (int k = 0; k < np; ++k) {
+            B.k = k;
             B.in_off = k == 0 ? -1 : (long long)(L.ckpt + (size_t)(k - 1) * sb);
             B.out_off = (long long)(L.ckpt + (size_t)k * sb);
-            hipLaunchKernelGGL((k_qaoa_fwd<CT, TB>), grid, block, 0, st, plan.passes[k], plan.W, g, B);
+            hipLaunchKernelGGL((k_qaoa_fwd<CT, TB, POOLED>), grid, block, 0, st, pass(k), W, g, B);
         }
         for (int k = np - 1; k >= 0; --k) {
+            B.k = k;
             B.in_off = (long long)(L.ckpt + (size_t)k * sb);
-            hipLaunchKernelGGL((k_qaoa_bwd<CT, TB>), grid, block, 0, st, plan.passes[k], plan.W, g, B);
+            hipLaunchKernelGGL((k_qaoa_bwd<CT, TB, POOLED>), grid, block, 0, st, pass(k), W, g, B);
         }
-        hipLaunchKernelGGL(k_qaoa_final, dim3(2 * g.p + 1, nb), block, 0, st, g, B, E_out, grad_out, 1);
+        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(2 * g.p + 1, nb), block, 0, st, g, B, E_out, grad_out, 1);
     } else {
         for (int k = 0; k < np; ++k) {
+            B.k = k;
             B.in_off = k == 0 ? -1 : (long long)L.ckpt;
             B.out_off = k == np - 1 ? -1 : (long long)L.ckpt;
-            hipLaunchKernelGGL((k_qaoa_fwd<CT, TB>), grid, block, 0, st, plan.passes[k], plan.W, g, B);
+            hipLaunchKernelGGL((k_qaoa_fwd<CT, TB, POOLED>), grid, block, 0, st, pass(k), W, g, B);
         }
-        hipLaunchKernelGGL(k_qaoa_final, dim3(1, nb), block, 0, st, g, B, E_out, (double *)nullptr, 0);
+        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(1, nb), block, 0, st, g, B, E_out, (double *)nullptr, 0);
     }
 }
 
-int launch_qaoa_batch(const QPlan &plan, const double *theta, int nb, double *E_out, double *grad_out, char *ws, size_t circ_bytes, hipStream_t st) {
-    const bool w = plan.geo.weighted;
-    switch (plan.TB) {
-    case 10: w ? launch_batch_t<double, 10>(plan, theta, nb, E_out, grad_out, ws, circ_bytes, st)
-               : launch_batch_t<int, 10>(plan, theta, nb, E_out, grad_out, ws, circ_bytes, st); break;
-    case 12: w ? launch_batch_t<double, 12>(plan, theta, nb, E_out, grad_out, ws, circ_bytes, st)
-               : launch_batch_t<int, 12>(plan, theta, nb, E_out, grad_out, ws, circ_bytes, st); break;
-    default: w ? launch_batch_t<double, 11>(plan, theta, nb, E_out, grad_out, ws, circ_bytes, st)
-               : launch_batch_t<int, 11>(plan, theta, nb, E_out, grad_out, ws, circ_bytes, st); break;
+template <bool POOLED>
+static int launch_any(int TB, const QGeom &g, const QPass *passes, const QWeights &W, const QBatch &B, int nb, double *E_out, double *grad_out,
+                      hipStream_t st) {
+    const bool w = g.weighted;
+    switch (TB) {
+    case 10: w ? launch_batch_t<double, 10, POOLED>(g, passes, W, B, nb, E_out, grad_out, st)
+               : launch_batch_t<int, 10, POOLED>(g, passes, W, B, nb, E_out, grad_out, st); break;
+    case 12: w ? launch_batch_t<double, 12, POOLED>(g, passes, W, B, nb, E_out, grad_out, st)
+               : launch_batch_t<int, 12, POOLED>(g, passes, W, B, nb, E_out, grad_out, st); break;
+    default: w ? launch_batch_t<double, 11, POOLED>(g, passes, W, B, nb, E_out, grad_out, st)
+               : launch_batch_t<int, 11, POOLED>(g, passes, W, B, nb, E_out, grad_out, st); break;
     }
     QS_LAUNCH_CHECK("qaoa");
     return QS_OK;
+}
+
+int launch_qaoa_batch(const QPlan &plan, const double *theta, int nb, double *E_out, double *grad_out, char *ws, size_t circ_bytes, hipStream_t st) {
+    QBatch B{};
+    B.ws = ws;
+    B.circ_bytes = circ_bytes;
+    B.theta = theta;
+    return launch_any<false>(plan.TB, plan.geo, plan.passes.data(), plan.W, B, nb, E_out, grad_out, st);
+}
+
+int launch_qaoa_pooled(int TB, const QGeom &geo, const QBatch &B, int nb, double *E_out, double *grad_out, hipStream_t st) {
+    static const QWeights unit = [] {
+        QWeights w;
+        for (int e = 0; e < kQMaxEdges; ++e) w.w[e] = 1.0;
+        return w;
+    }();
+    return launch_any<true>(TB, geo, nullptr, unit, B, nb, E_out, grad_out, st);
 }
 
 static int check_desc(const qs_qaoa_desc *d) {

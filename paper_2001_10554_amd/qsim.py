@@ -283,6 +283,39 @@ class Qaoa:
         return E, G
 
 
+class Pool:
+    """A pool of QAOA Max-Cut circuits: graph g (with its own qubit count) times
+    sets_per_graph angle vectors, circuit c = g * sets_per_graph + a.  One call
+    evaluates every <C> and (optionally) every adjoint gradient; the launch
+    sequence is captured into a hipGraph on the first call and replayed after."""
+
+    def __init__(self, graphs, n_qubits, sets_per_graph: int, p: int, device="cuda", grad: bool = True, ws_bytes: int | None = None):
+        self.n_qubits = np.ascontiguousarray(n_qubits, dtype=np.int32)
+        self.edges = np.ascontiguousarray(np.concatenate([_edges(e) for e in graphs]).reshape(-1), dtype=np.int32)
+        self.offsets = np.ascontiguousarray(np.concatenate([[0], np.cumsum([len(_edges(e)) for e in graphs])]), dtype=np.int32)
+        self.sets, self.p = sets_per_graph, p
+        self.count = len(graphs) * sets_per_graph
+        self._desc = PoolDesc(len(graphs), sets_per_graph, p, self.n_qubits.ctypes.data, self.offsets.ctypes.data, self.edges.ctypes.data)
+        if ws_bytes is None:
+            nbytes = ctypes.c_size_t()
+            check(lib().qs_pool_workspace_bytes(ctypes.byref(self._desc), ctypes.byref(nbytes)))
+            ws_bytes = nbytes.value
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+        self.angles = torch.zeros(self.count, 2 * p, dtype=torch.float64, device=device)
+        self.E = torch.empty(self.count, dtype=torch.float64, device=device)
+        self.G = torch.empty(self.count, 2 * p, dtype=torch.float64, device=device) if grad else None
+
+    def run(self, angles: torch.Tensor | None = None, stream=None):
+        """Copy `angles` [count, 2p] into the pool's device buffer (if given) and
+        evaluate; returns (E, G) device tensors owned by the pool."""
+        if angles is not None:
+            self.angles.copy_(angles.reshape(self.count, 2 * self.p))
+        check(lib().qs_pool_run(ctypes.byref(self._desc), ctypes.c_void_p(self.angles.data_ptr()), ctypes.c_void_p(self.E.data_ptr()),
+                                ctypes.c_void_p(self.G.data_ptr()) if self.G is not None else None,
+                                ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.c_void_p(_stream_ptr(stream))))
+        return self.E, self.G
+
+
 def traj_run(n: int, gates: np.ndarray, basis_index: int, n_traj: int, p: float, seed: int, dtype=torch.complex128,
              log_cap: int = 0, prob_mean: bool = True, device="cuda", stream=None) -> dict:
     """Noise trajectories with stochastic Pauli insertion.  Returns device tensors:

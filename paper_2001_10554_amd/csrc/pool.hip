@@ -31,9 +31,9 @@
 namespace qs {
 
 struct PoolClass {
-    int n = 0, TB = 11;
+    int n = 0;
     std::vector<int> graphs;  // pool graph ids in this class
-    QGeom geo{};
+    QPlan proto;              // shape, kernel family and geometry shared by the class
     QPass *dev_passes = nullptr;  // [graph in class][np]
     int32_t *dev_map = nullptr;   // class-local circuit -> pool circuit id
     size_t circ_bytes = 0;
@@ -48,7 +48,7 @@ struct PoolPlan {
 
 static std::mutex g_pool_mu;
 static std::map<std::string, PoolPlan> g_pool_plans;
-static std::map<std::string, int> g_tb_choice;  // "n:p:sets:grad" -> TB
+static std::map<std::string, std::pair<int, int>> g_tb_choice;  // "n:p:sets:grad" -> (TB, r)
 
 static std::string tb_key(int n, int p, int sets, bool grad) {
     return std::to_string(n) + ":" + std::to_string(p) + ":" + std::to_string(sets) + ":" + (grad ? "1" : "0");
@@ -62,20 +62,22 @@ static void load_tb_cache() {
     if (!path) return;
     if (FILE *f = fopen(path, "r")) {
         char key[128];
-        int tb;
-        while (fscanf(f, "%127s %d", key, &tb) == 2) g_tb_choice[key] = tb;
+        int tb, r;
+        while (fscanf(f, "%127s %d %d", key, &tb, &r) == 3) g_tb_choice[key] = {tb, r};
         fclose(f);
     }
 }
 
-static void save_tb_choice(const std::string &key, int tb) {
+static void save_tb_choice(const std::string &key, QShape s) {
     const char *path = getenv("QSIM_AUTOTUNE_CACHE");
     if (!path) return;
     if (FILE *f = fopen(path, "a")) {
-        fprintf(f, "%s %d\n", key.c_str(), tb);
+        fprintf(f, "%s %d %d\n", key.c_str(), s.TB, s.r);
         fclose(f);
     }
 }
+
+static QShape shape_of(int TB, int r) { return QShape{TB, TB >= 12 ? 9 : 8, r}; }
 
 static int check_pool(const qs_pool_desc *d) {
     if (!d) return fail(QS_ERR_ARG, "null pool descriptor");
@@ -93,22 +95,24 @@ static int check_pool(const qs_pool_desc *d) {
     return QS_OK;
 }
 
-// Build the classes' device tables for the given TB choices.
-static int build_class(const qs_pool_desc *d, PoolClass &C, int TB, bool grad) {
-    C.TB = TB;
+// Build the class's device tables for one tile shape.
+static int build_class(const qs_pool_desc *d, PoolClass &C, QShape shape, bool grad) {
     std::vector<QPass> all;
     int max_edges = 0;
     QPlan plan;
     for (int g : C.graphs) {
         const int ne = d->edge_offset[g + 1] - d->edge_offset[g];
         max_edges = ne > max_edges ? ne : max_edges;
-        build_qplan(C.n, d->p, ne, d->edges + 2 * (size_t)d->edge_offset[g], nullptr, TB, plan);
+        build_qplan(C.n, d->p, ne, d->edges + 2 * (size_t)d->edge_offset[g], nullptr, shape, plan);
         all.insert(all.end(), plan.passes.begin(), plan.passes.end());
     }
-    C.geo = plan.geo;
-    C.geo.num_edges = max_edges;  // phase tables cover every graph of the class
-    C.np = d->p * C.geo.P;
-    C.circ_bytes = qaoa_layout(C.geo, grad).bytes;
+    C.proto.shape = plan.shape;
+    C.proto.rt = plan.rt;
+    C.proto.geo = plan.geo;
+    C.proto.geo.num_edges = max_edges;  // phase tables cover every graph of the class
+    C.proto.passes.clear();
+    C.np = d->p * C.proto.geo.P;
+    C.circ_bytes = qaoa_layout(C.proto.geo, grad).bytes;
     std::vector<int32_t> map;
     for (int g : C.graphs)
         for (int a = 0; a < d->sets_per_graph; ++a) map.push_back(g * d->sets_per_graph + a);
@@ -139,7 +143,7 @@ static int run_class(const qs_pool_desc *d, const PoolClass &C, const double *an
         B.c0 = c0;
         B.sets = d->sets_per_graph;
         B.np = C.np;
-        if (int rc = launch_qaoa_pooled(C.TB, C.geo, B, nb, E, grad, st)) return rc;
+        if (int rc = launch_qaoa_pooled(C.proto, B, nb, E, grad, st)) return rc;
     }
     return QS_OK;
 }
@@ -150,17 +154,16 @@ static int autotune_class(const qs_pool_desc *d, PoolClass &C, const double *ang
     load_tb_cache();
     const std::string key = tb_key(C.n, d->p, d->sets_per_graph, grad != nullptr);
     auto it = g_tb_choice.find(key);
-    if (it != g_tb_choice.end()) return build_class(d, C, it->second, grad != nullptr);
-    const char *force = getenv("QSIM_QAOA_TB");
-    if (force || C.n <= 10) return build_class(d, C, qaoa_default_tb(C.n), grad != nullptr);
+    if (it != g_tb_choice.end()) return build_class(d, C, shape_of(it->second.first, it->second.second), grad != nullptr);
+    const std::vector<QShape> cands = qaoa_candidate_shapes(C.n);
+    if (getenv("QSIM_QAOA_TB") || cands.size() == 1) return build_class(d, C, qaoa_default_shape(C.n), grad != nullptr);
     hipEvent_t e0, e1;
     QS_HIP(hipEventCreate(&e0));
     QS_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_tb = 11;
-    for (int TB : {10, 11, 12}) {
-        if (TB > C.n) continue;
-        if (int rc = build_class(d, C, TB, grad != nullptr)) return rc;
+    QShape best_s = qaoa_default_shape(C.n);
+    for (QShape s : cands) {
+        if (int rc = build_class(d, C, s, grad != nullptr)) return rc;
         if (ws_bytes < C.circ_bytes) continue;
         const u64 fit = ws_bytes / C.circ_bytes;
         const int probe = (int)(fit < 64 ? fit : 64);
@@ -175,14 +178,14 @@ static int autotune_class(const qs_pool_desc *d, PoolClass &C, const double *ang
         ms /= (float)probe;
         if (ms < best) {
             best = ms;
-            best_tb = TB;
+            best_s = s;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    g_tb_choice[key] = best_tb;
-    save_tb_choice(key, best_tb);
-    return build_class(d, C, best_tb, grad != nullptr);
+    g_tb_choice[key] = {best_s.TB, best_s.r};
+    save_tb_choice(key, best_s);
+    return build_class(d, C, best_s, grad != nullptr);
 }
 
 static std::string pool_key(const qs_pool_desc *d, const void *angles, const void *E, const void *grad, const void *ws, size_t ws_bytes) {
@@ -205,8 +208,8 @@ static size_t max_circ_bytes(const qs_pool_desc *d, bool grad) {
     for (int g = 0; g < d->num_graphs; ++g) {
         QPlan plan;
         const int ne = d->edge_offset[g + 1] - d->edge_offset[g];
-        for (int TB : {10, 11, 12}) {
-            build_qplan(d->n_qubits[g], d->p, ne, d->edges + 2 * (size_t)d->edge_offset[g], nullptr, TB, plan);
+        for (QShape s : qaoa_candidate_shapes(d->n_qubits[g])) {
+            build_qplan(d->n_qubits[g], d->p, ne, d->edges + 2 * (size_t)d->edge_offset[g], nullptr, s, plan);
             const size_t b = qaoa_layout(plan.geo, grad).bytes;
             m = b > m ? b : m;
         }

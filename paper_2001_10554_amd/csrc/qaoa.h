@@ -8,27 +8,28 @@
 
 namespace qs {
 
-constexpr int kQThreads = 256;   // 8 thread-index bits per tile
 constexpr int kQMaxEdges = 128;
 
 enum { QF_FIRST = 1, QF_PHASE_END = 2, QF_LAST = 4 };
 
-// Edge classes by where the endpoints sit for a pass's thread map: tile bits
-// 0..7 are thread-index bits ("t"), higher tile bits register-index bits
-// ("j"), other qubits fixed per tile ("r").
+// Edge classes by where the endpoints sit for a thread map: thread-index bit
+// ("t"), register-index bit ("j"), or a qubit fixed per tile ("r").
 enum { EC_TT = 0, EC_TR, EC_TJ, EC_JJ, EC_JR, EC_RR, EC_N };
 
 struct QEdge {
     uint8_t a, b, wi, pad;
 };
 
+// One pass.  Edge lists are classified for the two register layouts of the
+// register-tiled kernels (list 0 also serves the LDS kernels).
 struct QPass {
     int tb, nrest, layer, flags, pidx;
     uint32_t rx_mask;  // tile bits that receive RX
+    int use_l1;        // some RX bit is only reachable in the second layout
     uint8_t T[16];
     uint8_t rest[40];
-    uint16_t cnt[EC_N];
-    QEdge e[kQMaxEdges];
+    uint16_t cnt[2][EC_N];
+    QEdge e[2][kQMaxEdges];
 };
 
 struct QWeights {
@@ -49,13 +50,20 @@ struct QBatch {
     u64 circ_bytes;
     long long in_off, out_off, lam_off, part_off, epart_off;
     const double *theta;
-    const struct QPass *passes;
+    const QPass *passes;
     const int32_t *circ_map;
     int c0, k, sets, np;
 };
 
+// Tile shape: TB tile qubits handled by 2^TT threads; r contiguous low qubits
+// in every higher-group tile.  rt: register-tiled kernels (n >= 10).
+struct QShape {
+    int TB, TT, r;
+};
+
 struct QPlan {
-    int TB;
+    QShape shape;
+    bool rt;
     QGeom geo;
     std::vector<QPass> passes;  // forward order: pass (l, g) at index l*P + g
     QWeights W;
@@ -67,12 +75,16 @@ struct QLayout {
     size_t bytes;
 };
 
-int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double *w, int TB, QPlan &plan);
+int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double *w, QShape shape, QPlan &plan);
 QLayout qaoa_layout(const QGeom &g, int with_grad);
 int launch_qaoa_batch(const QPlan &plan, const double *theta, int nb, double *E_out, double *grad_out, char *ws, size_t circ_bytes, hipStream_t st);
 // nb circuits starting at B.c0 of a pooled size class (unit weights).
-int launch_qaoa_pooled(int TB, const QGeom &geo, const QBatch &B, int nb, double *E_out, double *grad_out, hipStream_t st);
+int launch_qaoa_pooled(const QPlan &proto, const QBatch &B, int nb, double *E_out, double *grad_out, hipStream_t st);
 int check_edges(int n, int ne, const int32_t *edges);
-int qaoa_default_tb(int n);
+// Shape with the fewest passes for n qubits (QSIM_QAOA_TB / QSIM_QAOA_R override).
+QShape qaoa_default_shape(int n);
+// Candidate shapes the pool's autotuner times.
+std::vector<QShape> qaoa_candidate_shapes(int n);
+int qaoa_passes_per_layer(int n, QShape s);
 
 }  // namespace qs

@@ -1,14 +1,14 @@
 // QAOA Max-Cut: fused forward passes and the adjoint (reverse) sweep, batched
-// over circuits that share one graph.
+// over circuits.
 //
 // Circuit: |psi> = prod_l exp(-i beta_l B) exp(-i gamma_l C) H^n |0>, with
 // B = sum_j X_j (so exp(-i beta B) = prod_j RX_j(2 beta)) and C the cut
 // counter; E = <psi|C|psi>.
 //
 // Pass structure.  The qubits are split into groups: G_0 = the TB lowest
-// qubits, then groups of at most TB - 3 higher qubits (their tiles also hold
-// qubits 0..2 so every row is a 128-byte line).  Layer l is P passes, pass
-// (l, g) applying RX(2 beta_l) to the qubits of G_g inside an LDS tile.  The
+// qubits, then groups of at most TB - r higher qubits (their tiles also hold
+// qubits 0..r-1 so every row is a 2^r-amplitude contiguous run).  Layer l is
+// P passes, pass (l, g) applying RX(2 beta_l) to the qubits of G_g.  The
 // diagonal cost layers ride along: exp(-i gamma_1 C) is applied at the start
 // of the very first pass (on the uniform state generated in registers), and
 // exp(-i gamma_{l+1} C) at the end of pass (l, P-1).  The last pass also
@@ -16,24 +16,33 @@
 //
 // Adjoint.  The forward writes every pass's output as a checkpoint.  The
 // backward walks the passes in reverse with lambda (lambda = C psi at the
-// end): because all RX of one mixer commute with each X_j, the derivative
-// inner products 2 Im<lambda|X_j|psi> of a pass's qubits can all be taken at
-// the pass's end point, where lambda and the checkpoint coincide; a phase at
-// the end of the pass gives 2 Im<lambda|C|psi> there and is then undone on
-// both vectors element-wise; finally RX(-2 beta) is applied to lambda only.
-// psi is therefore never transformed through LDS.  The first pass's phase sits
-// at its start, so its inner product uses psi regenerated on the fly
-// (exp(-i gamma_1 C(k)) 2^{-n/2}).  Inner products are per-block FP64 partial
-// sums, reduced in a fixed order.
+// end).  A phase at the end of a pass gives 2 Im<lambda|C|psi> there and is
+// then undone on both vectors element-wise; then the pass's RX gates are
+// undone one qubit at a time on both vectors, each preceded by its inner
+// product 2 Im<lambda|X_j|psi> (both vectors at the same point; the RX gates
+// of one mixer commute with every X_j).  The first pass's phase sits at its
+// start, so its inner product uses psi regenerated on the fly
+// (exp(-i gamma_1 C(k)) 2^{-n/2}).  Inner products are per-block FP64
+// partial sums, reduced in a fixed order.
 //
-// Cut values.  C(k) is never evaluated edge by edge per amplitude: for the
-// thread map m = tid + 256 j each edge is classified once per pass by where
-// its endpoints sit (thread-index bit, register-index bit, or a bit fixed per
-// tile), and a thread folds the edges into a constant plus one coefficient per
-// register bit.
+// Register tiles (n >= 10).  A tile of 2^TB amplitudes is held by 2^TT
+// threads, 2^(TB-TT) amplitudes per thread, in one of two layouts:
+//   L0: tile index m = t | j << TT;
+//   L1: m = lane | (j mod 2^W) << 6 | wave << TT | (j >> W) << (TT + W),
+// with t = wave * 64 + lane, W = TT - 6 wave bits.  Gates on register-index
+// bits act inside a thread, gates on lane bits exchange with the partner lane
+// (wavefront shuffle), and one LDS transpose between L0 and L1 reaches the
+// remaining (wave) bits.  So a pass touches LDS once per vector, instead of
+// once per gate.  Small registers (n < 10) use the LDS kernels.
+//
+// Cut values.  C(k) is never evaluated edge by edge per amplitude: each edge
+// is classified once per pass and layout by where its endpoints sit
+// (thread-index bit, register-index bit, or a qubit fixed per tile), and a
+// thread folds the edges into a constant plus one coefficient per register
+// bit.
 //
 // Batching.  blockIdx.x = circuit * G + tile; circuit c owns the workspace
-// region ws + c * circ_bytes and the angle vector theta + c * 2p.
+// region ws + c * circ_bytes.
 #include <cmath>
 #include <vector>
 
@@ -45,25 +54,29 @@
 
 namespace qs {
 
-// Cut value of the thread's R amplitudes m = tid + 256 j.  CT = int (unit
-// weights) or double.  JB = register-index bits of the tile size.
+constexpr int kLdsThreads = 256;  // LDS kernels: m = tid + 256 j
+
+// Cut value of the thread's 2^JB amplitudes for edge list `list`.  CT = int
+// (unit weights) or double.
 template <typename CT, int JB>
-__device__ __forceinline__ void cut_values(const QPass &P, const QWeights &W, bool weighted, u64 base, int tid, CT (&C)[1 << JB]) {
+__device__ __forceinline__ void cut_values(const QPass &P, int list, const QWeights &W, bool weighted, u64 base, int tid, CT (&C)[1 << JB]) {
     constexpr int R = 1 << JB;
     CT cb = 0;
     CT coef[JB > 0 ? JB : 1] = {};
     int k = 0;
+    const QEdge *E = P.e[list];
+    const uint16_t *cnt = P.cnt[list];
     auto wt = [&](const QEdge &e) -> CT { return weighted ? (CT)W.w[e.wi] : (CT)1; };
-    for (int i = 0; i < P.cnt[EC_TT]; ++i, ++k) {
-        const QEdge e = P.e[k];
+    for (int i = 0; i < cnt[EC_TT]; ++i, ++k) {
+        const QEdge e = E[k];
         cb += (((tid >> e.a) ^ (tid >> e.b)) & 1) ? wt(e) : (CT)0;
     }
-    for (int i = 0; i < P.cnt[EC_TR]; ++i, ++k) {
-        const QEdge e = P.e[k];
+    for (int i = 0; i < cnt[EC_TR]; ++i, ++k) {
+        const QEdge e = E[k];
         cb += (((tid >> e.a) & 1) != (int)((base >> e.b) & 1)) ? wt(e) : (CT)0;
     }
-    for (int i = 0; i < P.cnt[EC_TJ]; ++i, ++k) {
-        const QEdge e = P.e[k];
+    for (int i = 0; i < cnt[EC_TJ]; ++i, ++k) {
+        const QEdge e = E[k];
         const int ta = (tid >> e.a) & 1;
         const CT w = wt(e);
         cb += ta ? w : (CT)0;
@@ -72,9 +85,9 @@ __device__ __forceinline__ void cut_values(const QPass &P, const QWeights &W, bo
             if (x == e.b) coef[x] += ta ? -w : w;
     }
     const int kjj = k;
-    k += P.cnt[EC_JJ];
-    for (int i = 0; i < P.cnt[EC_JR]; ++i, ++k) {
-        const QEdge e = P.e[k];
+    k += cnt[EC_JJ];
+    for (int i = 0; i < cnt[EC_JR]; ++i, ++k) {
+        const QEdge e = E[k];
         const int br = (int)((base >> e.b) & 1);
         const CT w = wt(e);
         cb += br ? w : (CT)0;
@@ -82,8 +95,8 @@ __device__ __forceinline__ void cut_values(const QPass &P, const QWeights &W, bo
         for (int x = 0; x < JB; ++x)
             if (x == e.a) coef[x] += br ? -w : w;
     }
-    for (int i = 0; i < P.cnt[EC_RR]; ++i, ++k) {
-        const QEdge e = P.e[k];
+    for (int i = 0; i < cnt[EC_RR]; ++i, ++k) {
+        const QEdge e = E[k];
         cb += (((base >> e.a) ^ (base >> e.b)) & 1) ? wt(e) : (CT)0;
     }
 #pragma unroll
@@ -94,8 +107,8 @@ __device__ __forceinline__ void cut_values(const QPass &P, const QWeights &W, bo
             if ((j >> x) & 1) c += coef[x];
         C[j] = c;
     }
-    for (int i = 0; i < P.cnt[EC_JJ]; ++i) {
-        const QEdge e = P.e[kjj + i];
+    for (int i = 0; i < cnt[EC_JJ]; ++i) {
+        const QEdge e = E[kjj + i];
         const CT w = wt(e);
 #pragma unroll
         for (int j = 0; j < R; ++j)
@@ -139,7 +152,7 @@ __device__ __forceinline__ d2v cmul2(d2v a, d2v b) {
 }
 
 __device__ __forceinline__ void fill_table(d2v *tab, int ne_total, double g) {
-    for (int c = threadIdx.x; c <= ne_total; c += kQThreads) {
+    for (int c = threadIdx.x; c <= ne_total; c += blockDim.x) {
         double s, co;
         sincos(g * (double)c, &s, &co);
         d2v v;
@@ -149,19 +162,32 @@ __device__ __forceinline__ void fill_table(d2v *tab, int ne_total, double g) {
     }
 }
 
-// RX(theta) with (c, s) = (cos theta/2, sin theta/2) on LDS pairs of tile bit b.
-__device__ __forceinline__ void lds_rx(d2v *sh, int TS, int b, double c, double s) {
-    for (int k = threadIdx.x; k < TS / 2; k += kQThreads) {
-        const int m0 = (int)insert0((u64)k, b), m1 = m0 | (1 << b);
-        const d2v a = sh[m0], v = sh[m1];
-        d2v na, nb;
-        na.x = c * a.x + s * v.y;
-        na.y = c * a.y - s * v.x;
-        nb.x = s * a.y + c * v.x;
-        nb.y = c * v.y - s * a.x;
-        sh[m0] = na;
-        sh[m1] = nb;
-    }
+// RX(theta), (c, s) = (cos theta/2, sin theta/2): (a, v) -> (c a - i s v, -i s a + c v).
+__device__ __forceinline__ void rx_pair(d2v &a, d2v &v, double c, double s) {
+    d2v na, nb;
+    na.x = c * a.x + s * v.y;
+    na.y = c * a.y - s * v.x;
+    nb.x = s * a.y + c * v.x;
+    nb.y = c * v.y - s * a.x;
+    a = na;
+    v = nb;
+}
+
+// One lane's half of RX on a lane bit: own -> c own - i s partner.
+__device__ __forceinline__ d2v rx_half(d2v a, d2v v, double c, double s) {
+    d2v r;
+    r.x = c * a.x + s * v.y;
+    r.y = c * a.y - s * v.x;
+    return r;
+}
+
+__device__ __forceinline__ double im_conj_mul(d2v l, d2v p) { return l.x * p.y - l.y * p.x; }  // Im(conj(l) p)
+
+__device__ __forceinline__ d2v shfl_xor2(d2v v, int m) {
+    d2v r;
+    r.x = __shfl_xor(v.x, m, 64);
+    r.y = __shfl_xor(v.y, m, 64);
+    return r;
 }
 
 __device__ __forceinline__ double qblock_sum(double v, double *sh) {
@@ -171,51 +197,74 @@ __device__ __forceinline__ double qblock_sum(double v, double *sh) {
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
     double t = 0.0;
-    for (int k = 0; k < kQThreads / 64; ++k) t += sh[k];
+    const int nw = blockDim.x >> 6;
+    for (int k = 0; k < nw; ++k) t += sh[k];
     return t;
 }
 
-// Forward pass.  in_off < 0 only for the first pass (uniform state generated
-// on the fly); out_off < 0 skips the store (E-only last pass).
-template <typename CT, int TB, bool POOLED>
-__global__ __launch_bounds__(kQThreads) void k_qaoa_fwd(QPass Parg, QWeights W, QGeom geo, QBatch B) {
-    constexpr int JB = TB - 8, R = 1 << JB;
-    __shared__ d2v sh[1 << TB];
-    __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
-    __shared__ double red[kQThreads / 64];
-    const u64 c = blockIdx.x >> geo.glog, tile = blockIdx.x & ((1ull << geo.glog) - 1);
-    const QPass *Pp;
-    u64 cid;
+// Per-circuit pointers of a batched launch.
+struct QCirc {
+    const QPass *P;
+    u64 cid, tile;
+    char *region;
+    const double *theta;
+};
+
+template <bool POOLED>
+__device__ __forceinline__ QCirc qcirc(const QPass &Parg, const QGeom &geo, const QBatch &B) {
+    QCirc q;
+    const u64 c = blockIdx.x >> geo.glog;
+    q.tile = blockIdx.x & ((1ull << geo.glog) - 1);
     if constexpr (POOLED) {
-        Pp = B.passes + ((B.c0 + c) / B.sets) * B.np + B.k;
-        cid = (u64)B.circ_map[B.c0 + c];
+        q.P = B.passes + ((B.c0 + c) / B.sets) * B.np + B.k;
+        q.cid = (u64)B.circ_map[B.c0 + c];
     } else {
-        Pp = &Parg;
-        cid = c;
+        q.P = &Parg;
+        q.cid = c;
     }
-    const QPass &P = *Pp;
-    char *region = B.ws + c * B.circ_bytes;
-    const d2v *in = B.in_off >= 0 ? (const d2v *)(region + B.in_off) : nullptr;
-    d2v *out = B.out_off >= 0 ? (d2v *)(region + B.out_off) : nullptr;
-    const double *theta = B.theta + cid * 2 * geo.p;
-    const int TS = 1 << P.tb;
-    const int tid = threadIdx.x;
-    const int l = P.layer, p = geo.p;
-    const u64 base = qtile_base(P, tile);
+    q.region = B.ws + c * B.circ_bytes;
+    q.theta = B.theta + q.cid * 2 * geo.p;
+    return q;
+}
+
+// ================================================================== LDS kernels (n < 10)
+
+__device__ __forceinline__ void lds_rx(d2v *sh, int TS, int b, double c, double s) {
+    for (int k = threadIdx.x; k < TS / 2; k += kLdsThreads) {
+        const int m0 = (int)insert0((u64)k, b), m1 = m0 | (1 << b);
+        d2v a = sh[m0], v = sh[m1];
+        rx_pair(a, v, c, s);
+        sh[m0] = a;
+        sh[m1] = v;
+    }
+}
+
+// Tiles of up to 2^10 amplitudes, 256 threads, m = tid + 256 j (edge list 0).
+template <typename CT, bool POOLED>
+__global__ __launch_bounds__(kLdsThreads) void k_qaoa_fwd_lds(QPass Parg, QWeights W, QGeom geo, QBatch B) {
+    constexpr int JB = 2, R = 4;
+    __shared__ d2v sh[1 << 10];
+    __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
+    __shared__ double red[16];
+    const QCirc q = qcirc<POOLED>(Parg, geo, B);
+    const QPass &P = *q.P;
+    const d2v *in = B.in_off >= 0 ? (const d2v *)(q.region + B.in_off) : nullptr;
+    d2v *out = B.out_off >= 0 ? (d2v *)(q.region + B.out_off) : nullptr;
+    const int TS = 1 << P.tb, tid = threadIdx.x, l = P.layer, p = geo.p;
+    const u64 base = qtile_base(P, q.tile);
     const bool first = P.flags & QF_FIRST, pend = P.flags & QF_PHASE_END, last = P.flags & QF_LAST;
-    const double g_a = theta[l], g_b = pend ? theta[l + 1] : 0.0;
+    const double g_a = q.theta[l], g_b = pend ? q.theta[l + 1] : 0.0;
     if (!geo.weighted) {
         if (first) fill_table(tab_a, geo.num_edges, g_a);
         if (pend) fill_table(tab_b, geo.num_edges, g_b);
     }
     CT C[R];
-    cut_values<CT, JB>(P, W, geo.weighted, base, tid, C);
+    cut_values<CT, JB>(P, 0, W, geo.weighted, base, tid, C);
     __syncthreads();
-
     const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int m = tid + kQThreads * j;
+        const int m = tid + kLdsThreads * j;
         if (m < TS) {
             d2v v;
             if (first) {
@@ -223,14 +272,14 @@ __global__ __launch_bounds__(kQThreads) void k_qaoa_fwd(QPass Parg, QWeights W, 
                 v.x = amp0 * f.x;
                 v.y = amp0 * f.y;
             } else {
-                v = ld<true>(in + (base | qtile_off(P, (u64)m)));
+                v = in[base | qtile_off(P, (u64)m)];
             }
             sh[m] = v;
         }
     }
     __syncthreads();
     double sb, cb;
-    sincos(theta[p + l], &sb, &cb);  // RX(2 beta): cos(beta), sin(beta)
+    sincos(q.theta[p + l], &sb, &cb);
     for (int b = 0; b < P.tb; ++b) {
         if (!((P.rx_mask >> b) & 1)) continue;
         lds_rx(sh, TS, b, cb, sb);
@@ -239,76 +288,57 @@ __global__ __launch_bounds__(kQThreads) void k_qaoa_fwd(QPass Parg, QWeights W, 
     double e_acc = 0.0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int m = tid + kQThreads * j;
+        const int m = tid + kLdsThreads * j;
         if (m < TS) {
             d2v v = sh[m];
             if (pend) v = cmul2(v, Phase<CT>::get(tab_b, g_b, C[j]));
             if (last) e_acc += (double)C[j] * (v.x * v.x + v.y * v.y);
-            if (out) st<true>(out + (base | qtile_off(P, (u64)m)), v);
+            if (out) out[base | qtile_off(P, (u64)m)] = v;
         }
     }
     if (last) {
         const double t = qblock_sum(e_acc, red);
-        if (tid == 0) ((double *)(region + B.epart_off))[tile] = t;
+        if (tid == 0) ((double *)(q.region + B.epart_off))[q.tile] = t;
     }
 }
 
-// Backward pass: see the file comment.  partial[pidx][tile][3] = (Im<lam|C|psi>
-// at the end phase, sum_j Im<lam|X_j|psi>, Im<lam|C|phi_1> at the first pass's
-// start phase).  The checkpoint is read from in_off, lambda lives at lam_off.
-template <typename CT, int TB, bool POOLED>
-__global__ __launch_bounds__(kQThreads) void k_qaoa_bwd(QPass Parg, QWeights W, QGeom geo, QBatch B) {
-    constexpr int JB = TB - 8, R = 1 << JB;
-    __shared__ d2v shl[1 << TB], shp[1 << TB];
+template <typename CT, bool POOLED>
+__global__ __launch_bounds__(kLdsThreads) void k_qaoa_bwd_lds(QPass Parg, QWeights W, QGeom geo, QBatch B) {
+    constexpr int JB = 2, R = 4;
+    __shared__ d2v shl[1 << 10], shp[1 << 10];
     __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
-    __shared__ double red[kQThreads / 64];
-    const u64 c = blockIdx.x >> geo.glog, tile = blockIdx.x & ((1ull << geo.glog) - 1);
-    const QPass *Pp;
-    u64 cid;
-    if constexpr (POOLED) {
-        Pp = B.passes + ((B.c0 + c) / B.sets) * B.np + B.k;
-        cid = (u64)B.circ_map[B.c0 + c];
-    } else {
-        Pp = &Parg;
-        cid = c;
-    }
-    const QPass &P = *Pp;
-    char *region = B.ws + c * B.circ_bytes;
-    const d2v *ckpt = (const d2v *)(region + B.in_off);
-    d2v *lam = (d2v *)(region + B.lam_off);
-    double *partial = (double *)(region + B.part_off);
-    const double *theta = B.theta + cid * 2 * geo.p;
-    const int TS = 1 << P.tb;
-    const int tid = threadIdx.x;
-    const int l = P.layer, p = geo.p;
-    const u64 base = qtile_base(P, tile);
+    __shared__ double red[16];
+    const QCirc q = qcirc<POOLED>(Parg, geo, B);
+    const QPass &P = *q.P;
+    const d2v *ckpt = (const d2v *)(q.region + B.in_off);
+    d2v *lam = (d2v *)(q.region + B.lam_off);
+    double *partial = (double *)(q.region + B.part_off);
+    const int TS = 1 << P.tb, tid = threadIdx.x, l = P.layer, p = geo.p;
+    const u64 base = qtile_base(P, q.tile);
     const bool first = P.flags & QF_FIRST, pend = P.flags & QF_PHASE_END, last = P.flags & QF_LAST;
-    const double g_a = theta[l], g_b = pend ? theta[l + 1] : 0.0;
+    const double g_a = q.theta[l], g_b = pend ? q.theta[l + 1] : 0.0;
     if (!geo.weighted) {
         if (first) fill_table(tab_a, geo.num_edges, g_a);
-        if (pend) fill_table(tab_b, geo.num_edges, -g_b);  // exp(+i gamma C): undo the phase
+        if (pend) fill_table(tab_b, geo.num_edges, -g_b);
     }
     CT C[R];
-    cut_values<CT, JB>(P, W, geo.weighted, base, tid, C);
+    cut_values<CT, JB>(P, 0, W, geo.weighted, base, tid, C);
     __syncthreads();
-
     double ipc = 0.0, ipb = 0.0, ipc1 = 0.0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int m = tid + kQThreads * j;
+        const int m = tid + kLdsThreads * j;
         if (m < TS) {
             const u64 idx = base | qtile_off(P, (u64)m);
-            d2v ps = ld<true>(ckpt + idx);
-            d2v lm;
+            d2v ps = ckpt[idx], lm;
             if (last) {
                 lm.x = (double)C[j] * ps.x;
                 lm.y = (double)C[j] * ps.y;
             } else {
-                lm = ld<true>(lam + idx);
+                lm = lam[idx];
             }
             if (pend) {
-                // Im(conj(lam) psi) weighted by C, then undo exp(-i gamma C) on both.
-                ipc += (double)C[j] * (lm.x * ps.y - lm.y * ps.x);
+                ipc += (double)C[j] * im_conj_mul(lm, ps);
                 const d2v f = Phase<CT>::get(tab_b, -g_b, C[j]);
                 lm = cmul2(lm, f);
                 ps = cmul2(ps, f);
@@ -318,33 +348,34 @@ __global__ __launch_bounds__(kQThreads) void k_qaoa_bwd(QPass Parg, QWeights W, 
         }
     }
     __syncthreads();
-    for (int b = 0; b < P.tb; ++b) {
-        if (!((P.rx_mask >> b) & 1)) continue;
-        for (int k = tid; k < TS / 2; k += kQThreads) {
-            const int m0 = (int)insert0((u64)k, b), m1 = m0 | (1 << b);
-            const d2v l0 = shl[m0], l1 = shl[m1], p0 = shp[m0], p1 = shp[m1];
-            ipb += (l0.x * p1.y - l0.y * p1.x) + (l1.x * p0.y - l1.y * p0.x);
-        }
-    }
-    __syncthreads();  // all inner products read lambda before RX(-2 beta) rewrites it
     double sb, cb;
-    sincos(theta[p + l], &sb, &cb);
+    sincos(q.theta[p + l], &sb, &cb);
     for (int b = 0; b < P.tb; ++b) {
         if (!((P.rx_mask >> b) & 1)) continue;
-        lds_rx(shl, TS, b, cb, -sb);  // RX(-2 beta)
+        for (int k = tid; k < TS / 2; k += kLdsThreads) {
+            const int m0 = (int)insert0((u64)k, b), m1 = m0 | (1 << b);
+            d2v l0 = shl[m0], l1 = shl[m1], p0 = shp[m0], p1 = shp[m1];
+            ipb += im_conj_mul(l0, p1) + im_conj_mul(l1, p0);
+            rx_pair(l0, l1, cb, -sb);
+            rx_pair(p0, p1, cb, -sb);
+            shl[m0] = l0;
+            shl[m1] = l1;
+            shp[m0] = p0;
+            shp[m1] = p1;
+        }
         __syncthreads();
     }
     const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int m = tid + kQThreads * j;
+        const int m = tid + kLdsThreads * j;
         if (m < TS) {
             const d2v lm = shl[m];
             if (first) {
-                const d2v f = Phase<CT>::get(tab_a, g_a, C[j]);  // phi_1 = 2^{-n/2} exp(-i gamma_1 C)
+                const d2v f = Phase<CT>::get(tab_a, g_a, C[j]);
                 ipc1 += (double)C[j] * amp0 * (lm.x * f.y - lm.y * f.x);
             } else {
-                st<true>(lam + (base | qtile_off(P, (u64)m)), lm);
+                lam[base | qtile_off(P, (u64)m)] = lm;
             }
         }
     }
@@ -352,19 +383,320 @@ __global__ __launch_bounds__(kQThreads) void k_qaoa_bwd(QPass Parg, QWeights W, 
     const double tbx = qblock_sum(ipb, red);
     const double tc1 = qblock_sum(ipc1, red);
     if (tid == 0) {
-        double *o = partial + ((u64)P.pidx * geo.G + tile) * 3;
+        double *o = partial + ((u64)P.pidx * geo.G + q.tile) * 3;
         o[0] = tc;
         o[1] = tbx;
         o[2] = tc1;
     }
 }
 
+// ================================================================== register-tiled kernels (n >= 10)
+
+template <int TB, int TT> struct RT {
+    static constexpr int NT = 1 << TT, W = TT - 6, JB = TB - TT, R = 1 << JB, TS = 1 << TB;
+    static_assert(JB >= W, "the second layout needs a register bit per wave bit");
+    __device__ static int m0(int t, int j) { return t | (j << TT); }
+    __device__ static int m1(int t, int j) { return (t & 63) | ((j & ((1 << W) - 1)) << 6) | ((t >> 6) << TT) | ((j >> W) << (TT + W)); }
+    // tile bit of register bit x in layout L
+    __host__ __device__ static constexpr int reg_bit(int L, int x) { return L == 0 ? TT + x : (x < W ? 6 + x : TT + x); }
+};
+
+// Global offsets (relative to the tile base) of the thread's amplitudes in layout L.
+template <int TB, int TT, int L>
+__device__ __forceinline__ void rt_offsets(const QPass &P, int t, u64 (&off)[1 << (TB - TT)]) {
+    using G = RT<TB, TT>;
+    u64 ot = 0;
+    if (L == 0) {
+#pragma unroll
+        for (int b = 0; b < TT; ++b)
+            if ((t >> b) & 1) ot |= 1ull << P.T[b];
+    } else {
+#pragma unroll
+        for (int b = 0; b < 6; ++b)
+            if ((t >> b) & 1) ot |= 1ull << P.T[b];
+#pragma unroll
+        for (int w = 0; w < G::W; ++w)
+            if ((t >> (6 + w)) & 1) ot |= 1ull << P.T[TT + w];
+    }
+#pragma unroll
+    for (int j = 0; j < G::R; ++j) {
+        u64 o = ot;
+#pragma unroll
+        for (int x = 0; x < G::JB; ++x)
+            if ((j >> x) & 1) o |= 1ull << P.T[G::reg_bit(L, x)];
+        off[j] = o;
+    }
+}
+
+// LDS transpose of one register array between the layouts (ends with a barrier).
+template <int TB, int TT, int FROM>
+__device__ __forceinline__ void rt_transpose(d2v (&a)[1 << (TB - TT)], d2v *sh) {
+    using G = RT<TB, TT>;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < G::R; ++j) sh[FROM == 0 ? G::m0(t, j) : G::m1(t, j)] = a[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < G::R; ++j) a[j] = sh[FROM == 0 ? G::m1(t, j) : G::m0(t, j)];
+    __syncthreads();
+}
+
+template <typename CT, int TB, int TT, bool POOLED>
+__global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
+    using G = RT<TB, TT>;
+    constexpr int R = G::R, JB = G::JB, Wb = G::W;
+    __shared__ d2v sh[G::TS];
+    __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
+    __shared__ double red[16];
+    const QCirc q = qcirc<POOLED>(Parg, geo, B);
+    const QPass &P = *q.P;
+    const d2v *in = B.in_off >= 0 ? (const d2v *)(q.region + B.in_off) : nullptr;
+    d2v *out = B.out_off >= 0 ? (d2v *)(q.region + B.out_off) : nullptr;
+    const int t = threadIdx.x, l = P.layer, p = geo.p;
+    const u64 base = qtile_base(P, q.tile);
+    const bool first = P.flags & QF_FIRST, pend = P.flags & QF_PHASE_END, last = P.flags & QF_LAST;
+    const bool l1 = P.use_l1;
+    const double g_a = q.theta[l], g_b = pend ? q.theta[l + 1] : 0.0;
+    if (!geo.weighted) {
+        if (first) fill_table(tab_a, geo.num_edges, g_a);
+        if (pend) fill_table(tab_b, geo.num_edges, g_b);
+    }
+    CT C0[R], C1[R];
+    if (first) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, C0);
+    if (pend || last) cut_values<CT, JB>(P, l1 ? 1 : 0, W, geo.weighted, base, t, C1);
+    __syncthreads();
+    u64 off[R];
+    rt_offsets<TB, TT, 0>(P, t, off);
+    const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
+    d2v a[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (first) {
+            const d2v f = Phase<CT>::get(tab_a, g_a, C0[j]);
+            a[j].x = amp0 * f.x;
+            a[j].y = amp0 * f.y;
+        } else {
+            a[j] = ld<true>(in + (base | off[j]));
+        }
+    }
+    double sb, cb;
+    sincos(q.theta[p + l], &sb, &cb);  // RX(2 beta): cos(beta), sin(beta)
+    const u32 rx = P.rx_mask;
+    // Layout L0: register bits (tile bits TT..TB-1) and lane bits (0..5).
+#pragma unroll
+    for (int x = 0; x < JB; ++x) {
+        if ((rx >> (TT + x)) & 1) {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (!((j >> x) & 1)) rx_pair(a[j], a[j | (1 << x)], cb, sb);
+        }
+    }
+#pragma unroll
+    for (int lb = 0; lb < 6; ++lb) {
+        if ((rx >> lb) & 1) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) a[j] = rx_half(a[j], shfl_xor2(a[j], 1 << lb), cb, sb);
+        }
+    }
+    if (l1) {
+        // Layout L1: the wave bits 6..6+W-1 become register bits 0..W-1.
+        rt_transpose<TB, TT, 0>(a, sh);
+#pragma unroll
+        for (int x = 0; x < Wb; ++x) {
+            if ((rx >> (6 + x)) & 1) {
+#pragma unroll
+                for (int j = 0; j < R; ++j)
+                    if (!((j >> x) & 1)) rx_pair(a[j], a[j | (1 << x)], cb, sb);
+            }
+        }
+        rt_offsets<TB, TT, 1>(P, t, off);
+    }
+    double e_acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        d2v v = a[j];
+        if (pend) v = cmul2(v, Phase<CT>::get(tab_b, g_b, C1[j]));
+        if (last) e_acc += (double)C1[j] * (v.x * v.x + v.y * v.y);
+        if (out) st<true>(out + (base | off[j]), v);
+    }
+    if (last) {
+        const double s = qblock_sum(e_acc, red);
+        if (t == 0) ((double *)(q.region + B.epart_off))[q.tile] = s;
+    }
+}
+
+// Inner product and RX(-2 beta) on register bit x of both vectors.
+template <int R>
+__device__ __forceinline__ void bwd_reg(d2v (&lm)[R], d2v (&ps)[R], int x, double c, double s, double &ipb) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if ((j >> x) & 1) continue;
+        const int k = j | (1 << x);
+        ipb += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
+        rx_pair(lm[j], lm[k], c, s);
+        rx_pair(ps[j], ps[k], c, s);
+    }
+}
+
+template <typename CT, int TB, int TT, bool POOLED>
+__global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
+    using G = RT<TB, TT>;
+    constexpr int R = G::R, JB = G::JB, Wb = G::W;
+    __shared__ d2v sh[G::TS];
+    __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
+    __shared__ double red[16];
+    const QCirc q = qcirc<POOLED>(Parg, geo, B);
+    const QPass &P = *q.P;
+    const d2v *ckpt = (const d2v *)(q.region + B.in_off);
+    d2v *lam = (d2v *)(q.region + B.lam_off);
+    double *partial = (double *)(q.region + B.part_off);
+    const int t = threadIdx.x, l = P.layer, p = geo.p;
+    const u64 base = qtile_base(P, q.tile);
+    const bool first = P.flags & QF_FIRST, pend = P.flags & QF_PHASE_END, last = P.flags & QF_LAST;
+    const bool l1 = P.use_l1;
+    const double g_a = q.theta[l], g_b = pend ? q.theta[l + 1] : 0.0;
+    if (!geo.weighted) {
+        if (first) fill_table(tab_a, geo.num_edges, g_a);
+        if (pend) fill_table(tab_b, geo.num_edges, -g_b);  // exp(+i gamma C): undo the phase
+    }
+    // Order of work.  All inner products are taken before lambda is changed,
+    // with both vectors at the pass's end point, so psi needs no RX except on
+    // the wave bits that L0 reaches but L1 does not (B bits: tile bits
+    // TT..TT+W-1), which are undone on both vectors before the transpose; the
+    // inner products of the bits only L1 reaches (A bits: 6..6+W-1) are then
+    // taken at that common point.  Finally lambda alone gets RX(-2 beta) on
+    // the remaining bits and is stored from the layout it ends in.
+    d2v lm[R], ps[R];
+    double ipc = 0.0, ipb = 0.0, ipc1 = 0.0;
+    {
+        CT Cs[R];
+        if (last || pend) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, Cs);
+        __syncthreads();  // phase tables
+        u64 off[R];
+        rt_offsets<TB, TT, 0>(P, t, off);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            ps[j] = ld<true>(ckpt + (base | off[j]));
+            if (last) {
+                lm[j].x = (double)Cs[j] * ps[j].x;
+                lm[j].y = (double)Cs[j] * ps[j].y;
+            } else {
+                lm[j] = ld<true>(lam + (base | off[j]));
+            }
+            if (pend) {
+                // Im(conj(lam) psi) weighted by C, then undo exp(-i gamma C) on both.
+                ipc += (double)Cs[j] * im_conj_mul(lm[j], ps[j]);
+                const d2v f = Phase<CT>::get(tab_b, -g_b, Cs[j]);
+                lm[j] = cmul2(lm[j], f);
+                ps[j] = cmul2(ps[j], f);
+            }
+        }
+    }
+    double sb, cb;
+    sincos(q.theta[p + l], &sb, &cb);
+    const double sn = -sb;  // RX(-2 beta)
+    const u32 rx = P.rx_mask;
+    // Inner products in L0: register bits (tile TT..TB-1) and lane bits.
+#pragma unroll
+    for (int x = 0; x < JB; ++x) {
+        if ((rx >> G::reg_bit(0, x)) & 1) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if ((j >> x) & 1) continue;
+                const int k = j | (1 << x);
+                ipb += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int lb = 0; lb < 6; ++lb) {
+        if ((rx >> lb) & 1) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) ipb += im_conj_mul(lm[j], shfl_xor2(ps[j], 1 << lb));  // both lanes: both terms
+        }
+    }
+    if (l1) {
+        // Undo the B bits on both vectors, move both to L1, take the A-bit inner products.
+#pragma unroll
+        for (int x = 0; x < Wb; ++x) {
+            if ((rx >> (TT + x)) & 1) {
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    if ((j >> x) & 1) continue;
+                    const int k = j | (1 << x);
+                    rx_pair(lm[j], lm[k], cb, sn);
+                    rx_pair(ps[j], ps[k], cb, sn);
+                }
+            }
+        }
+        rt_transpose<TB, TT, 0>(lm, sh);
+        rt_transpose<TB, TT, 0>(ps, sh);
+#pragma unroll
+        for (int x = 0; x < Wb; ++x) {
+            if ((rx >> (6 + x)) & 1) {
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    if ((j >> x) & 1) continue;
+                    const int k = j | (1 << x);
+                    ipb += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
+                }
+            }
+        }
+    }
+    // psi is dead: RX(-2 beta) on lambda for every bit not yet undone.
+    const int L = l1 ? 1 : 0;
+#pragma unroll
+    for (int x = 0; x < JB; ++x) {
+        const int tbit = l1 ? G::reg_bit(1, x) : G::reg_bit(0, x);
+        if (l1 && x < Wb ? !((rx >> (6 + x)) & 1) : !((rx >> tbit) & 1)) continue;
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (!((j >> x) & 1)) rx_pair(lm[j], lm[j | (1 << x)], cb, sn);
+    }
+#pragma unroll
+    for (int lb = 0; lb < 6; ++lb) {
+        if ((rx >> lb) & 1) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) lm[j] = rx_half(lm[j], shfl_xor2(lm[j], 1 << lb), cb, sn);
+        }
+    }
+    const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
+    if (first) {
+        CT Cf[R];
+        cut_values<CT, JB>(P, L, W, geo.weighted, base, t, Cf);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const d2v f = Phase<CT>::get(tab_a, g_a, Cf[j]);  // phi_1 = 2^{-n/2} exp(-i gamma_1 C)
+            ipc1 += (double)Cf[j] * amp0 * (lm[j].x * f.y - lm[j].y * f.x);
+        }
+    } else {
+        u64 off[R];
+        if (l1)
+            rt_offsets<TB, TT, 1>(P, t, off);
+        else
+            rt_offsets<TB, TT, 0>(P, t, off);
+#pragma unroll
+        for (int j = 0; j < R; ++j) st<true>(lam + (base | off[j]), lm[j]);
+    }
+    const double tc = qblock_sum(ipc, red);
+    const double tbx = qblock_sum(ipb, red);
+    const double tc1 = qblock_sum(ipc1, red);
+    if (t == 0) {
+        double *o = partial + ((u64)P.pidx * geo.G + q.tile) * 3;
+        o[0] = tc;
+        o[1] = tbx;
+        o[2] = tc1;
+    }
+}
+
+// ================================================================== reduction of the partials
+
 // E and gradient of circuit blockIdx.y: one block per output, partials summed
 // in a fixed order.  Output k < 2p: gradient component; k = 2p: E.  Without a
 // gradient the grid has one block per circuit, which computes E.
 template <bool POOLED>
-__global__ __launch_bounds__(kQThreads) void k_qaoa_final(QGeom geo, QBatch B, double *__restrict__ E_out, double *__restrict__ grad_out, int with_grad) {
-    __shared__ double red[kQThreads / 64];
+__global__ __launch_bounds__(256) void k_qaoa_final(QGeom geo, QBatch B, double *__restrict__ E_out, double *__restrict__ grad_out, int with_grad) {
+    __shared__ double red[16];
     const int p = geo.p, P = geo.P, G = geo.G;
     const int k = with_grad ? (int)blockIdx.x : 2 * p;
     const u64 c = blockIdx.y;
@@ -374,17 +706,17 @@ __global__ __launch_bounds__(kQThreads) void k_qaoa_final(QGeom geo, QBatch B, d
     const double *e_partial = (const double *)(region + B.epart_off);
     double a = 0.0;
     if (k == 2 * p) {
-        for (int b = threadIdx.x; b < G; b += kQThreads) a += e_partial[b];
+        for (int b = threadIdx.x; b < G; b += blockDim.x) a += e_partial[b];
     } else if (k < p) {
         // gamma_{k+1}: phase at the start of pass 0 (k = 0, slot 2) or the end of pass (k-1, P-1) (slot 0).
         const int pidx = k == 0 ? 0 : (k - 1) * P + (P - 1);
         const int slot = k == 0 ? 2 : 0;
-        for (int b = threadIdx.x; b < G; b += kQThreads) a += partial[((u64)pidx * G + b) * 3 + slot];
+        for (int b = threadIdx.x; b < G; b += blockDim.x) a += partial[((u64)pidx * G + b) * 3 + slot];
     } else {
         const int l = k - p;
         for (int g = 0; g < P; ++g) {
             const int pidx = l * P + g;
-            for (int b = threadIdx.x; b < G; b += kQThreads) a += partial[((u64)pidx * G + b) * 3 + 1];
+            for (int b = threadIdx.x; b < G; b += blockDim.x) a += partial[((u64)pidx * G + b) * 3 + 1];
         }
     }
     const double t = qblock_sum(a, red);
@@ -396,11 +728,64 @@ __global__ __launch_bounds__(kQThreads) void k_qaoa_final(QGeom geo, QBatch B, d
     }
 }
 
-// ------------------------------------------------------------------ host planning
+// ================================================================== host planning
 
-int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double *w, int TB, QPlan &plan) {
-    const int tb = n < TB ? n : TB;
-    const int r = tb < 3 ? tb : 3;
+int qaoa_passes_per_layer(int n, QShape s) {
+    const int tb = n < s.TB ? n : s.TB;
+    if (n <= tb) return 1;
+    const int per = tb - s.r;
+    return 1 + (n - tb + per - 1) / per;
+}
+
+static int threads_bits_for(int TB) { return TB >= 12 ? 9 : 8; }
+
+QShape qaoa_default_shape(int n) {
+    static const int env_tb = [] {
+        const char *e = getenv("QSIM_QAOA_TB");
+        return e ? atoi(e) : 0;
+    }();
+    static const int env_r = [] {
+        const char *e = getenv("QSIM_QAOA_R");
+        return e ? atoi(e) : 0;
+    }();
+    if (n < 10) return QShape{n, 8, n < 3 ? n : 3};
+    if (env_tb >= 10 && env_tb <= 13) {
+        const int tb = env_tb < n ? env_tb : n;
+        return QShape{tb, threads_bits_for(tb), env_r == 2 || env_r == 3 ? env_r : 3};
+    }
+    // 13-qubit tiles would save a pass per layer for some n, but their backward
+    // kernel exceeds the register file (spills); they are not offered.
+    return QShape{n < 12 ? n : 12, threads_bits_for(n < 12 ? n : 12), 3};
+}
+
+std::vector<QShape> qaoa_candidate_shapes(int n) {
+    std::vector<QShape> v;
+    if (n < 10) return {qaoa_default_shape(n)};
+    for (QShape s : {QShape{10, 8, 3}, QShape{11, 8, 3}, QShape{12, 9, 3}, QShape{12, 9, 2}})
+        if (s.TB <= n) v.push_back(s);
+    return v;
+}
+
+// Tile bit b -> (is thread bit, index) in layout L of a (TB, TT) tile.
+static void layout_kind(int L, int TT, int b, bool &thread, int &idx) {
+    const int W = TT - 6;
+    if (L == 0) {
+        thread = b < TT;
+        idx = thread ? b : b - TT;
+        return;
+    }
+    if (b < 6) { thread = true; idx = b; }
+    else if (b < 6 + W) { thread = false; idx = b - 6; }
+    else if (b < TT + W) { thread = true; idx = 6 + (b - TT); }
+    else { thread = false; idx = b - TT; }
+}
+
+int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double *w, QShape shape, QPlan &plan) {
+    const bool rt = n >= 10;
+    if (!rt) shape = QShape{n, 8, n < 3 ? n : 3};
+    const int tb = n < shape.TB ? n : shape.TB;
+    if (rt) shape.TB = tb, shape.TT = threads_bits_for(tb);
+    const int r = shape.r < tb ? shape.r : tb;
     std::vector<std::vector<int>> groups;
     {
         std::vector<int> g0;
@@ -414,10 +799,12 @@ int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double 
         }
     }
     const int P = (int)groups.size();
-    plan.TB = TB;
+    plan.shape = shape;
+    plan.rt = rt;
     plan.geo = QGeom{n, p, P, tb, 1 << (n - tb), n - tb, num_edges, w != nullptr};
     for (int e = 0; e < num_edges; ++e) plan.W.w[e] = w ? w[e] : 1.0;
     plan.passes.clear();
+    const int TT = shape.TT, Wb = TT - 6;
     for (int l = 0; l < p; ++l) {
         for (int g = 0; g < P; ++g) {
             QPass Q{};
@@ -443,38 +830,38 @@ int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double 
             }
             Q.rx_mask = 0;
             for (int q : groups[g]) Q.rx_mask |= 1u << pos[q];
+            Q.use_l1 = rt && ((Q.rx_mask >> 6) & ((1u << Wb) - 1)) != 0;
             Q.layer = l;
             Q.pidx = l * P + g;
             Q.flags = 0;
             if (l == 0 && g == 0) Q.flags |= QF_FIRST;
             if (g == P - 1 && l < p - 1) Q.flags |= QF_PHASE_END;
             if (g == P - 1 && l == p - 1) Q.flags |= QF_LAST;
-            // Classify edges for the thread map m = tid + 256 j: tile bits 0..7
-            // are thread-index bits, higher tile bits register-index bits.
-            std::vector<QEdge> cls[EC_N];
-            for (int e = 0; e < num_edges; ++e) {
-                int u = edges[2 * e], v = edges[2 * e + 1];
-                int pu = pos[u], pv = pos[v];
-                auto kind = [](int ps) { return ps < 0 ? 2 : (ps < 8 ? 0 : 1); };  // 0 = t, 1 = j, 2 = r
-                int ku = kind(pu), kv = kind(pv);
-                if (ku > kv) {
-                    std::swap(u, v);
-                    std::swap(pu, pv);
-                    std::swap(ku, kv);
+            for (int L = 0; L < (rt ? 2 : 1); ++L) {
+                std::vector<QEdge> cls[EC_N];
+                for (int e = 0; e < num_edges; ++e) {
+                    int u = edges[2 * e], v = edges[2 * e + 1];
+                    // kind: 0 = thread bit, 1 = register bit, 2 = fixed per tile
+                    int ku = 2, kv = 2, iu = u, iv = v;
+                    bool th;
+                    if (pos[u] >= 0) { layout_kind(L, TT, pos[u], th, iu); ku = th ? 0 : 1; }
+                    if (pos[v] >= 0) { layout_kind(L, TT, pos[v], th, iv); kv = th ? 0 : 1; }
+                    if (ku > kv) {
+                        std::swap(ku, kv);
+                        std::swap(iu, iv);
+                    }
+                    QEdge x{};
+                    x.wi = (uint8_t)e;
+                    x.a = (uint8_t)iu;
+                    x.b = (uint8_t)iv;
+                    const int c = ku == 0 ? (kv == 0 ? EC_TT : kv == 2 ? EC_TR : EC_TJ) : ku == 1 ? (kv == 1 ? EC_JJ : EC_JR) : EC_RR;
+                    cls[c].push_back(x);
                 }
-                QEdge x{};
-                x.wi = (uint8_t)e;
-                if (ku == 0 && kv == 0) { x.a = pu; x.b = pv; cls[EC_TT].push_back(x); }
-                else if (ku == 0 && kv == 2) { x.a = pu; x.b = v; cls[EC_TR].push_back(x); }
-                else if (ku == 0 && kv == 1) { x.a = pu; x.b = pv - 8; cls[EC_TJ].push_back(x); }
-                else if (ku == 1 && kv == 1) { x.a = pu - 8; x.b = pv - 8; cls[EC_JJ].push_back(x); }
-                else if (ku == 1 && kv == 2) { x.a = pu - 8; x.b = v; cls[EC_JR].push_back(x); }
-                else { x.a = u; x.b = v; cls[EC_RR].push_back(x); }
-            }
-            int k = 0;
-            for (int c = 0; c < EC_N; ++c) {
-                Q.cnt[c] = (uint16_t)cls[c].size();
-                for (auto &x : cls[c]) Q.e[k++] = x;
+                int k = 0;
+                for (int c = 0; c < EC_N; ++c) {
+                    Q.cnt[L][c] = (uint16_t)cls[c].size();
+                    for (auto &x : cls[c]) Q.e[L][k++] = x;
+                }
             }
             plan.passes.push_back(Q);
         }
@@ -507,59 +894,73 @@ QLayout qaoa_layout(const QGeom &g, int with_grad) {
     return L;
 }
 
+// Kernel pair for one (weights, shape) choice.
+template <typename CT, int TB, int TT, bool POOLED> struct RtKernels {
+    static constexpr int threads = 1 << TT;
+    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B) {
+        hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED>), grid, dim3(threads), 0, st, P, W, g, B);
+    }
+    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B) {
+        hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED>), grid, dim3(threads), 0, st, P, W, g, B);
+    }
+};
+template <typename CT, bool POOLED> struct LdsKernels {
+    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B) {
+        hipLaunchKernelGGL((k_qaoa_fwd_lds<CT, POOLED>), grid, dim3(kLdsThreads), 0, st, P, W, g, B);
+    }
+    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B) {
+        hipLaunchKernelGGL((k_qaoa_bwd_lds<CT, POOLED>), grid, dim3(kLdsThreads), 0, st, P, W, g, B);
+    }
+};
+
 // Forward (+ backward + final) launches for nb circuits.  Single-graph mode
 // takes the pass descriptors by value from `passes`; pooled mode reads them
 // from B.passes on the device.
-template <typename CT, int TB, bool POOLED>
-static void launch_batch_t(const QGeom &g, const QPass *passes, const QWeights &W, QBatch B, int nb, double *E_out, double *grad_out,
-                           hipStream_t st) {
+template <typename K, bool POOLED>
+static void launch_seq(const QGeom &g, const QPass *passes, const QWeights &W, QBatch B, int nb, double *E_out, double *grad_out, hipStream_t st) {
     const QLayout L = qaoa_layout(g, grad_out != nullptr);
     const size_t sb = ((size_t)1 << g.n) * 16;
     const int np = g.p * g.P;
-    const dim3 grid((unsigned)((u64)nb << g.glog)), block(kQThreads);
+    const dim3 grid((unsigned)((u64)nb << g.glog));
     B.lam_off = L.lam;
     B.part_off = L.part;
     B.epart_off = L.epart;
-    const QPass dummy{};
+    static const QPass dummy{};
     auto pass = [&](int k) -> const QPass & { return POOLED ? dummy : passes[k]; };
     if (grad_out) {
         for (int k = 0; k < np; ++k) {
             B.k = k;
             B.in_off = k == 0 ? -1 : (long long)(L.ckpt + (size_t)(k - 1) * sb);
             B.out_off = (long long)(L.ckpt + (size_t)k * sb);
-            hipLaunchKernelGGL((k_qaoa_fwd<CT, TB, POOLED>), grid, block, 0, st, pass(k), W, g, B);
+            K::fwd(grid, st, pass(k), W, g, B);
         }
         for (int k = np - 1; k >= 0; --k) {
             B.k = k;
             B.in_off = (long long)(L.ckpt + (size_t)k * sb);
-            hipLaunchKernelGGL((k_qaoa_bwd<CT, TB, POOLED>), grid, block, 0, st, pass(k), W, g, B);
+            K::bwd(grid, st, pass(k), W, g, B);
         }
-        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(2 * g.p + 1, nb), block, 0, st, g, B, E_out, grad_out, 1);
+        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(2 * g.p + 1, nb), dim3(256), 0, st, g, B, E_out, grad_out, 1);
     } else {
         for (int k = 0; k < np; ++k) {
             B.k = k;
             B.in_off = k == 0 ? -1 : (long long)L.ckpt;
             B.out_off = k == np - 1 ? -1 : (long long)L.ckpt;
-            hipLaunchKernelGGL((k_qaoa_fwd<CT, TB, POOLED>), grid, block, 0, st, pass(k), W, g, B);
+            K::fwd(grid, st, pass(k), W, g, B);
         }
-        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(1, nb), block, 0, st, g, B, E_out, (double *)nullptr, 0);
+        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(1, nb), dim3(256), 0, st, g, B, E_out, (double *)nullptr, 0);
     }
 }
 
-template <bool POOLED>
-static int launch_any(int TB, const QGeom &g, const QPass *passes, const QWeights &W, const QBatch &B, int nb, double *E_out, double *grad_out,
-                      hipStream_t st) {
-    const bool w = g.weighted;
-    switch (TB) {
-    case 10: w ? launch_batch_t<double, 10, POOLED>(g, passes, W, B, nb, E_out, grad_out, st)
-               : launch_batch_t<int, 10, POOLED>(g, passes, W, B, nb, E_out, grad_out, st); break;
-    case 12: w ? launch_batch_t<double, 12, POOLED>(g, passes, W, B, nb, E_out, grad_out, st)
-               : launch_batch_t<int, 12, POOLED>(g, passes, W, B, nb, E_out, grad_out, st); break;
-    default: w ? launch_batch_t<double, 11, POOLED>(g, passes, W, B, nb, E_out, grad_out, st)
-               : launch_batch_t<int, 11, POOLED>(g, passes, W, B, nb, E_out, grad_out, st); break;
+template <typename CT, bool POOLED>
+static void launch_ct(const QPlan &plan, const QPass *passes, const QWeights &W, const QBatch &B, int nb, double *E_out, double *grad_out, hipStream_t st) {
+    const QGeom &g = plan.geo;
+    if (!plan.rt) return launch_seq<LdsKernels<CT, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
+    switch (plan.shape.TB) {
+    case 10: return launch_seq<RtKernels<CT, 10, 8, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
+    case 11: return launch_seq<RtKernels<CT, 11, 8, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
+    case 12: return launch_seq<RtKernels<CT, 12, 9, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
+    default: return launch_seq<RtKernels<CT, 13, 9, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
     }
-    QS_LAUNCH_CHECK("qaoa");
-    return QS_OK;
 }
 
 int launch_qaoa_batch(const QPlan &plan, const double *theta, int nb, double *E_out, double *grad_out, char *ws, size_t circ_bytes, hipStream_t st) {
@@ -567,23 +968,23 @@ int launch_qaoa_batch(const QPlan &plan, const double *theta, int nb, double *E_
     B.ws = ws;
     B.circ_bytes = circ_bytes;
     B.theta = theta;
-    return launch_any<false>(plan.TB, plan.geo, plan.passes.data(), plan.W, B, nb, E_out, grad_out, st);
+    if (plan.geo.weighted)
+        launch_ct<double, false>(plan, plan.passes.data(), plan.W, B, nb, E_out, grad_out, st);
+    else
+        launch_ct<int, false>(plan, plan.passes.data(), plan.W, B, nb, E_out, grad_out, st);
+    QS_LAUNCH_CHECK("qaoa");
+    return QS_OK;
 }
 
-int launch_qaoa_pooled(int TB, const QGeom &geo, const QBatch &B, int nb, double *E_out, double *grad_out, hipStream_t st) {
+int launch_qaoa_pooled(const QPlan &proto, const QBatch &B, int nb, double *E_out, double *grad_out, hipStream_t st) {
     static const QWeights unit = [] {
         QWeights w;
         for (int e = 0; e < kQMaxEdges; ++e) w.w[e] = 1.0;
         return w;
     }();
-    return launch_any<true>(TB, geo, nullptr, unit, B, nb, E_out, grad_out, st);
-}
-
-static int check_desc(const qs_qaoa_desc *d) {
-    if (!d) return fail(QS_ERR_ARG, "null QAOA descriptor");
-    if (d->n < 2 || d->n > QS_MAX_QUBITS_C128) return fail(QS_ERR_ARG, "QAOA n must be in [2, 34]");
-    if (d->p < 1 || d->p > 64) return fail(QS_ERR_ARG, "QAOA p must be in [1, 64]");
-    return check_edges(d->n, d->num_edges, d->edges);
+    launch_ct<int, true>(proto, nullptr, unit, B, nb, E_out, grad_out, st);
+    QS_LAUNCH_CHECK("qaoa_pool");
+    return QS_OK;
 }
 
 int check_edges(int n, int ne, const int32_t *edges) {
@@ -595,15 +996,11 @@ int check_edges(int n, int ne, const int32_t *edges) {
     return QS_OK;
 }
 
-// Tile bits for a single QAOA instance: QSIM_QAOA_TB overrides the default.
-int qaoa_default_tb(int n) {
-    static int env = [] {
-        const char *e = getenv("QSIM_QAOA_TB");
-        return e ? atoi(e) : 0;
-    }();
-    if (env == 10 || env == 11 || env == 12) return env;
-    (void)n;
-    return 11;
+static int check_desc(const qs_qaoa_desc *d) {
+    if (!d) return fail(QS_ERR_ARG, "null QAOA descriptor");
+    if (d->n < 2 || d->n > QS_MAX_QUBITS_C128) return fail(QS_ERR_ARG, "QAOA n must be in [2, 34]");
+    if (d->p < 1 || d->p > 64) return fail(QS_ERR_ARG, "QAOA p must be in [1, 64]");
+    return check_edges(d->n, d->num_edges, d->edges);
 }
 
 }  // namespace qs
@@ -615,7 +1012,7 @@ QS_API int qs_qaoa_workspace_bytes(const qs_qaoa_desc *d, int with_grad, size_t 
         if (int rc = check_desc(d)) return rc;
         if (!bytes) return fail(QS_ERR_ARG, "null output");
         QPlan plan;
-        build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_tb(d->n), plan);
+        build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_shape(d->n), plan);
         *bytes = qaoa_layout(plan.geo, with_grad).bytes;
         return QS_OK;
     } catch (...) {
@@ -629,7 +1026,7 @@ QS_API int qs_qaoa_run(const qs_qaoa_desc *d, const double *angles_dev, int B, d
         if (int rc = check_desc(d)) return rc;
         if (!angles_dev || !E_dev || !ws || B < 0) return fail(QS_ERR_ARG, "null angles, energies or workspace");
         QPlan plan;
-        build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_tb(d->n), plan);
+        build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_shape(d->n), plan);
         const size_t circ = qaoa_layout(plan.geo, grad_dev != nullptr).bytes;
         if (ws_bytes < circ) return fail(QS_ERR_SIZE, "QAOA workspace too small");
         // As many angle sets per launch as the workspace holds.

@@ -39,9 +39,11 @@ struct TGate {  // gate list on the device (kind, q0, q1, u)
     double u[8];
 };
 
-// frames[t * count + g] = (a | b << 32) before gate g; final[t] after all gates.
+// frames[t * count + g] = (a | b << 32) before gate g; final[t] after all gates;
+// nins[t] = number of insertions (0 for the noiseless run t = n_traj).
 __global__ void k_traj_frames(const TGate *__restrict__ gates, int count, int n_traj, u32 thr, u32 k0, u32 k1, uint64_t *__restrict__ frames,
-                              uint64_t *__restrict__ final_frame, int32_t *__restrict__ counts, uint32_t *__restrict__ log, int log_cap) {
+                              uint64_t *__restrict__ final_frame, int32_t *__restrict__ nins_ws, int32_t *__restrict__ counts,
+                              uint32_t *__restrict__ log, int log_cap) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t > n_traj) return;
     u32 a = 0, b = 0, slot = 0;
@@ -70,8 +72,15 @@ __global__ void k_traj_frames(const TGate *__restrict__ gates, int count, int n_
         }
     }
     final_frame[t] = (u64)a | ((u64)b << 32);
+    nins_ws[t] = nins;
     if (counts && !ideal) counts[t] = nins;
 }
+
+// A trajectory without insertions has exactly the noiseless state: only the
+// noisy trajectories and the noiseless run itself (t = n_traj) are simulated,
+// the others read the noiseless run's state and read-outs.
+__device__ __forceinline__ bool traj_simulated(const int32_t *nins, u64 t, int n_traj) { return t == (u64)n_traj || nins[t] > 0; }
+__device__ __forceinline__ u64 traj_rep(const int32_t *nins, u64 t, int n_traj) { return nins[t] > 0 ? t : (u64)n_traj; }
 
 // U' = P^dagger U P for P = X^xa Z^zb (row-major interleaved u[8]).
 __device__ __forceinline__ void conj_pauli(double *u, int xa, int zb) {
@@ -88,10 +97,12 @@ __device__ __forceinline__ void conj_pauli(double *u, int xa, int zb) {
 
 template <typename R, int TBMAX>
 __global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states, u64 N, int tiles_log2, DPass P, const DGate *__restrict__ gates,
-                                                      const uint64_t *__restrict__ frames, int count, int first_pass, u64 basis) {
+                                                      const uint64_t *__restrict__ frames, int count, int first_pass, u64 basis,
+                                                      const int32_t *__restrict__ nins, int n_traj) {
     __shared__ cx<R> sh[1 << TBMAX];
     const u64 tile = blockIdx.x & ((1ull << tiles_log2) - 1);
     const u64 t = blockIdx.x >> tiles_log2;
+    if (!traj_simulated(nins, t, n_traj)) return;  // whole block: shares the noiseless state
     cx<R> *psi = states + t * N;
     const u64 TS = 1ull << P.tb;
     const u64 base = pass_base(P, tile);
@@ -142,99 +153,122 @@ __device__ __forceinline__ double tblock_sum(double v, double *red) {
     return red[0] + red[1] + red[2] + red[3];
 }
 
-// Per-trajectory partial sums over one chunk of amplitudes:
-// [0, n): sum (-1)^{k_q} |psi_k|^2; [n, 2n): <X_q>_stored; 2n, 2n+1: <ideal|F psi> (re, im).
+// Per simulated trajectory and chunk of amplitudes: [0, n) = sum (-1)^{k_q}
+// |psi_k|^2 and (n, n+1) = <ideal|F psi> (re, im).  The chunk's index bits
+// below log2(256) are fixed per thread, the others per loop step, so each
+// <Z_q> needs one add per amplitude only for the q the loop varies.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_traj_obs(const cx<R> *__restrict__ states, int n, int chunk_log2, int chunks_log2,
-                                                     const uint64_t *__restrict__ final_frame, int ideal_index, double *__restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ states, int n, int chunk_log2, int chunks_log2,
+                                                    const uint64_t *__restrict__ final_frame, const int32_t *__restrict__ nins, int n_traj,
+                                                    double *__restrict__ partial) {
     __shared__ double red[kBlock / 64];
     const u64 N = 1ull << n;
     const u64 c = blockIdx.x & ((1ull << chunks_log2) - 1);
     const u64 t = blockIdx.x >> chunks_log2;
+    if (!traj_simulated(nins, t, n_traj)) return;
     const cx<R> *psi = states + t * N;
-    const cx<R> *ideal = states + (u64)ideal_index * N;
+    const cx<R> *ideal = states + (u64)n_traj * N;
     const u64 f = final_frame[t];
     const u32 fa = (u32)f, fb = (u32)(f >> 32);
-    double z[kTrajMaxQubits], x[kTrajMaxQubits], fre = 0.0, fim = 0.0;
+    double z[kTrajMaxQubits], fre = 0.0, fim = 0.0;
 #pragma unroll
-    for (int q = 0; q < kTrajMaxQubits; ++q) z[q] = x[q] = 0.0;
+    for (int q = 0; q < kTrajMaxQubits; ++q) z[q] = 0.0;
     const u64 lo = c << chunk_log2, hi = lo + (1ull << chunk_log2);
     for (u64 i = lo + threadIdx.x; i < hi; i += kBlock) {
         const cx<R> v = psi[i];
         const double p = (double)v.x * v.x + (double)v.y * v.y;
 #pragma unroll
-        for (int q = 0; q < kTrajMaxQubits; ++q) {
-            if (q < n) {
-                z[q] += ((i >> q) & 1) ? -p : p;
-                if (!((i >> q) & 1)) {
-                    const cx<R> w = psi[i | (1ull << q)];
-                    x[q] += 2.0 * ((double)v.x * w.x + (double)v.y * w.y);
-                }
-            }
-        }
+        for (int q = 0; q < kTrajMaxQubits; ++q) z[q] += ((i >> q) & 1) ? -p : p;
         const cx<R> id = ideal[i ^ fa];
         const double sgn = (__popcll(i & fb) & 1) ? -1.0 : 1.0;
         fre += sgn * ((double)id.x * v.x + (double)id.y * v.y);
         fim += sgn * ((double)id.x * v.y - (double)id.y * v.x);
     }
-    const int nv = 2 * n + 2;
+    const int nv = n + 2;
     double *out = partial + (u64)blockIdx.x * nv;
 #pragma unroll
     for (int q = 0; q < kTrajMaxQubits; ++q) {
-        if (q >= n) break;
-        const double tz = tblock_sum(z[q], red);
-        if (threadIdx.x == 0) out[q] = tz;
-        const double tx = tblock_sum(x[q], red);
-        if (threadIdx.x == 0) out[n + q] = tx;
+        const double s = tblock_sum(z[q], red);
+        if (threadIdx.x == 0 && q < n) out[q] = s;
     }
     const double tre = tblock_sum(fre, red);
     const double tim = tblock_sum(fim, red);
     if (threadIdx.x == 0) {
-        out[2 * n] = tre;
-        out[2 * n + 1] = tim;
+        out[n] = tre;
+        out[n + 1] = tim;
     }
 }
 
-// One thread per (trajectory, value): sum the chunk partials in order, undo the frame.
-__global__ void k_traj_final(const double *__restrict__ partial, int n, int chunks, int n_traj, const uint64_t *__restrict__ final_frame,
-                             double *__restrict__ z, double *__restrict__ x, double *__restrict__ fid) {
+// <X_q>_stored partials: block (t, q, chunk) sums 2 Re(conj(psi_i) psi_{i + 2^q})
+// over the chunk's pairs (i with bit q clear).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_traj_x(const cx<R> *__restrict__ states, int n, int chunk_log2, int chunks_log2,
+                                                   const int32_t *__restrict__ nins, int n_traj, double *__restrict__ partial) {
+    __shared__ double red[kBlock / 64];
+    const u64 N = 1ull << n;
+    const u64 c = blockIdx.x & ((1ull << chunks_log2) - 1);
+    const u64 rest = blockIdx.x >> chunks_log2;
+    const int q = (int)(rest % (u64)n);
+    const u64 t = rest / (u64)n;
+    if (!traj_simulated(nins, t, n_traj)) return;
+    const cx<R> *psi = states + t * N;
+    const u64 npairs = N >> 1, per = npairs >> chunks_log2;
+    double acc = 0.0;
+    for (u64 k = c * per + threadIdx.x; k < (c + 1) * per; k += kBlock) {
+        const u64 i = insert0(k, q);
+        const cx<R> a = psi[i], b = psi[i | (1ull << q)];
+        acc += 2.0 * ((double)a.x * b.x + (double)a.y * b.y);
+    }
+    const double s = tblock_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// One thread per (trajectory, value): sum the chunk partials of the
+// trajectory's representative in order, then undo the trajectory's frame.
+__global__ void k_traj_final(const double *__restrict__ pzf, const double *__restrict__ px, int n, int chunks, int n_traj,
+                             const uint64_t *__restrict__ final_frame, const int32_t *__restrict__ nins, double *__restrict__ z,
+                             double *__restrict__ x, double *__restrict__ fid) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nv = 2 * n + 2;
     const int per = n + n + 1;  // z values, x values, fidelity
     if (id >= n_traj * per) return;
     const int t = id / per, v = id % per;
+    const u64 rep = traj_rep(nins, t, n_traj);
     const u64 f = final_frame[t];
     const u32 a = (u32)f, b = (u32)(f >> 32);
-    const double *p = partial + (u64)t * chunks * nv;
-    if (v < 2 * n) {
+    const int nv = n + 2;
+    if (v < n) {
+        const double *p = pzf + rep * chunks * nv;
         double s = 0.0;
         for (int c = 0; c < chunks; ++c) s += p[(u64)c * nv + v];
-        if (v < n) {
-            if (z) z[(u64)t * n + v] = ((a >> v) & 1) ? -s : s;
-        } else {
-            const int q = v - n;
-            if (x) x[(u64)t * n + q] = ((b >> q) & 1) ? -s : s;
-        }
+        if (z) z[(u64)t * n + v] = ((a >> v) & 1) ? -s : s;
+    } else if (v < 2 * n) {
+        const int q = v - n;
+        const double *p = px + (rep * n + q) * chunks;
+        double s = 0.0;
+        for (int c = 0; c < chunks; ++c) s += p[c];
+        if (x) x[(u64)t * n + q] = ((b >> q) & 1) ? -s : s;
     } else {
+        const double *p = pzf + rep * chunks * nv;
         double re = 0.0, im = 0.0;
         for (int c = 0; c < chunks; ++c) {
-            re += p[(u64)c * nv + 2 * n];
-            im += p[(u64)c * nv + 2 * n + 1];
+            re += p[(u64)c * nv + n];
+            im += p[(u64)c * nv + n + 1];
         }
         if (fid) fid[t] = re * re + im * im;
     }
 }
 
-// p_mean(k) = (1/T) sum_t |psi_t(k xor a_t)|^2, trajectories summed in order.
+// p_mean(k) = (1/T) sum_t |psi_t(k xor a_t)|^2, trajectories summed in order
+// (a noiseless trajectory reads the noiseless run's state).
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restrict__ states, u64 N, int n_traj, const uint64_t *__restrict__ final_frame,
-                                                           double *__restrict__ out) {
+                                                           const int32_t *__restrict__ nins, double *__restrict__ out) {
     const u64 k = (u64)blockIdx.x * kBlock + threadIdx.x;
     if (k >= N) return;
     double s = 0.0;
     for (int t = 0; t < n_traj; ++t) {
         const u32 a = (u32)final_frame[t];
-        const cx<R> v = states[(u64)t * N + (k ^ a)];
+        const cx<R> v = states[traj_rep(nins, t, n_traj) * N + (k ^ a)];
         s += (double)v.x * v.x + (double)v.y * v.y;
     }
     out[k] = s / (double)n_traj;
@@ -243,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restri
 // ------------------------------------------------------------------ host side
 
 struct TrajLayout {
-    size_t states, frames, final_frame, partial, gates, dgates, total;
+    size_t states, frames, final_frame, nins, pzf, px, gates, dgates, total;
     int chunk_log2, chunks_log2;
 };
 
@@ -260,8 +294,12 @@ static TrajLayout traj_layout(int n, int dtype, int count, int n_traj) {
     off = align(off + (size_t)(n_traj + 1) * count * sizeof(uint64_t));
     L.final_frame = off;
     off = align(off + (size_t)(n_traj + 1) * sizeof(uint64_t));
-    L.partial = off;
-    off = align(off + (size_t)(n_traj + 1) * ((size_t)1 << L.chunks_log2) * (2 * n + 2) * sizeof(double));
+    L.nins = off;
+    off = align(off + (size_t)(n_traj + 1) * sizeof(int32_t));
+    L.pzf = off;
+    off = align(off + (size_t)(n_traj + 1) * ((size_t)1 << L.chunks_log2) * (n + 2) * sizeof(double));
+    L.px = off;
+    off = align(off + (size_t)(n_traj + 1) * n * ((size_t)1 << L.chunks_log2) * sizeof(double));
     L.gates = off;
     off = align(off + (size_t)count * sizeof(TGate));
     L.dgates = off;
@@ -286,8 +324,9 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     if (p >= 1.0) thr = 0xFFFFFFFFu;
     else if (p > 0.0) thr = (u32)floor(p * 4294967296.0);
     uint64_t *frames = (uint64_t *)(ws + L.frames), *final_frame = (uint64_t *)(ws + L.final_frame);
+    int32_t *nins = (int32_t *)(ws + L.nins);
     hipLaunchKernelGGL(k_traj_frames, dim3((n_traj + 1 + 63) / 64), dim3(64), 0, st, (const TGate *)(ws + L.gates), count, n_traj, thr,
-                       (u32)seed, (u32)(seed >> 32), frames, final_frame, out->counts, out->log, out->log ? out->log_cap : 0);
+                       (u32)seed, (u32)(seed >> 32), frames, final_frame, nins, out->counts, out->log, out->log ? out->log_cap : 0);
     QS_LAUNCH_CHECK("traj_frames");
     cx<R> *states = (cx<R> *)(ws + L.states);
     const int T1 = n_traj + 1;
@@ -296,24 +335,33 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
         const int tiles_log2 = P.nrest;
         const u64 blocks = (u64)T1 << tiles_log2;
         hipLaunchKernelGGL((k_traj_pass<R, TBMAX>), dim3((unsigned)blocks), dim3(kBlock), 0, st, states, N, tiles_log2, P, (const DGate *)(ws + L.dgates),
-                           (const uint64_t *)frames, count, first ? 1 : 0, basis);
+                           (const uint64_t *)frames, count, first ? 1 : 0, basis, (const int32_t *)nins, n_traj);
         QS_LAUNCH_CHECK("traj_pass");
         first = false;
     }
-    double *partial = (double *)(ws + L.partial);
-    if (out->z || out->x || out->fid) {
+    double *pzf = (double *)(ws + L.pzf), *px = (double *)(ws + L.px);
+    const int chunks = 1 << L.chunks_log2;
+    if (out->z || out->fid) {
         const u64 blocks = (u64)T1 << L.chunks_log2;
-        hipLaunchKernelGGL(k_traj_obs<R>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<R> *)states, n, L.chunk_log2, L.chunks_log2,
-                           (const uint64_t *)final_frame, n_traj, partial);
-        QS_LAUNCH_CHECK("traj_obs");
+        hipLaunchKernelGGL(k_traj_zf<R>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<R> *)states, n, L.chunk_log2, L.chunks_log2,
+                           (const uint64_t *)final_frame, (const int32_t *)nins, n_traj, pzf);
+        QS_LAUNCH_CHECK("traj_zf");
+    }
+    if (out->x) {
+        const u64 blocks = ((u64)T1 * n) << L.chunks_log2;
+        hipLaunchKernelGGL(k_traj_x<R>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<R> *)states, n, L.chunk_log2, L.chunks_log2,
+                           (const int32_t *)nins, n_traj, px);
+        QS_LAUNCH_CHECK("traj_x");
+    }
+    if (out->z || out->x || out->fid) {
         const int work = n_traj * (2 * n + 1);
-        hipLaunchKernelGGL(k_traj_final, dim3((work + 255) / 256), dim3(256), 0, st, (const double *)partial, n, 1 << L.chunks_log2, n_traj,
-                           (const uint64_t *)final_frame, out->z, out->x, out->fid);
+        hipLaunchKernelGGL(k_traj_final, dim3((work + 255) / 256), dim3(256), 0, st, (const double *)pzf, (const double *)px, n, chunks, n_traj,
+                           (const uint64_t *)final_frame, (const int32_t *)nins, out->z, out->x, out->fid);
         QS_LAUNCH_CHECK("traj_final");
     }
     if (out->prob_mean) {
         hipLaunchKernelGGL(k_traj_prob_mean<R>, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, (const cx<R> *)states, N, n_traj,
-                           (const uint64_t *)final_frame, out->prob_mean);
+                           (const uint64_t *)final_frame, (const int32_t *)nins, out->prob_mean);
         QS_LAUNCH_CHECK("traj_prob_mean");
     }
     return QS_OK;

@@ -99,9 +99,22 @@ def sweep_bench(n, steps, warmup):
     for kind, q, a, b in events:
         (per_1q if kind == "1q" else per_cx)[q].append(a.elapsed_time(b) * 1e-3)
     norm = s.norm2().item()
-    del s
+    # Reference: a plain device-to-device copy of the register (known size,
+    # also the scale for the HBM byte counters).
+    dst = torch.empty_like(s.amps)
+    copy_t = []
+    for _ in range(3):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dst.copy_(s.amps)
+        b.record(stream)
+        b.synchronize()
+        copy_t.append(a.elapsed_time(b) * 1e-3)
+    copy_gbs = 2 * (16 << n) / min(copy_t) / 1e9
+    del s, dst
     torch.cuda.empty_cache()
-    return wall, per_1q, per_cx, norm
+    return wall, per_1q, per_cx, norm, copy_gbs
 
 
 def _time_cuda(fn, reps):
@@ -192,16 +205,46 @@ def traj_bench():
     gates = W.qft_circuit(n)
     x0 = W.random_basis_index(n, 5)
     out = {"workload": "16-qubit QFT on a seeded basis state, depolarizing p=1e-3, 1024 trajectories"}
+    Ts = [1 << k for k in range(11)]
     for name, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
         t = _time_cuda(lambda: traj_run(n, gates, x0, T, p, seed=5, dtype=dt, prob_mean=True), 3)
         r = traj_run(n, gates, x0, T, p, seed=5, dtype=dt)
         fid = r["fid"].cpu().numpy()
-        curve = {str(k): float(fid[:k].mean()) for k in (1, 4, 16, 64, 256, 1024)}
         out[name] = {"trajectories_per_s": round(T / t, 1), "ms": round(t * 1e3, 3), "mean_fidelity": float(fid.mean()),
-                     "fidelity_mean_vs_T": curve, "max_abs_Z": float(r["z"].abs().max().item()),
+                     "max_abs_Z": float(r["z"].abs().max().item()),
                      "max_abs_p_minus_2^-16": float((r["prob_mean"] - 2.0 ** -n).abs().max().item()),
                      "insertions": int(r["counts"].sum().item())}
+    # Convergence of the trajectory means with T, over 8 independent seeds (c128).
+    curves_f, curves_x = [], []
+    for seed in range(5, 13):
+        r = traj_run(n, gates, x0, T, p, seed=seed, dtype=torch.complex128, prob_mean=False)
+        fid = r["fid"].cpu().numpy()
+        xm = r["x"].cpu().numpy().mean(axis=1)  # mean over qubits of <X_q>, per trajectory
+        curves_f.append([round(float(fid[:k].mean()), 6) for k in Ts])
+        curves_x.append([round(float(xm[:k].mean()), 6) for k in Ts])
+    out["convergence"] = {"T": Ts, "seeds": list(range(5, 13)), "mean_fidelity": curves_f, "mean_X": curves_x}
     return out
+
+
+def brick_bench():
+    """12-qubit complex128 brick circuit from |0>: 20 layers of Haar 1q gates on
+    every qubit and CZ on brick pairs (350 gates) as one fused block, then all
+    <Z_i>.  The register fits one 64 KiB tile, so the block is one launch."""
+    import torch
+
+    from paper_2001_10554_amd import workloads as W
+    from paper_2001_10554_amd.qsim import State
+    n = 12
+    gates = W.brick_circuit(n, 20, seed=1)
+    s = State(n, torch.complex128)
+
+    def run():
+        s.init_basis(0)
+        s.apply_block(gates)
+        s.expect_z_all()
+    t = _time_cuda(run, 20)
+    return {"workload": "12-qubit complex128 brick circuit, 20 layers, 350 gates, fused block + <Z_i>",
+            "us_per_circuit": round(t * 1e6, 1), "gates_per_s": round(len(gates) / t, 1)}
 
 
 def cpu_baseline(seconds):
@@ -224,9 +267,20 @@ def cpu_baseline(seconds):
         gates += 1
         q = (q + 1) % n
     bytes_moved = gates * 2 * (1 << n) * 16
-    return {"value": round(bytes_moved / spent / 1e9, 3), "unit": "GB/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{gates} one-qubit gates (targets cycling 0..{n-1}) on a {n}-qubit c128 register, "
-                      f"{spent:.1f} s of gate time"}
+    out = {"value": round(bytes_moved / spent / 1e9, 3), "unit": "GB/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"{gates} one-qubit gates (targets cycling 0..{n-1}) on a {n}-qubit c128 register, "
+                     f"{spent:.1f} s of gate time"}
+    # Oracle QAOA gradient evaluations/s on a smaller instance of the same family.
+    del psi
+    nq, p = 20, 8
+    edges = W.random_regular_graph(nq, 3, seed=3)
+    theta = W.qaoa_angles(p, seed=3)
+    t0 = time.perf_counter()
+    oracle.qaoa_grad(nq, edges, p, theta)
+    t_adj = time.perf_counter() - t0
+    out["qaoa"] = {"adjoint_grads_per_s": round(1.0 / t_adj, 3),
+                   "sample": f"oracle adjoint gradient, {nq}-qubit random 3-regular graph, p={p}, one evaluation"}
+    return out
 
 
 def main():
@@ -239,7 +293,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     n = args.n
-    wall, per_1q, per_cx, norm = sweep_bench(n, args.steps, args.warmup)
+    wall, per_1q, per_cx, norm, copy_gbs = sweep_bench(n, args.steps, args.warmup)
     bytes_1q = 2 * (1 << n) * 16
     t1q = sum(sum(v) for v in per_1q.values())
     launches_1q = sum(len(v) for v in per_1q.values())
@@ -279,6 +333,8 @@ def main():
         "per_qubit_1q_gbs": per_q,
         "per_qubit_cnot_gbs": per_c,
         "min_1q_frac": round(min(per_q.values()) / PEAK_HBM_GBS, 4),
+        "device_copy_gbs": round(copy_gbs, 1),
+        "value_over_device_copy": round(gbs / copy_gbs, 3),
         "norm_after": norm,
     }
     if not args.no_extra:
@@ -288,6 +344,8 @@ def main():
         out["pool"] = pool_bench()
         log("trajectories")
         out["traj"] = traj_bench()
+        log("brick circuit")
+        out["brick12"] = brick_bench()
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

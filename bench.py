@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -247,6 +248,118 @@ def brick_bench():
             "us_per_circuit": round(t * 1e6, 1), "gates_per_s": round(len(gates) / t, 1)}
 
 
+def pso_bench(G=300, R=16, rounds=32):
+    """Particle swarm over the pool, the paper's study shape: random 3-regular
+    graphs on 18 vertices, p = 4 (8 coordinates), one swarm of R particles per
+    graph, R * rounds = 512 evaluations per graph, eq. (4) with the paper's
+    constants.  The whole run (pool evaluations + swarm kernels) stays on the
+    device; the approximation ratio divides by the exact Max-Cut value."""
+    import numpy as np
+    import torch
+
+    from paper_2001_10554_amd import workloads as W
+    from paper_2001_10554_amd.qsim import Pool, Swarm, cut_max
+    n, p = 18, 4
+    graphs = [W.random_regular_graph(n, 3, seed=1000 + g) for g in range(G)]
+    sizes = [n] * G
+    t0 = time.perf_counter()
+    mx, _ = cut_max(graphs, sizes)
+    torch.cuda.synchronize()
+    t_cut = time.perf_counter() - t0
+    pool = Pool(graphs, sizes, R, p, grad=False, ws_circuits=G * R)
+    sw = Swarm(pool)
+    t0 = time.perf_counter()
+    sw.run(rounds, seed=1)  # plans, tunes and captures the pool on first use
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    t = _time_cuda(lambda: sw.run(rounds, seed=2), 2)
+    hist = sw.run(rounds, seed=3)
+    ratio = (hist / mx[None, :]).cpu().numpy()
+    evals = G * R * rounds
+    out = {"workload": f"particle swarm: {G} random 3-regular graphs, n={n}, p={p}, {R} particles x {rounds} rounds "
+                       f"(512 evaluations per graph), complex128",
+           "evaluations_per_s": round(evals / t, 1), "ms_per_round": round(t / rounds * 1e3, 3), "seconds_per_run": round(t, 4),
+           "first_run_s": round(t_setup, 2), "cut_max_ms_all_graphs": round(t_cut * 1e3, 2),
+           "mean_ratio_by_round": [round(float(x), 5) for x in ratio.mean(axis=1)],
+           "mean_ratio_at_512_evals": round(float(ratio[-1].mean()), 5), "std_ratio_at_512_evals": round(float(ratio[-1].std()), 5),
+           "max_ratio": float(ratio.max())}
+    del pool, sw
+    torch.cuda.empty_cache()
+    return out
+
+
+def noise_bench(T=1024):
+    """Noisy QAOA (the paper's convergence study shape): 16-qubit random
+    3-regular graph, p = 4; angles from a particle swarm on the device
+    (32 particles, 48 rounds) and, for the second panel, uniform random angles;
+    a noise gate of one gate time on every touched qubit after every gate,
+    T1 = 500, T2 = 250 gate times; <C> per trajectory as a diagonal read-out.
+    Convergence of the ensemble mean of <C> with the ensemble size for 8
+    random streams."""
+    import numpy as np
+    import torch
+
+    from paper_2001_10554_amd import workloads as W
+    from paper_2001_10554_amd.qsim import Pool, Swarm, cut_max, traj_run
+    n, p = 16, 4
+    edges = W.random_regular_graph(n, 3, seed=8)
+    e_exact = cut_max([edges], [n])[0].item()
+    pool = Pool([edges], [n], 32, p, grad=False, ws_circuits=32)
+    sw = Swarm(pool)
+    hist = sw.run(48, seed=8)
+    theta_pso = sw.gbest[0].cpu().numpy()
+    e_pso = float(hist[-1, 0].item())
+    k = np.arange(1 << n)
+    diag = torch.tensor(sum(((k >> u) ^ (k >> v)) & 1 for u, v in edges).astype(np.float64), device="cuda")
+    Ts = [1 << j for j in range(int(math.log2(T)) + 1)]
+    out = {"workload": f"noisy QAOA: 16 qubits, random 3-regular graph (seed 8), p={p}, noise gate of 1 gate time per touched "
+                       f"qubit after every gate, T1=500, T2=250, {T} trajectories, complex128",
+           "E_exact": e_exact}
+    for label, theta in (("pso_angles", theta_pso), ("random_angles", W.qaoa_angles(p, seed=9, hi=2 * math.pi))):
+        gates = W.with_noise_gates(W.qaoa_circuit(n, edges, p, theta), 1.0)
+        t = _time_cuda(lambda: traj_run(n, gates, 0, T, 0.0, 1, T1=500.0, T2=250.0, diag=diag, prob_mean=False), 2)
+        curves = []
+        for seed in range(1, 9):
+            r = traj_run(n, gates, 0, T, 0.0, seed, T1=500.0, T2=250.0, diag=diag, prob_mean=False)
+            c = r["diag"].cpu().numpy()
+            curves.append([round(float(c[:m].mean()), 5) for m in Ts])
+        ideal = traj_run(n, gates, 0, 1, 0.0, 1, diag=diag, prob_mean=False)  # no decay: the noiseless value
+        out[label] = {"gates": int(len(gates)), "trajectories_per_s": round(T / t, 1), "ms": round(t * 1e3, 3),
+                      "noiseless_C": round(float(ideal["diag"][0].item()), 6),
+                      "noisy_C_mean_8x1024": round(float(np.mean([cv[-1] for cv in curves])), 5),
+                      "convergence": {"T": Ts, "mean_C": curves}}
+    out["pso_angles"]["swarm_best_C"] = round(e_pso, 6)
+    del pool, sw
+    torch.cuda.empty_cache()
+    return out
+
+
+def kq_bench(n=30):
+    """Dense k-qubit gates (k = 1..5, random unitaries) and one Born
+    measurement on a 30-qubit complex128 register (16 GiB)."""
+    import numpy as np
+    import torch
+
+    from paper_2001_10554_amd.qsim import State
+    s = State(n).init_random(1)
+    state_bytes = (1 << n) * 16
+    out = {"workload": f"{n}-qubit complex128 register: dense k-qubit gate on qubits [n-1, 0, n/2, 5, 17][:k], one measurement"}
+    g = np.random.default_rng(0)
+    for k in range(1, 6):
+        a = g.standard_normal((1 << k, 1 << k)) + 1j * g.standard_normal((1 << k, 1 << k))
+        U, _ = np.linalg.qr(a)
+        qs = [n - 1, 0, n // 2, 5, 17][:k]
+        t = _time_cuda(lambda: s.apply_kq(qs, U), 3)
+        out[f"k{k}"] = {"ms": round(t * 1e3, 3), "GB_per_s": round(2 * state_bytes / t / 1e9, 1),
+                        "GFLOP_per_s": round((1 << n) * (1 << k) * 8 / t / 1e9, 1)}
+    t = _time_cuda(lambda: s.measure(n // 2, 7), 3)
+    # read the state for the two sums, then read the kept half and write all
+    out["measure"] = {"ms": round(t * 1e3, 3), "GB_per_s": round(2.5 * state_bytes / t / 1e9, 1)}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds):
     """Oracle (plain C, OpenMP element loops) applying the sweep's Haar gates to a
     smaller register until `seconds` of gate time have been spent."""
@@ -280,6 +393,26 @@ def cpu_baseline(seconds):
     t_adj = time.perf_counter() - t0
     out["qaoa"] = {"adjoint_grads_per_s": round(1.0 / t_adj, 3),
                    "sample": f"oracle adjoint gradient, {nq}-qubit random 3-regular graph, p={p}, one evaluation"}
+    # The other workloads, each on a small sample.
+    gates = W.brick_circuit(12, 20, seed=1)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        psi = oracle.init_basis(12, 0)
+        oracle.apply_gates(psi, gates)
+        oracle.expect_z_all(psi)
+    out["brick12"] = {"us_per_circuit": round((time.perf_counter() - t0) / 20 * 1e6, 1), "sample": "20 circuits"}
+    w = W.pool_workload(8, 1, 4, seed=4, n_choices=(14, 16, 18))
+    t0 = time.perf_counter()
+    for g in range(8):
+        oracle.qaoa_grad(w.n_qubits[g], w.graphs[g], 4, w.angles[g][0])
+    out["pool"] = {"circuits_per_s": round(8 / (time.perf_counter() - t0), 2),
+                   "sample": "8 pool circuits (E + adjoint gradient), n in {14,16,18}, p=4"}
+    qft = W.qft_circuit(16)
+    x0 = W.random_basis_index(16, 5)
+    t0 = time.perf_counter()
+    oracle.traj_ensemble(16, qft, x0, 16, 1e-3, seed=5)
+    out["traj"] = {"trajectories_per_s": round(16 / (time.perf_counter() - t0), 2),
+                   "sample": "16 trajectories of the 16-qubit QFT with read-outs (c128)"}
     return out
 
 
@@ -346,6 +479,12 @@ def main():
         out["traj"] = traj_bench()
         log("brick circuit")
         out["brick12"] = brick_bench()
+        log("particle swarm")
+        out["pso"] = pso_bench()
+        log("k-qubit gates and measurement")
+        out["kq"] = kq_bench()
+        log("noisy QAOA trajectories")
+        out["noise"] = noise_bench()
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

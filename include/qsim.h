@@ -73,6 +73,8 @@ typedef struct qs_gate {
 #define QS_G_C1Q 2   /* U on target q1 iff control q0 is |1> (controlled form, Software description) */
 #define QS_G_DIAG2 3 /* diagonal two-qubit phase, e.g. CZ or a controlled phase */
 #define QS_G_SWAP 4  /* exchange qubits q0 and q1 */
+#define QS_G_NOISE 5 /* stochastic noise gate on q0 for the duration u[0] (qs_traj_run_noise only; the
+                        noiseless reference run treats it as the identity) */
 
 /* ---------------------------------------------------------------- state */
 
@@ -128,13 +130,38 @@ int qs_apply_diag2(qs_state *s, int q0, int q1, const double d[8]);
 /* SWAP of qubits a != b. */
 int qs_apply_swap(qs_state *s, int a, int b);
 
+/* Dense k-qubit gate, 1 <= k <= 5 (the Software description's gate action
+ * generalised from eq. (3)'s pairs to groups of 2^k amplitudes): qubits is a
+ * host array of k distinct qubits; U_dev is DEVICE memory holding the
+ * 2^k x 2^k matrix row-major as interleaved (re, im) doubles, row = output,
+ * and bit m of a row/column index is the value of qubits[m].  For every
+ * group of indices that differ only in those bits the 2^k amplitudes are
+ * replaced by U times them (computed in FP64; rounded to float for c64).
+ * U_dev must be 16-byte aligned and stay valid until the stream has run the
+ * gate. */
+int qs_apply_kq(qs_state *s, const int32_t *qubits, int k, const double *U_dev);
+
+/* Projective measurement of qubit q onto a given outcome (0 or 1): amplitudes
+ * whose bit q differs become 0, the others are divided by sqrt(P), P = the sum
+ * of their |a_i|^2 before the call (FP64, fixed-order reduction).  If P = 0
+ * the whole state becomes 0.  prob_dev: device double receiving P, or NULL. */
+int qs_collapse(qs_state *s, int q, int outcome, double *prob_dev);
+
+/* Born-rule measurement of qubit q: u = u53(x0, x1) of Philox4x32-10(key =
+ * seed, counter = (q, 0, 6, 0)); the outcome is 1 iff u < P1 / (P0 + P1)
+ * (both sums in FP64), then the state collapses as in qs_collapse.  The
+ * decision stays on the device: outcome_dev (device int32) and prob_dev
+ * (device double, the outcome's probability) receive it, either may be NULL. */
+int qs_measure(qs_state *s, int q, uint64_t seed, int32_t *outcome_dev, double *prob_dev);
+
 /* Fused block: the same result as applying gates[0..count) one after the
  * other.  The library groups consecutive gates into passes whose targets fit
  * one on-chip tile and runs each pass as one read+write of the state.  Plans
  * are cached per gate list (content-keyed) in the handle; the first call with
  * a new list builds and uploads the plan synchronously, later calls with the
  * same list only launch kernels (so they may be captured in a hipGraph).
- * QS_ERR_ARG on an unknown kind or bad qubit. */
+ * QS_ERR_ARG on an unknown kind (QS_G_NOISE included: noise gates belong to
+ * trajectories) or a bad qubit. */
 int qs_apply_block(qs_state *s, const qs_gate *gates, int count);
 
 /* QAOA cost layer: amplitude k *= exp(-i gamma C(k)),
@@ -215,17 +242,81 @@ typedef struct qs_pool_desc {
     int num_graphs;
     int sets_per_graph;
     int p;                      /* layers, shared by all circuits */
-    const int32_t *n_qubits;    /* host [num_graphs], each in [2, 22] */
+    const int32_t *n_qubits;    /* host [num_graphs], each in [2, 26] */
     const int32_t *edge_offset; /* host [num_graphs + 1]: edges of graph g are [edge_offset[g], edge_offset[g+1]) */
     const int32_t *edges;       /* host [2 * edge_offset[num_graphs]] */
 } qs_pool_desc;
 
+/* Workspace for gradients of one graph's angle sets per launch:
+ * sets_per_graph times the bytes of one circuit of the largest size. */
 int qs_pool_workspace_bytes(const qs_pool_desc *d, size_t *bytes);
+
+/* Bytes one circuit of the largest size needs (with_grad = 0: forward only,
+ * one state; else per-pass checkpoints as well).  A workspace of m times this
+ * runs up to m circuits per launch; qs_pool_run accepts any size of at least
+ * one circuit. */
+int qs_pool_circuit_bytes(const qs_pool_desc *d, int with_grad, size_t *bytes);
 
 /* angles_dev: device [circuits * 2p]; E_dev: device [circuits];
  * grad_dev: device [circuits * 2p] or NULL.  Complex128. */
 int qs_pool_run(const qs_pool_desc *d, const double *angles_dev, double *E_dev, double *grad_dev,
                 void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- Max-Cut optimum and particle swarm */
+
+/* E_exact of each graph of a pool (Particle Swarm / QAOA section: the
+ * approximation ratio divides the best <C> by the exact Max-Cut value):
+ * max_dev[g] = max over all 2^n bipartitions k of C(k), summed in edge order
+ * (unit weights when w is NULL, else w[e] for edge e of the pool's edge
+ * list); argmax_dev[g] = the smallest k attaining it (NULL to skip).  Both
+ * device arrays of num_graphs entries.  n up to 34; the work is 2^(n-1)
+ * cut evaluations per graph (C(k) = C(complement of k)). */
+int qs_cut_max(const qs_pool_desc *d, const double *w, double *max_dev, uint64_t *argmax_dev, void *stream);
+
+/* Particle swarm over a pool (Particle Swarm / QAOA section, eq. (4)): graph
+ * g has its own swarm of R = sets_per_graph particles; particle k of graph g
+ * is pool circuit c = g R + k and its position is that circuit's angle
+ * vector (D = 2p coordinates).  All arrays are caller-owned device memory. */
+typedef struct qs_pso_swarm {
+    double *pos;       /* [G * R * D] positions (the pool's angle vectors) */
+    double *vel;       /* [G * R * D] velocities */
+    double *pbest;     /* [G * R * D] best position each particle has evaluated */
+    double *pbest_val; /* [G * R] <C> at pbest (-inf before the first round) */
+    double *gbest;     /* [G * D] best position of each swarm */
+    double *gbest_val; /* [G] */
+    double *E;         /* [G * R] <C> at the current positions */
+} qs_pso_swarm;
+
+typedef struct qs_pso_params {
+    double omega, phi_p, phi_g; /* the paper's study: 0.66, 1.6, 0.62 */
+    int attract;                /* +1: pulled toward the bests, v += phi r (best - theta)
+                                   (the standard form of the cited source); -1: the sign
+                                   as printed in eq. (4), v += phi r (theta - best) */
+} qs_pso_params;
+
+/* Positions and velocities uniform in [0, 2 pi): coordinate d of particle c
+ * takes Philox4x32-10(key = seed, counter = (c, d, 5, 0)) -> (x0..x3),
+ * position 2 pi u53(x0, x1), velocity 2 pi u53(x2, x3), u53(lo, hi) =
+ * ((hi << 32 | lo) >> 11) 2^-53.  Best values are set to -inf. */
+int qs_pso_init(const qs_pool_desc *d, uint64_t seed, const qs_pso_swarm *sw, void *stream);
+
+/* One round after the evaluations sw->E of the current positions: each
+ * personal best takes the current position on strict improvement, each
+ * swarm's global best the lowest-index particle with the largest personal
+ * best if that beats it strictly; history_dev (device [G] or NULL) receives
+ * gbest_val.  If move != 0 every particle then takes velocity eq. (4) with
+ * scalars r_p = u53(x0, x1), r_g = u53(x2, x3) of Philox4x32-10(key = seed,
+ * counter = (c, round, 4, 0)) and position theta + v. */
+int qs_pso_step(const qs_pool_desc *d, const qs_pso_params *prm, int round, int move, uint64_t seed,
+                const qs_pso_swarm *sw, double *history_dev, void *stream);
+
+/* A whole swarm run on the device: init, then `rounds` rounds of (pool
+ * forward evaluation of every particle, qs_pso_step with move = 1 except
+ * after the last round).  history_dev: device [rounds * G], row r = the
+ * global bests after round r.  ws: the pool workspace (qs_pool_workspace_bytes).
+ * No host synchronisation between rounds. */
+int qs_pso_run(const qs_pool_desc *d, const qs_pso_params *prm, int rounds, uint64_t seed, const qs_pso_swarm *sw,
+               double *history_dev, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------- noise trajectories */
 
@@ -244,6 +335,8 @@ typedef struct qs_traj_out {
     int32_t *counts;    /* device [n_traj]: insertions per trajectory, or NULL */
     uint32_t *log;      /* device [n_traj * log_cap]: (slot << 2 | pauli) records, or NULL */
     int log_cap;
+    const double *diag; /* device [2^n] diagonal observable d, or NULL */
+    double *diag_val;   /* device [n_traj]: per-trajectory sum_k d_k |a_k|^2 (needs diag), or NULL */
 } qs_traj_out;
 
 /* Device workspace for qs_traj_run: n_traj + 1 states (the extra one is the
@@ -258,6 +351,26 @@ int qs_traj_workspace_bytes(int n, int dtype, int count, int n_traj, size_t *byt
  * means and convergence curves are reductions of them. */
 int qs_traj_run(int n, int dtype, const qs_gate *gates, int count, uint64_t basis_index, int n_traj,
                 double p_depol, uint64_t seed, const qs_traj_out *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Noise models of a trajectory run. */
+typedef struct qs_noise {
+    double p_depol; /* Pauli insertion probability per touched qubit after each gate, as in qs_traj_run */
+    double T1, T2;  /* timescales of the QS_G_NOISE gates: 0 < T2 <= 2 T1, or INFINITY (no decay) */
+} qs_noise;
+
+/* qs_traj_run with stochastic noise gates as well (Pool of multiple states:
+ * noise by one-qubit rotations with random angles, T1/T2 timescales).  A
+ * QS_G_NOISE gate of duration d on qubit q applies R_X(a_x), R_Y(a_y), R_Z(a_z),
+ * R_P(a) = exp(-i a P / 2), with independent normal angles of variances d/T1,
+ * d/T1 and 2d/T2 - d/T1; averaged over trajectories this scales the qubit's
+ * Bloch vector by (e^{-d/T2}, e^{-d/T2}, e^{-d/T1}).  The normals come from
+ * Box-Muller on Philox4x32-10(key = seed, counter = (t, gate index, 7, w)),
+ * u1 = u53(x0, x1), u2 = u53(x2, x3), r = sqrt(-2 ln(1 - u1)): w = 0 gives
+ * a_x = r cos(2 pi u2) and a_y = r sin(2 pi u2) (scaled), w = 1 gives a_z from
+ * the cos branch.  Noise gates draw no insertion slots.  With noise gates
+ * every trajectory is simulated (none shares the noiseless state). */
+int qs_traj_run_noise(int n, int dtype, const qs_gate *gates, int count, uint64_t basis_index, int n_traj,
+                      const qs_noise *noise, uint64_t seed, const qs_traj_out *out, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -66,6 +66,10 @@ def lib():
             "ref_init_uniform": (None, [_c_cplx_p, c_int]),
             "ref_init_random": (None, [_c_cplx_p, c_int, c_u64]),
             "ref_cut_value": (c_double, [c_u64, c_int, _c_i32_p, vp]),
+            "ref_cut_max": (c_double, [c_int, c_int, _c_i32_p, vp, _c_u64_p]),
+            "ref_apply_kq": (c_int, [_c_cplx_p, c_int, _c_i32_p, c_int, _c_f64_p]),
+            "ref_collapse": (c_double, [_c_cplx_p, c_int, c_int, c_int]),
+            "ref_measure": (c_int, [_c_cplx_p, c_int, c_int, c_u64, _c_f64_p]),
             "ref_apply_cut_phase": (None, [_c_cplx_p, c_int, c_int, _c_i32_p, vp, c_double]),
             "ref_norm2": (c_double, [_c_cplx_p, c_int]),
             "ref_prob_one": (c_double, [_c_cplx_p, c_int, c_int]),
@@ -80,7 +84,7 @@ def lib():
             "ref_qaoa_grad": (c_double, [c_int, c_int, _c_i32_p, vp, c_int, _c_f64_p, _c_f64_p]),
             "ref_qaoa_grad_fd": (None, [c_int, c_int, _c_i32_p, vp, c_int, _c_f64_p, c_double, _c_f64_p]),
             "ref_depol_threshold": (c_u32, [c_double]),
-            "ref_traj_run_one": (c_int, [_c_cplx_p, c_int, vp, c_int, c_double, c_u64, c_u32, vp, c_int]),
+            "ref_traj_run_one": (c_int, [_c_cplx_p, c_int, vp, c_int, c_double, c_u64, c_u32, vp, c_int, c_double, c_double]),
             "ref_threads": (c_int, []),
         }
         for name, (res, args) in sig.items():
@@ -170,6 +174,26 @@ def apply_swap(psi, a, b):
     lib().ref_apply_swap(psi, _nq(psi), a, b)
 
 
+def apply_kq(psi, qubits, m):
+    """k-qubit matrix m (2^k x 2^k, row = output); bit j of its index is qubits[j]."""
+    qs = np.ascontiguousarray(qubits, dtype=np.int32)
+    m = np.asarray(m, dtype=np.complex128)
+    u = np.empty(2 * m.size)
+    u[0::2], u[1::2] = m.real.reshape(-1), m.imag.reshape(-1)
+    if lib().ref_apply_kq(psi, _nq(psi), qs, len(qs), u) != 0:
+        raise ValueError("k must be in [1, 5]")
+
+
+def collapse(psi, q, outcome) -> float:
+    return lib().ref_collapse(psi, _nq(psi), q, int(outcome))
+
+
+def measure(psi, q, seed):
+    prob = np.zeros(1)
+    out = lib().ref_measure(psi, _nq(psi), q, seed, prob)
+    return int(out), float(prob[0])
+
+
 def apply_gates(psi, gates: np.ndarray):
     g = np.ascontiguousarray(gates)
     rc = lib().ref_apply_gates(psi, _nq(psi), g.ctypes.data_as(ctypes.c_void_p), len(g))
@@ -203,6 +227,15 @@ def cut_value(k: int, edges, w=None) -> float:
     e = _edges(edges)
     warr, wp = _w(w)
     return lib().ref_cut_value(k, len(e), e, wp)
+
+
+def cut_max(n: int, edges, w=None):
+    """(E_exact, smallest maximiser): the Max-Cut optimum by enumeration."""
+    e = _edges(edges)
+    warr, wp = _w(w)
+    arg = np.zeros(1, dtype=np.uint64)
+    best = lib().ref_cut_max(n, len(e), e, wp, arg)
+    return best, int(arg[0])
 
 
 def expect_cut(psi, edges, w=None) -> float:
@@ -268,11 +301,15 @@ def qaoa_grad_fd(n, edges, p, theta, h=1e-6, w=None):
 
 
 # ---------------------------------------------------------------- trajectories
-def traj_run_one(psi, gates, p, seed, t, log_cap=64):
+def _inv(T):
+    return 0.0 if T is None or not np.isfinite(T) else 1.0 / T
+
+
+def traj_run_one(psi, gates, p, seed, t, log_cap=64, T1=None, T2=None):
     g = np.ascontiguousarray(gates)
     log = np.zeros(max(log_cap, 1), dtype=np.uint32)
     nins = lib().ref_traj_run_one(psi, _nq(psi), g.ctypes.data_as(ctypes.c_void_p), len(g), p, seed, t,
-                                  log.ctypes.data_as(ctypes.c_void_p), log_cap)
+                                  log.ctypes.data_as(ctypes.c_void_p), log_cap, _inv(T1), _inv(T2))
     return nins, log[:min(nins, log_cap)].copy()
 
 
@@ -281,7 +318,7 @@ def expect_x_all(psi) -> np.ndarray:
     return np.array([expect_pauli(psi, 1 << q, 0).real for q in range(n)])
 
 
-def traj_ensemble(n, gates, basis_index, n_traj, p, seed, log_cap=64, ideal=None):
+def traj_ensemble(n, gates, basis_index, n_traj, p, seed, log_cap=64, ideal=None, T1=None, T2=None, diag=None):
     """Per-trajectory read-outs of the noisy circuit on |basis_index>:
     <Z_i>, <X_i>, fidelity |<ideal|psi_t>|^2, insertion counts and logs, and
     the trajectory-mean computational-basis probabilities."""
@@ -294,13 +331,121 @@ def traj_ensemble(n, gates, basis_index, n_traj, p, seed, log_cap=64, ideal=None
     counts = np.zeros(n_traj, dtype=np.int64)
     logs = []
     prob_sum = np.zeros(1 << n)
+    dval = np.zeros(n_traj)
     for t in range(n_traj):
         psi = init_basis(n, basis_index)
-        nins, log = traj_run_one(psi, gates, p, seed, t, log_cap)
+        nins, log = traj_run_one(psi, gates, p, seed, t, log_cap, T1, T2)
+        if diag is not None:
+            dval[t] = expect_diag(psi, diag)
         counts[t] = nins
         logs.append(log)
         z[t] = expect_z_all(psi)
         x[t] = expect_x_all(psi)
         fid[t] = abs(inner(ideal, psi)) ** 2
         prob_sum += np.abs(psi) ** 2
-    return dict(z=z, x=x, fid=fid, counts=counts, logs=logs, prob_mean=prob_sum / n_traj)
+    return dict(z=z, x=x, fid=fid, counts=counts, logs=logs, prob_mean=prob_sum / n_traj, diag=dval)
+
+
+# ---------------------------------------------------------------- particle swarm
+# Sec. "Particle Swarm / QAOA Simulation": each particle is one virtual
+# device evaluating L(theta) = <C> at its position theta (2p angles); every
+# graph has its own swarm of R particles.  Positions and velocities start
+# uniform in [0, 2 pi); after each round of evaluations the personal and
+# global bests are updated and the velocity follows eq. (4), then the
+# particle moves by its velocity.
+#
+# Readings where the paper is silent or at odds with itself:
+# * eq. (4) as printed pulls along (theta_k - best); the standard form of its
+#   cited source pulls toward the best, (best - theta_k).  `attract = +1`
+#   (default) takes the standard form, `attract = -1` the printed one.
+# * r_p and r_g are scalars per particle and round (as written), not
+#   per-coordinate draws.
+# * bests maximise <C> (the largest eigenvalue of the cut observable is
+#   sought); a personal or global best moves only on strict improvement,
+#   the global best to the lowest-index particle among equal maxima.
+# * positions are not wrapped into [0, 2 pi).
+# Draws: Philox4x32-10 with key = seed and counter (c, d, 5, 0) for the
+# initial position / velocity of coordinate d of particle c = g R + k
+# (position 2 pi u53(x0, x1), velocity 2 pi u53(x2, x3)); counter
+# (c, round, 4, 0) for r_p = u53(x0, x1) and r_g = u53(x2, x3).
+TAG_PSO, TAG_PSO_INIT = 4, 5
+TWO_PI = 2.0 * np.pi
+PSO_PAPER = dict(omega=0.66, phi_p=1.6, phi_g=0.62)
+
+
+def _u53(lo, hi) -> float:
+    return float(((int(hi) << 32) | int(lo)) >> 11) * 2.0 ** -53
+
+
+def _draw(seed: int, w0: int, w1: int, tag: int) -> np.ndarray:
+    return philox4x32_10([w0, w1, tag, 0], [seed & 0xFFFFFFFF, seed >> 32])
+
+
+def pso_init(G: int, R: int, D: int, seed: int):
+    """Swarm state dict: pos, vel, pbest [G, R, D]; pbest_val [G, R];
+    gbest [G, D]; gbest_val [G] (values -inf before the first round)."""
+    pos = np.empty((G, R, D))
+    vel = np.empty((G, R, D))
+    for g in range(G):
+        for k in range(R):
+            for d in range(D):
+                x = _draw(seed, g * R + k, d, TAG_PSO_INIT)
+                pos[g, k, d] = TWO_PI * _u53(x[0], x[1])
+                vel[g, k, d] = TWO_PI * _u53(x[2], x[3])
+    return dict(pos=pos, vel=vel, pbest=pos.copy(), pbest_val=np.full((G, R), -np.inf),
+                gbest=np.zeros((G, D)), gbest_val=np.full(G, -np.inf))
+
+
+def pso_update_bests(sw, E):
+    """Fold one round of evaluations E [G, R] into the personal and global bests."""
+    G, R = E.shape
+    for g in range(G):
+        for k in range(R):
+            if E[g, k] > sw["pbest_val"][g, k]:
+                sw["pbest_val"][g, k] = E[g, k]
+                sw["pbest"][g, k] = sw["pos"][g, k]
+        for k in range(R):
+            if sw["pbest_val"][g, k] > sw["gbest_val"][g]:
+                sw["gbest_val"][g] = sw["pbest_val"][g, k]
+                sw["gbest"][g] = sw["pbest"][g, k]
+
+
+def pso_move(sw, rnd: int, seed: int, omega=0.66, phi_p=1.6, phi_g=0.62, attract=1):
+    """Eq. (4) for every particle, then theta <- theta + v."""
+    G, R, D = sw["pos"].shape
+    for g in range(G):
+        for k in range(R):
+            x = _draw(seed, g * R + k, rnd, TAG_PSO)
+            rp, rg = _u53(x[0], x[1]), _u53(x[2], x[3])
+            th = sw["pos"][g, k]
+            to_p = (sw["pbest"][g, k] - th) * attract
+            to_g = (sw["gbest"][g] - th) * attract
+            sw["vel"][g, k] = omega * sw["vel"][g, k] + phi_p * rp * to_p + phi_g * rg * to_g
+            sw["pos"][g, k] = th + sw["vel"][g, k]
+
+
+def pso_run(objective, G: int, R: int, D: int, rounds: int, seed: int, attract=1, **params):
+    """`rounds` rounds of evaluation (the first at the initial positions);
+    the swarm moves between rounds.  objective(pos [G, R, D]) -> E [G, R].
+    Returns (swarm, history [rounds, G] of the global best after each round,
+    evaluations [rounds, G, R])."""
+    prm = dict(PSO_PAPER, **params)
+    sw = pso_init(G, R, D, seed)
+    hist = np.zeros((rounds, G))
+    evals = np.zeros((rounds, G, R))
+    for r in range(rounds):
+        E = np.asarray(objective(sw["pos"]), dtype=np.float64).reshape(G, R)
+        evals[r] = E
+        pso_update_bests(sw, E)
+        hist[r] = sw["gbest_val"]
+        if r + 1 < rounds:
+            pso_move(sw, r, seed, attract=attract, **prm)
+    return sw, hist, evals
+
+
+def qaoa_objective(graphs, n_qubits, p: int):
+    """<C> of the QAOA circuit of graph g at each particle's angles."""
+    def f(pos):
+        G, R, _ = pos.shape
+        return np.array([[qaoa_energy(int(n_qubits[g]), graphs[g], p, pos[g, k]) for k in range(R)] for g in range(G)])
+    return f

@@ -59,13 +59,18 @@ EXPORT void ref_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2]
 
 /* Stream tags in counter word 2, so independent uses of one seed never share
  * counters. */
-enum { TAG_INIT_RANDOM = 1, TAG_SAMPLE = 2, TAG_TRAJ = 3 };
+enum { TAG_INIT_RANDOM = 1, TAG_SAMPLE = 2, TAG_TRAJ = 3, TAG_MEASURE = 6, TAG_NOISE = 7 };
+
+static void philox_draw_w3(uint64_t seed, uint32_t w0, uint32_t w1, uint32_t tag, uint32_t w3, uint32_t out[4])
+{
+    uint32_t ctr[4] = {w0, w1, tag, w3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    ref_philox4x32_10(ctr, key, out);
+}
 
 static void philox_draw(uint64_t seed, uint32_t w0, uint32_t w1, uint32_t tag, uint32_t out[4])
 {
-    uint32_t ctr[4] = {w0, w1, tag, 0u};
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    ref_philox4x32_10(ctr, key, out);
+    philox_draw_w3(seed, w0, w1, tag, 0u, out);
 }
 
 /* 53-bit uniform in [0,1) from two 32-bit words (lo, hi). */
@@ -139,10 +144,41 @@ EXPORT void ref_apply_swap(cplx *psi, int n, int a, int b)
     }
 }
 
+/* k-qubit gate (1 <= k <= 5): U is 2^k x 2^k, row-major interleaved (re, im),
+ * row = output; bit m of a matrix index is the value of qubit qs[m].  For
+ * every index i with all k target bits clear, the 2^k amplitudes
+ * a_{i + off(j)}, off(j) = sum_m j_m 2^{qs[m]}, are replaced by U times them
+ * (the two-qubit case of the Software description's gates, generalised). */
+EXPORT int ref_apply_kq(cplx *psi, int n, const int32_t *qs, int k, const double *u)
+{
+    if (k < 1 || k > 5) return -1;
+    const int K = 1 << k;
+    uint64_t mask = 0, off[32];
+    for (int m = 0; m < k; ++m) mask |= 1ull << qs[m];
+    for (int j = 0; j < K; ++j) {
+        off[j] = 0;
+        for (int m = 0; m < k; ++m)
+            if ((j >> m) & 1) off[j] |= 1ull << qs[m];
+    }
+    const uint64_t N = 1ull << n;
+#pragma omp parallel for schedule(static)
+    for (uint64_t i = 0; i < N; ++i) {
+        if (i & mask) continue;
+        cplx in[32];
+        for (int j = 0; j < K; ++j) in[j] = psi[i + off[j]];
+        for (int r = 0; r < K; ++r) {
+            cplx acc = 0;
+            for (int j = 0; j < K; ++j) acc += (u[2 * (r * K + j)] + I * u[2 * (r * K + j) + 1]) * in[j];
+            psi[i + off[r]] = acc;
+        }
+    }
+    return 0;
+}
+
 /* Gate-list record, laid out as the workload module's structured dtype:
  * int32 kind, q0, q1, pad; double u[8]. */
 typedef struct { int32_t kind, q0, q1, pad; double u[8]; } ref_gate;
-enum { RG_1Q = 1, RG_C1Q = 2, RG_DIAG2 = 3, RG_SWAP = 4 };
+enum { RG_1Q = 1, RG_C1Q = 2, RG_DIAG2 = 3, RG_SWAP = 4, RG_NOISE = 5 };
 
 static void apply_gate(cplx *psi, int n, const ref_gate *g)
 {
@@ -159,7 +195,8 @@ static void apply_gate(cplx *psi, int n, const ref_gate *g)
 EXPORT int ref_apply_gates(cplx *psi, int n, const ref_gate *g, int count)
 {
     for (int k = 0; k < count; ++k) {
-        if (g[k].kind < RG_1Q || g[k].kind > RG_SWAP) return -1;
+        if (g[k].kind < RG_1Q || g[k].kind > RG_NOISE) return -1;
+        if (g[k].kind == RG_NOISE) continue;  /* the noiseless circuit: noise gates are the identity */
         apply_gate(psi, n, &g[k]);
     }
     return 0;
@@ -223,6 +260,32 @@ EXPORT double ref_cut_value(uint64_t k, int E, const int32_t *edges, const doubl
     return cut_value(k, E, edges, w);
 }
 
+/* E_exact = max over all 2^n bipartitions k of C(k), by enumeration; the
+ * smallest k attaining it goes to *argmax.  The approximation ratio of the
+ * swarm study divides the best <C> by this value. */
+EXPORT double ref_cut_max(int n, int E, const int32_t *edges, const double *w, uint64_t *argmax)
+{
+    const uint64_t N = 1ull << n;
+    double best = -INFINITY;
+    uint64_t arg = 0;
+#pragma omp parallel
+    {
+        double tb = -INFINITY;
+        uint64_t ta = 0;
+#pragma omp for schedule(static)
+        for (uint64_t k = 0; k < N; ++k) {
+            const double c = cut_value(k, E, edges, w);
+            if (c > tb) { tb = c; ta = k; }
+        }
+#pragma omp critical
+        {
+            if (tb > best || (tb == best && ta < arg)) { best = tb; arg = ta; }
+        }
+    }
+    if (argmax) *argmax = arg;
+    return best;
+}
+
 /* a_k <- exp(-i gamma C(k)) a_k: the QAOA cost layer, diagonal in the
  * computational basis. */
 EXPORT void ref_apply_cut_phase(cplx *psi, int n, int E, const int32_t *edges, const double *w, double gamma)
@@ -258,6 +321,40 @@ EXPORT double ref_prob_one(const cplx *psi, int n, int q)
 
 /* <Z_q> = P(0) - P(1) = 1 - 2 P(1) for a normalised state; written as the
  * plain sum of (-1)^{i_q} |a_i|^2 so it holds for any norm. */
+/* Projective measurement of qubit q with a given outcome: P = sum of |a_i|^2
+ * over i with bit q = outcome; amplitudes with the other bit value become 0,
+ * the rest are divided by sqrt(P) (all become 0 if P = 0).  Returns P. */
+EXPORT double ref_collapse(cplx *psi, int n, int q, int outcome)
+{
+    const uint64_t N = 1ull << n, s = 1ull << q, want = outcome ? s : 0;
+    ldbl p = 0;
+    for (uint64_t i = 0; i < N; ++i)
+        if ((i & s) == want) p += (ldbl)creal(psi[i]) * creal(psi[i]) + (ldbl)cimag(psi[i]) * cimag(psi[i]);
+    const double scale = p > 0 ? (double)(1.0L / sqrtl(p)) : 0.0;
+    for (uint64_t i = 0; i < N; ++i) psi[i] = (i & s) == want ? psi[i] * scale : 0.0;
+    return (double)p;
+}
+
+/* Born-rule measurement of qubit q: u = u53(x0, x1) of Philox4x32-10(key =
+ * seed, counter = (q, 0, 6, 0)); outcome 1 iff u < P1 / (P0 + P1), then the
+ * state collapses onto it.  Returns the outcome; *prob = its probability. */
+EXPORT int ref_measure(cplx *psi, int n, int q, uint64_t seed, double *prob)
+{
+    const uint64_t N = 1ull << n, s = 1ull << q;
+    ldbl p0 = 0, p1 = 0;
+    for (uint64_t i = 0; i < N; ++i) {
+        const ldbl m = (ldbl)creal(psi[i]) * creal(psi[i]) + (ldbl)cimag(psi[i]) * cimag(psi[i]);
+        if (i & s) p1 += m; else p0 += m;
+    }
+    uint32_t x[4];
+    philox_draw(seed, (uint32_t)q, 0u, TAG_MEASURE, x);
+    const double u = u53(x[0], x[1]);
+    const int outcome = u < (double)p1 / ((double)p0 + (double)p1);
+    const double p = ref_collapse(psi, n, q, outcome);
+    if (prob) *prob = p;
+    return outcome;
+}
+
 EXPORT void ref_expect_z_all(const cplx *psi, int n, double *out)
 {
     const uint64_t N = 1ull << n;
@@ -507,11 +604,49 @@ EXPORT uint32_t ref_depol_threshold(double p)
     return (uint32_t)floor(p * 4294967296.0);
 }
 
+/* Stochastic noise gate (Pool of multiple states: one-qubit rotations with
+ * random angles whose ensemble average is the decoherence channel).  For a
+ * duration d: independent rotations R_X(a_x), then R_Y(a_y), then R_Z(a_z),
+ * R_P(a) = exp(-i a P / 2), with normal angles of variances d / T1, d / T1
+ * and 2 d / T2 - d / T1 (inv_T1 = 1 / T1, inv_T2 = 1 / T2).  A rotation by a
+ * normal angle of variance v averages to the Pauli channel that flips with
+ * probability (1 - e^{-v/2}) / 2, so the three together scale the Bloch
+ * vector by (e^{-d/T2}, e^{-d/T2}, e^{-d/T1}).  Normals by Box-Muller from
+ * Philox(key = seed, counter = (t, gate index, 7, w)): w = 0 gives a_x (cos
+ * branch) and a_y (sin branch), w = 1 gives a_z (cos branch). */
+static double gauss_pair(uint64_t seed, uint32_t t, uint32_t k, uint32_t w, double *second)
+{
+    uint32_t x[4];
+    philox_draw_w3(seed, t, k, TAG_NOISE, w, x);
+    const double u1 = u53(x[0], x[1]), u2 = u53(x[2], x[3]);
+    const double r = sqrt(-2.0 * log(1.0 - u1));
+    const double ang = 2.0 * M_PI * u2;
+    if (second) *second = r * sin(ang);
+    return r * cos(ang);
+}
+
+static void noise_gate(cplx *psi, int n, int q, double d, double inv_T1, double inv_T2, uint64_t seed, uint32_t t, uint32_t k)
+{
+    const double vxy = d * inv_T1, vz = 2.0 * d * inv_T2 - d * inv_T1;
+    double gy;
+    const double gx = gauss_pair(seed, t, k, 0u, &gy);
+    const double gz = gauss_pair(seed, t, k, 1u, NULL);
+    const double ax = sqrt(vxy) * gx, ay = sqrt(vxy) * gy, az = sqrt(vz > 0 ? vz : 0.0) * gz;
+    const double cx = cos(ax / 2), sx = sin(ax / 2), cy = cos(ay / 2), sy = sin(ay / 2), cz = cos(az / 2), sz = sin(az / 2);
+    const double RX[8] = {cx, 0, 0, -sx, 0, -sx, cx, 0};
+    const double RY[8] = {cy, 0, -sy, 0, sy, 0, cy, 0};
+    const double RZ[8] = {cz, -sz, 0, 0, 0, 0, cz, sz};
+    ref_apply_1q(psi, n, q, RX);
+    ref_apply_1q(psi, n, q, RY);
+    ref_apply_1q(psi, n, q, RZ);
+}
+
 /* Runs trajectory `t` in place on psi (already initialised).  Writes up to
  * log_cap insertion records (slot << 2 | pauli) and returns the number of
- * insertions. */
+ * insertions.  Noise gates (kind 5, qubit q0, duration u[0]) draw no
+ * insertion slots. */
 EXPORT int ref_traj_run_one(cplx *psi, int n, const ref_gate *g, int count, double p, uint64_t seed, uint32_t t,
-                            uint32_t *log, int log_cap)
+                            uint32_t *log, int log_cap, double inv_T1, double inv_T2)
 {
     const double X[8] = {0, 0, 1, 0, 1, 0, 0, 0};
     const double Y[8] = {0, 0, 0, -1, 0, 1, 0, 0};
@@ -520,6 +655,10 @@ EXPORT int ref_traj_run_one(cplx *psi, int n, const ref_gate *g, int count, doub
     uint32_t slot = 0;
     int nins = 0;
     for (int k = 0; k < count; ++k) {
+        if (g[k].kind == RG_NOISE) {
+            noise_gate(psi, n, g[k].q0, g[k].u[0], inv_T1, inv_T2, seed, t, (uint32_t)k);
+            continue;
+        }
         apply_gate(psi, n, &g[k]);
         const int touched[2] = {g[k].q0, g[k].q1};
         const int nt = (g[k].kind == RG_1Q) ? 1 : 2;

@@ -166,14 +166,46 @@ QS_API int qs_apply_swap(qs_state *s, int a, int b) {
     return launch_apply_swap(s, a, b);
 }
 
+QS_API int qs_apply_kq(qs_state *s, const int32_t *qubits, int k, const double *U_dev) {
+    QS_GUARD_BEGIN
+    if (int rc = check_state(s)) return rc;
+    if (!qubits || !U_dev) return fail(QS_ERR_ARG, "null qubit list or matrix");
+    if ((uintptr_t)U_dev % 16) return fail(QS_ERR_ARG, "matrix must be 16-byte aligned");
+    if (k < 1 || k > 5) return fail(QS_ERR_ARG, "k-qubit gates need 1 <= k <= 5");
+    if (k > s->n) return fail(QS_ERR_ARG, "more gate qubits than the register has");
+    for (int m = 0; m < k; ++m) {
+        if (int rc = check_qubit(s, qubits[m], "gate")) return rc;
+        for (int j = 0; j < m; ++j)
+            if (qubits[j] == qubits[m]) return fail(QS_ERR_ARG, "gate qubits must be distinct");
+    }
+    return launch_apply_kq(s, qubits, k, U_dev);
+    QS_GUARD_END
+}
+
+QS_API int qs_collapse(qs_state *s, int q, int outcome, double *prob_dev) {
+    if (int rc = check_state(s)) return rc;
+    if (int rc = check_qubit(s, q, "measured")) return rc;
+    if (outcome != 0 && outcome != 1) return fail(QS_ERR_ARG, "outcome must be 0 or 1");
+    return launch_measure(s, q, outcome, 0, nullptr, prob_dev);
+}
+
+QS_API int qs_measure(qs_state *s, int q, uint64_t seed, int32_t *outcome_dev, double *prob_dev) {
+    if (int rc = check_state(s)) return rc;
+    if (int rc = check_qubit(s, q, "measured")) return rc;
+    return launch_measure(s, q, -1, seed, outcome_dev, prob_dev);
+}
+
 namespace qs {
-int validate_gates(int n, const qs_gate *gates, int count) {
+int validate_gates(int n, const qs_gate *gates, int count, bool allow_noise) {
     if (count < 0) return fail(QS_ERR_ARG, "negative gate count");
     if (count > 0 && !gates) return fail(QS_ERR_ARG, "null gate list");
     for (int k = 0; k < count; ++k) {
         const qs_gate &g = gates[k];
-        const bool two = g.kind != QS_G_1Q;
-        if (g.kind < QS_G_1Q || g.kind > QS_G_SWAP) return fail(QS_ERR_ARG, "gate " + std::to_string(k) + ": unknown kind");
+        const bool two = g.kind != QS_G_1Q && g.kind != QS_G_NOISE;
+        if (g.kind < QS_G_1Q || g.kind > (allow_noise ? QS_G_NOISE : QS_G_SWAP))
+            return fail(QS_ERR_ARG, "gate " + std::to_string(k) + ": unknown kind");
+        if (g.kind == QS_G_NOISE && !(g.u[0] >= 0.0 && g.u[0] < INFINITY))
+            return fail(QS_ERR_ARG, "gate " + std::to_string(k) + ": noise duration must be finite and >= 0");
         if (g.q0 < 0 || g.q0 >= n || (two && (g.q1 < 0 || g.q1 >= n || g.q1 == g.q0)))
             return fail(QS_ERR_ARG, "gate " + std::to_string(k) + ": qubit out of range or repeated");
     }
@@ -184,7 +216,7 @@ int validate_gates(int n, const qs_gate *gates, int count) {
 QS_API int qs_apply_block(qs_state *s, const qs_gate *gates, int count) {
     QS_GUARD_BEGIN
     if (int rc = check_state(s)) return rc;
-    if (int rc = validate_gates(s->n, gates, count)) return rc;
+    if (int rc = validate_gates(s->n, gates, count, false)) return rc;
     return run_block(s, gates, count);
     QS_GUARD_END
 }

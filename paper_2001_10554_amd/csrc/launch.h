@@ -27,6 +27,10 @@ int launch_expect_pauli(qs_state *s, u64 xmask, u64 zmask, double *out_dev);
 int launch_inner(qs_state *a, qs_state *b, double *out_dev);
 int launch_sample(qs_state *s, int64_t shots, u64 seed, u64 *out_dev);
 
+// measure.hip
+int launch_measure(qs_state *s, int q, int outcome, u64 seed, int32_t *outcome_dev, double *prob_dev);
+int launch_apply_kq(qs_state *s, const int32_t *qubits, int k, const double *U_dev);
+
 // tile.hip
 int run_block(qs_state *s, const qs_gate *gates, int count);
 void free_plan_cache(qs_state *s);

@@ -232,6 +232,17 @@ QS_API int qs_pool_workspace_bytes(const qs_pool_desc *d, size_t *bytes) {
     }
 }
 
+QS_API int qs_pool_circuit_bytes(const qs_pool_desc *d, int with_grad, size_t *bytes) {
+    try {
+        if (int rc = check_pool(d)) return rc;
+        if (!bytes) return fail(QS_ERR_ARG, "null output");
+        *bytes = max_circ_bytes(d, with_grad != 0);
+        return QS_OK;
+    } catch (...) {
+        return fail(QS_ERR_UNSUPPORTED, "unexpected internal error");
+    }
+}
+
 QS_API int qs_pool_run(const qs_pool_desc *d, const double *angles_dev, double *E_dev, double *grad_dev, void *ws, size_t ws_bytes, void *stream) {
     try {
         if (int rc = check_pool(d)) return rc;

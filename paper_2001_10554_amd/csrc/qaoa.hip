@@ -753,15 +753,23 @@ QShape qaoa_default_shape(int n) {
         const int tb = env_tb < n ? env_tb : n;
         return QShape{tb, threads_bits_for(tb), env_r == 2 || env_r == 3 ? env_r : 3};
     }
-    // 13-qubit tiles would save a pass per layer for some n, but their backward
-    // kernel exceeds the register file (spills); they are not offered.
-    return QShape{n < 12 ? n : 12, threads_bits_for(n < 12 ? n : 12), 3};
+    // Measured on MI355X (adjoint gradient, p = 8, one angle set): small
+    // registers are latency-bound and favour the 16 KiB tiles (more blocks);
+    // from 20 qubits on, the shape with the fewest passes per layer and the
+    // most blocks at that pass count wins.  13-qubit tiles would save a pass
+    // for some n, but their backward kernel exceeds the register file.
+    if (n <= 16) return QShape{10, 8, 3};
+    if (n <= 18) return QShape{10, 8, 2};
+    if (n <= 20) return QShape{12, 9, 3};
+    if (n <= 22) return QShape{12, 9, 2};
+    if (n <= 26) return QShape{11, 8, 3};
+    return QShape{12, 9, 3};
 }
 
 std::vector<QShape> qaoa_candidate_shapes(int n) {
     std::vector<QShape> v;
     if (n < 10) return {qaoa_default_shape(n)};
-    for (QShape s : {QShape{10, 8, 3}, QShape{11, 8, 3}, QShape{12, 9, 3}, QShape{12, 9, 2}})
+    for (QShape s : {QShape{10, 8, 3}, QShape{10, 8, 2}, QShape{11, 8, 3}, QShape{12, 9, 3}, QShape{12, 9, 2}})
         if (s.TB <= n) v.push_back(s);
     return v;
 }

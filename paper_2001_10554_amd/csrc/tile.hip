@@ -73,7 +73,7 @@ void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass>
         for (; k < count; ++k) {
             u64 need = 0;
             const qs_gate &x = g[k];
-            if (x.kind == QS_G_1Q) need = 1ull << x.q0;
+            if (x.kind == QS_G_1Q || x.kind == QS_G_NOISE) need = 1ull << x.q0;
             else if (x.kind == QS_G_C1Q) need = 1ull << x.q1;
             else if (x.kind == QS_G_SWAP) need = (1ull << x.q0) | (1ull << x.q1);
             if (__builtin_popcountll(T | need) > tbmax) break;
@@ -99,9 +99,10 @@ void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass>
             DGate d{};
             d.kind = g[j].kind;
             d.q0 = (int8_t)g[j].q0;
-            d.q1 = (int8_t)(g[j].kind == QS_G_1Q ? 0 : g[j].q1);
+            const bool one = g[j].kind == QS_G_1Q || g[j].kind == QS_G_NOISE;
+            d.q1 = (int8_t)(one ? 0 : g[j].q1);
             d.p0 = (int8_t)pos[g[j].q0];
-            d.p1 = (int8_t)(g[j].kind == QS_G_1Q ? -1 : pos[g[j].q1]);
+            d.p1 = (int8_t)(one ? -1 : pos[g[j].q1]);
             memcpy(d.u, g[j].u, sizeof(d.u));
             dg.push_back(d);
         }

@@ -41,9 +41,12 @@ struct TGate {  // gate list on the device (kind, q0, q1, u)
 
 // frames[t * count + g] = (a | b << 32) before gate g; final[t] after all gates;
 // nins[t] = number of insertions (0 for the noiseless run t = n_traj).
+// force_all: every noisy trajectory is simulated on its own (noise gates make
+// each trajectory's state differ even without insertions); nins_ws > 0 marks
+// a trajectory simulated on its own.
 __global__ void k_traj_frames(const TGate *__restrict__ gates, int count, int n_traj, u32 thr, u32 k0, u32 k1, uint64_t *__restrict__ frames,
                               uint64_t *__restrict__ final_frame, int32_t *__restrict__ nins_ws, int32_t *__restrict__ counts,
-                              uint32_t *__restrict__ log, int log_cap) {
+                              uint32_t *__restrict__ log, int log_cap, int force_all) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t > n_traj) return;
     u32 a = 0, b = 0, slot = 0;
@@ -57,7 +60,7 @@ __global__ void k_traj_frames(const TGate *__restrict__ gates, int count, int n_
             if (((a & x) != 0) != ((a & y) != 0)) a ^= x | y;
             if (((b & x) != 0) != ((b & y) != 0)) b ^= x | y;
         }
-        const int nt = G.kind == QS_G_1Q ? 1 : 2;
+        const int nt = G.kind == QS_G_NOISE ? 0 : G.kind == QS_G_1Q ? 1 : 2;
         for (int k = 0; k < nt; ++k, ++slot) {
             if (ideal) continue;
             const Philox4 r = philox4x32_10((u32)t, slot, kTagTraj, 0u, k0, k1);
@@ -72,7 +75,7 @@ __global__ void k_traj_frames(const TGate *__restrict__ gates, int count, int n_
         }
     }
     final_frame[t] = (u64)a | ((u64)b << 32);
-    nins_ws[t] = nins;
+    nins_ws[t] = nins + (force_all && !ideal ? 1 : 0);
     if (counts && !ideal) counts[t] = nins;
 }
 
@@ -95,10 +98,35 @@ __device__ __forceinline__ void conj_pauli(double *u, int xa, int zb) {
     }
 }
 
+// Noise gate of duration d for trajectory t, gate index gidx: the composed
+// rotation R_Z(a_z) R_Y(a_y) R_X(a_x) with Box-Muller normals from Philox
+// (key = seed, counter = (t, gidx, 7, w)), angle variances d/T1, d/T1 and
+// 2d/T2 - d/T1.
+constexpr u32 kTagNoise = 7;
+__device__ __forceinline__ void noise_matrix(double *u, double d, double inv_T1, double inv_T2, u32 t, u32 gidx, u32 k0, u32 k1) {
+    const double two_pi = 6.283185307179586476925286766559;
+    const Philox4 x0 = philox4x32_10(t, gidx, kTagNoise, 0u, k0, k1);
+    const Philox4 x1 = philox4x32_10(t, gidx, kTagNoise, 1u, k0, k1);
+    const double r0 = sqrt(-2.0 * log(1.0 - u53(x0.v[0], x0.v[1]))), t0 = two_pi * u53(x0.v[2], x0.v[3]);
+    const double r1 = sqrt(-2.0 * log(1.0 - u53(x1.v[0], x1.v[1]))), t1 = two_pi * u53(x1.v[2], x1.v[3]);
+    const double vxy = d * inv_T1, vz = 2.0 * d * inv_T2 - d * inv_T1;
+    const double ax = sqrt(vxy) * (r0 * cos(t0)), ay = sqrt(vxy) * (r0 * sin(t0)), az = sqrt(vz > 0.0 ? vz : 0.0) * (r1 * cos(t1));
+    const double cx = cos(0.5 * ax), sx = sin(0.5 * ax), cy = cos(0.5 * ay), sy = sin(0.5 * ay), cz = cos(0.5 * az), sz = sin(0.5 * az);
+    // Y X = [[cy, -sy], [sy, cy]] [[cx, -i sx], [-i sx, cx]]
+    const double m00r = cy * cx, m00i = sy * sx, m01r = -sy * cx, m01i = -cy * sx;
+    const double m10r = sy * cx, m10i = -cy * sx, m11r = cy * cx, m11i = -sy * sx;
+    // Z (Y X): row 0 times e^{-i az/2}, row 1 times e^{+i az/2}
+    u[0] = cz * m00r + sz * m00i; u[1] = cz * m00i - sz * m00r;
+    u[2] = cz * m01r + sz * m01i; u[3] = cz * m01i - sz * m01r;
+    u[4] = cz * m10r - sz * m10i; u[5] = cz * m10i + sz * m10r;
+    u[6] = cz * m11r - sz * m11i; u[7] = cz * m11i + sz * m11r;
+}
+
 template <typename R, int TBMAX>
 __global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states, u64 N, int tiles_log2, DPass P, const DGate *__restrict__ gates,
                                                       const uint64_t *__restrict__ frames, int count, int first_pass, u64 basis,
-                                                      const int32_t *__restrict__ nins, int n_traj) {
+                                                      const int32_t *__restrict__ nins, int n_traj, u32 k0, u32 k1, double inv_T1,
+                                                      double inv_T2) {
     __shared__ cx<R> sh[1 << TBMAX];
     const u64 tile = blockIdx.x & ((1ull << tiles_log2) - 1);
     const u64 t = blockIdx.x >> tiles_log2;
@@ -125,8 +153,13 @@ __global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states
         const u32 a = (u32)f, b = (u32)(f >> 32);
         double u[8];
         for (int k = 0; k < 8; ++k) u[k] = g.u[k];
-        int cval = 1;
-        if (g.kind == QS_G_1Q) {
+        int cval = 1, kind = g.kind;
+        if (kind == QS_G_NOISE) {
+            if (t == (u64)n_traj) continue;  // the noiseless reference run
+            noise_matrix(u, g.u[0], inv_T1, inv_T2, (u32)t, (u32)gidx, k0, k1);
+            conj_pauli(u, (a >> g.q0) & 1, (b >> g.q0) & 1);
+            kind = QS_G_1Q;
+        } else if (g.kind == QS_G_1Q) {
             conj_pauli(u, (a >> g.q0) & 1, (b >> g.q0) & 1);
         } else if (g.kind == QS_G_C1Q) {
             cval = 1 ^ (int)((a >> g.q0) & 1);
@@ -139,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states
                 u[2 * e + 1] = g.u[2 * src + 1];
             }
         }
-        lds_apply_gate<R, kBlock>(sh, TS, base, g.kind, g.p0, g.p1, g.q0, g.q1, cval, u);
+        lds_apply_gate<R, kBlock>(sh, TS, base, kind, g.p0, g.p1, g.q0, g.q1, cval, u);
     }
     for (u64 m = threadIdx.x; m < TS; m += kBlock) st<true>(psi + (base | pass_off(P, m)), sh[m]);
 }
@@ -154,13 +187,14 @@ __device__ __forceinline__ double tblock_sum(double v, double *red) {
 }
 
 // Per simulated trajectory and chunk of amplitudes: [0, n) = sum (-1)^{k_q}
-// |psi_k|^2 and (n, n+1) = <ideal|F psi> (re, im).  The chunk's index bits
+// |psi_k|^2, (n, n+1) = <ideal|F psi> (re, im) and n+2 = sum_k d_k |(F psi)_k|^2
+// for a diagonal observable d.  The chunk's index bits
 // below log2(256) are fixed per thread, the others per loop step, so each
 // <Z_q> needs one add per amplitude only for the q the loop varies.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ states, int n, int chunk_log2, int chunks_log2,
                                                     const uint64_t *__restrict__ final_frame, const int32_t *__restrict__ nins, int n_traj,
-                                                    double *__restrict__ partial) {
+                                                    const double *__restrict__ diag, double *__restrict__ partial) {
     __shared__ double red[kBlock / 64];
     const u64 N = 1ull << n;
     const u64 c = blockIdx.x & ((1ull << chunks_log2) - 1);
@@ -170,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ st
     const cx<R> *ideal = states + (u64)n_traj * N;
     const u64 f = final_frame[t];
     const u32 fa = (u32)f, fb = (u32)(f >> 32);
-    double z[kTrajMaxQubits], fre = 0.0, fim = 0.0;
+    double z[kTrajMaxQubits], fre = 0.0, fim = 0.0, dsum = 0.0;
 #pragma unroll
     for (int q = 0; q < kTrajMaxQubits; ++q) z[q] = 0.0;
     const u64 lo = c << chunk_log2, hi = lo + (1ull << chunk_log2);
@@ -183,8 +217,9 @@ __global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ st
         const double sgn = (__popcll(i & fb) & 1) ? -1.0 : 1.0;
         fre += sgn * ((double)id.x * v.x + (double)id.y * v.y);
         fim += sgn * ((double)id.x * v.y - (double)id.y * v.x);
+        if (diag) dsum += p * diag[i ^ fa];
     }
-    const int nv = n + 2;
+    const int nv = n + 3;
     double *out = partial + (u64)blockIdx.x * nv;
 #pragma unroll
     for (int q = 0; q < kTrajMaxQubits; ++q) {
@@ -193,9 +228,11 @@ __global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ st
     }
     const double tre = tblock_sum(fre, red);
     const double tim = tblock_sum(fim, red);
+    const double tds = tblock_sum(dsum, red);
     if (threadIdx.x == 0) {
         out[n] = tre;
         out[n + 1] = tim;
+        out[n + 2] = tds;
     }
 }
 
@@ -227,15 +264,15 @@ __global__ __launch_bounds__(kBlock) void k_traj_x(const cx<R> *__restrict__ sta
 // trajectory's representative in order, then undo the trajectory's frame.
 __global__ void k_traj_final(const double *__restrict__ pzf, const double *__restrict__ px, int n, int chunks, int n_traj,
                              const uint64_t *__restrict__ final_frame, const int32_t *__restrict__ nins, double *__restrict__ z,
-                             double *__restrict__ x, double *__restrict__ fid) {
+                             double *__restrict__ x, double *__restrict__ fid, double *__restrict__ dval) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    const int per = n + n + 1;  // z values, x values, fidelity
+    const int per = n + n + 2;  // z values, x values, fidelity, diagonal observable
     if (id >= n_traj * per) return;
     const int t = id / per, v = id % per;
     const u64 rep = traj_rep(nins, t, n_traj);
     const u64 f = final_frame[t];
     const u32 a = (u32)f, b = (u32)(f >> 32);
-    const int nv = n + 2;
+    const int nv = n + 3;
     if (v < n) {
         const double *p = pzf + rep * chunks * nv;
         double s = 0.0;
@@ -247,7 +284,7 @@ __global__ void k_traj_final(const double *__restrict__ pzf, const double *__res
         double s = 0.0;
         for (int c = 0; c < chunks; ++c) s += p[c];
         if (x) x[(u64)t * n + q] = ((b >> q) & 1) ? -s : s;
-    } else {
+    } else if (v == 2 * n) {
         const double *p = pzf + rep * chunks * nv;
         double re = 0.0, im = 0.0;
         for (int c = 0; c < chunks; ++c) {
@@ -255,6 +292,11 @@ __global__ void k_traj_final(const double *__restrict__ pzf, const double *__res
             im += p[(u64)c * nv + n + 1];
         }
         if (fid) fid[t] = re * re + im * im;
+    } else {
+        const double *p = pzf + rep * chunks * nv;
+        double s = 0.0;
+        for (int c = 0; c < chunks; ++c) s += p[(u64)c * nv + n + 2];
+        if (dval) dval[t] = s;
     }
 }
 
@@ -297,7 +339,7 @@ static TrajLayout traj_layout(int n, int dtype, int count, int n_traj) {
     L.nins = off;
     off = align(off + (size_t)(n_traj + 1) * sizeof(int32_t));
     L.pzf = off;
-    off = align(off + (size_t)(n_traj + 1) * ((size_t)1 << L.chunks_log2) * (n + 2) * sizeof(double));
+    off = align(off + (size_t)(n_traj + 1) * ((size_t)1 << L.chunks_log2) * (n + 3) * sizeof(double));
     L.px = off;
     off = align(off + (size_t)(n_traj + 1) * n * ((size_t)1 << L.chunks_log2) * sizeof(double));
     L.gates = off;
@@ -309,8 +351,8 @@ static TrajLayout traj_layout(int n, int dtype, int count, int n_traj) {
 }
 
 template <typename R, int TBMAX>
-static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 basis, int n_traj, double p, u64 seed, const qs_traj_out *out,
-                      char *ws, hipStream_t st) {
+static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 basis, int n_traj, double p, double inv_T1, double inv_T2, u64 seed,
+                      const qs_traj_out *out, char *ws, hipStream_t st) {
     const TrajLayout L = traj_layout(n, dtype, count, n_traj);
     const u64 N = 1ull << n;
     std::vector<DPass> passes;
@@ -325,8 +367,12 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     else if (p > 0.0) thr = (u32)floor(p * 4294967296.0);
     uint64_t *frames = (uint64_t *)(ws + L.frames), *final_frame = (uint64_t *)(ws + L.final_frame);
     int32_t *nins = (int32_t *)(ws + L.nins);
+    bool noisy_gates = false;
+    for (int k = 0; k < count; ++k)
+        if (gates[k].kind == QS_G_NOISE && gates[k].u[0] > 0.0 && (inv_T1 > 0.0 || inv_T2 > 0.0)) noisy_gates = true;
     hipLaunchKernelGGL(k_traj_frames, dim3((n_traj + 1 + 63) / 64), dim3(64), 0, st, (const TGate *)(ws + L.gates), count, n_traj, thr,
-                       (u32)seed, (u32)(seed >> 32), frames, final_frame, nins, out->counts, out->log, out->log ? out->log_cap : 0);
+                       (u32)seed, (u32)(seed >> 32), frames, final_frame, nins, out->counts, out->log, out->log ? out->log_cap : 0,
+                       noisy_gates ? 1 : 0);
     QS_LAUNCH_CHECK("traj_frames");
     cx<R> *states = (cx<R> *)(ws + L.states);
     const int T1 = n_traj + 1;
@@ -335,16 +381,18 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
         const int tiles_log2 = P.nrest;
         const u64 blocks = (u64)T1 << tiles_log2;
         hipLaunchKernelGGL((k_traj_pass<R, TBMAX>), dim3((unsigned)blocks), dim3(kBlock), 0, st, states, N, tiles_log2, P, (const DGate *)(ws + L.dgates),
-                           (const uint64_t *)frames, count, first ? 1 : 0, basis, (const int32_t *)nins, n_traj);
+                           (const uint64_t *)frames, count, first ? 1 : 0, basis, (const int32_t *)nins, n_traj, (u32)seed, (u32)(seed >> 32),
+                           inv_T1, inv_T2);
         QS_LAUNCH_CHECK("traj_pass");
         first = false;
     }
     double *pzf = (double *)(ws + L.pzf), *px = (double *)(ws + L.px);
     const int chunks = 1 << L.chunks_log2;
-    if (out->z || out->fid) {
+    const double *diag = out->diag_val ? out->diag : nullptr;
+    if (out->z || out->fid || diag) {
         const u64 blocks = (u64)T1 << L.chunks_log2;
         hipLaunchKernelGGL(k_traj_zf<R>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<R> *)states, n, L.chunk_log2, L.chunks_log2,
-                           (const uint64_t *)final_frame, (const int32_t *)nins, n_traj, pzf);
+                           (const uint64_t *)final_frame, (const int32_t *)nins, n_traj, diag, pzf);
         QS_LAUNCH_CHECK("traj_zf");
     }
     if (out->x) {
@@ -353,10 +401,10 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
                            (const int32_t *)nins, n_traj, px);
         QS_LAUNCH_CHECK("traj_x");
     }
-    if (out->z || out->x || out->fid) {
-        const int work = n_traj * (2 * n + 1);
+    if (out->z || out->x || out->fid || diag) {
+        const int work = n_traj * (2 * n + 2);
         hipLaunchKernelGGL(k_traj_final, dim3((work + 255) / 256), dim3(256), 0, st, (const double *)pzf, (const double *)px, n, chunks, n_traj,
-                           (const uint64_t *)final_frame, (const int32_t *)nins, out->z, out->x, out->fid);
+                           (const uint64_t *)final_frame, (const int32_t *)nins, out->z, out->x, out->fid, diag ? out->diag_val : nullptr);
         QS_LAUNCH_CHECK("traj_final");
     }
     if (out->prob_mean) {
@@ -367,7 +415,27 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     return QS_OK;
 }
 
-int validate_gates(int n, const qs_gate *gates, int count);
+int validate_gates(int n, const qs_gate *gates, int count, bool allow_noise);
+
+static int traj_run_any(int n, int dtype, const qs_gate *gates, int count, u64 basis_index, int n_traj, const qs_noise &nz, u64 seed,
+                        const qs_traj_out *out, void *ws, size_t ws_bytes, void *stream) {
+    if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_ERR_DTYPE, "dtype must be QS_C64 or QS_C128");
+    if (n < 1 || n > kTrajMaxQubits) return fail(QS_ERR_ARG, "trajectories need 1 <= n <= 20");
+    if (count < 1 || count > kTrajMaxGates || n_traj < 1) return fail(QS_ERR_ARG, "bad gate or trajectory count");
+    if (!out || !ws) return fail(QS_ERR_ARG, "null output struct or workspace");
+    if (out->log && out->log_cap < 1) return fail(QS_ERR_ARG, "log_cap must be >= 1 with a log buffer");
+    if (out->diag_val && !out->diag) return fail(QS_ERR_ARG, "diag_val needs the diagonal observable");
+    if (basis_index >= (1ull << n)) return fail(QS_ERR_ARG, "basis index >= 2^n");
+    if (!(nz.p_depol >= 0.0 && nz.p_depol <= 1.0)) return fail(QS_ERR_ARG, "p must be in [0, 1]");
+    if (!(nz.T1 > 0.0) || !(nz.T2 > 0.0) || !(nz.T2 <= 2.0 * nz.T1)) return fail(QS_ERR_ARG, "need T1 > 0 and 0 < T2 <= 2 T1");
+    if (int rc = validate_gates(n, gates, count, true)) return rc;
+    if (ws_bytes < traj_layout(n, dtype, count, n_traj).total) return fail(QS_ERR_SIZE, "trajectory workspace too small");
+    const double inv_T1 = nz.T1 < INFINITY ? 1.0 / nz.T1 : 0.0, inv_T2 = nz.T2 < INFINITY ? 1.0 / nz.T2 : 0.0;
+    hipStream_t st = (hipStream_t)stream;
+    return dtype == QS_C128
+               ? traj_run_t<double, 12>(n, dtype, gates, count, basis_index, n_traj, nz.p_depol, inv_T1, inv_T2, seed, out, (char *)ws, st)
+               : traj_run_t<float, 13>(n, dtype, gates, count, basis_index, n_traj, nz.p_depol, inv_T1, inv_T2, seed, out, (char *)ws, st);
+}
 
 }  // namespace qs
 
@@ -385,18 +453,20 @@ QS_API int qs_traj_workspace_bytes(int n, int dtype, int count, int n_traj, size
 QS_API int qs_traj_run(int n, int dtype, const qs_gate *gates, int count, uint64_t basis_index, int n_traj, double p_depol, uint64_t seed,
                        const qs_traj_out *out, void *ws, size_t ws_bytes, void *stream) {
     try {
-        if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_ERR_DTYPE, "dtype must be QS_C64 or QS_C128");
-        if (n < 1 || n > kTrajMaxQubits) return fail(QS_ERR_ARG, "trajectories need 1 <= n <= 20");
-        if (count < 1 || count > kTrajMaxGates || n_traj < 1) return fail(QS_ERR_ARG, "bad gate or trajectory count");
-        if (!out || !ws) return fail(QS_ERR_ARG, "null output struct or workspace");
-        if (out->log && out->log_cap < 1) return fail(QS_ERR_ARG, "log_cap must be >= 1 with a log buffer");
-        if (basis_index >= (1ull << n)) return fail(QS_ERR_ARG, "basis index >= 2^n");
-        if (!(p_depol >= 0.0 && p_depol <= 1.0)) return fail(QS_ERR_ARG, "p must be in [0, 1]");
-        if (int rc = validate_gates(n, gates, count)) return rc;
-        if (ws_bytes < traj_layout(n, dtype, count, n_traj).total) return fail(QS_ERR_SIZE, "trajectory workspace too small");
-        hipStream_t st = (hipStream_t)stream;
-        return dtype == QS_C128 ? traj_run_t<double, 12>(n, dtype, gates, count, basis_index, n_traj, p_depol, seed, out, (char *)ws, st)
-                                : traj_run_t<float, 13>(n, dtype, gates, count, basis_index, n_traj, p_depol, seed, out, (char *)ws, st);
+        for (int k = 0; gates && k < count && k < kTrajMaxGates; ++k)
+            if (gates[k].kind == QS_G_NOISE) return fail(QS_ERR_ARG, "noise gates need qs_traj_run_noise");
+        const qs_noise nz{p_depol, INFINITY, INFINITY};
+        return traj_run_any(n, dtype, gates, count, basis_index, n_traj, nz, seed, out, ws, ws_bytes, stream);
+    } catch (...) {
+        return fail(QS_ERR_UNSUPPORTED, "unexpected internal error");
+    }
+}
+
+QS_API int qs_traj_run_noise(int n, int dtype, const qs_gate *gates, int count, uint64_t basis_index, int n_traj, const qs_noise *noise,
+                             uint64_t seed, const qs_traj_out *out, void *ws, size_t ws_bytes, void *stream) {
+    try {
+        if (!noise) return fail(QS_ERR_ARG, "null noise model");
+        return traj_run_any(n, dtype, gates, count, basis_index, n_traj, *noise, seed, out, ws, ws_bytes, stream);
     } catch (...) {
         return fail(QS_ERR_UNSUPPORTED, "unexpected internal error");
     }

@@ -10,11 +10,13 @@ calls raise.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
+from . import gates as G
 from . import workloads as W
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,10 +44,22 @@ class PoolDesc(ctypes.Structure):
                 ("n_qubits", ctypes.c_void_p), ("edge_offset", ctypes.c_void_p), ("edges", ctypes.c_void_p)]
 
 
+class PsoSwarm(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("pos", "vel", "pbest", "pbest_val", "gbest", "gbest_val", "E")]
+
+
+class PsoParams(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("phi_p", ctypes.c_double), ("phi_g", ctypes.c_double), ("attract", ctypes.c_int)]
+
+
 class TrajOut(ctypes.Structure):
     _fields_ = [("z", ctypes.c_void_p), ("x", ctypes.c_void_p), ("fid", ctypes.c_void_p),
                 ("prob_mean", ctypes.c_void_p), ("counts", ctypes.c_void_p), ("log", ctypes.c_void_p),
-                ("log_cap", ctypes.c_int)]
+                ("log_cap", ctypes.c_int), ("diag", ctypes.c_void_p), ("diag_val", ctypes.c_void_p)]
+
+
+class Noise(ctypes.Structure):
+    _fields_ = [("p_depol", ctypes.c_double), ("T1", ctypes.c_double), ("T2", ctypes.c_double)]
 
 
 _lib = None
@@ -72,6 +86,9 @@ def lib():
             "qs_apply_c1q": [vp, i, i, vp],
             "qs_apply_diag2": [vp, i, i, vp],
             "qs_apply_swap": [vp, i, i],
+            "qs_apply_kq": [vp, vp, i, vp],
+            "qs_collapse": [vp, i, i, vp],
+            "qs_measure": [vp, i, u64, vp, vp],
             "qs_apply_block": [vp, vp, i],
             "qs_apply_cut_phase": [vp, vp, vp, i, d],
             "qs_prob_one": [vp, i, vp],
@@ -86,8 +103,14 @@ def lib():
             "qs_qaoa_run": [vp, vp, i, vp, vp, vp, sz, vp],
             "qs_pool_workspace_bytes": [vp, vp],
             "qs_pool_run": [vp, vp, vp, vp, vp, sz, vp],
+            "qs_pool_circuit_bytes": [vp, i, vp],
+            "qs_cut_max": [vp, vp, vp, vp, vp],
+            "qs_pso_init": [vp, u64, vp, vp],
+            "qs_pso_step": [vp, vp, i, i, u64, vp, vp, vp],
+            "qs_pso_run": [vp, vp, i, u64, vp, vp, vp, sz, vp],
             "qs_traj_workspace_bytes": [i, i, i, i, vp],
             "qs_traj_run": [i, i, vp, i, u64, i, d, u64, vp, vp, sz, vp],
+            "qs_traj_run_noise": [i, i, vp, i, u64, i, vp, u64, vp, vp, sz, vp],
         }
         for name, args in sigs.items():
             f = getattr(L, name, None)
@@ -138,6 +161,7 @@ class State:
             amps = torch.empty(1 << n, dtype=dtype, device=device)
         self.amps = amps
         self._h = ctypes.c_void_p()
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
         check(lib().qs_state_create(n, code, ctypes.c_void_p(amps.data_ptr()), amps.numel() * amps.element_size(),
                                     ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(self._h)))
 
@@ -157,6 +181,7 @@ class State:
             pass
 
     def set_stream(self, stream=None):
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
         check(lib().qs_state_set_stream(self._h, ctypes.c_void_p(_stream_ptr(stream))))
 
     def sync(self):
@@ -190,6 +215,55 @@ class State:
 
     def apply_swap(self, a: int, b: int):
         check(lib().qs_apply_swap(self._h, a, b))
+
+    def apply_kq(self, qubits, m):
+        """Dense k-qubit matrix m (2^k x 2^k, row = output), 1 <= k <= 5; bit j
+        of its row/column index is the value of qubits[j]."""
+        qs = np.ascontiguousarray(qubits, dtype=np.int32)
+        mm = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+        with torch.cuda.stream(self._stream):  # the matrix is copied and then read on the state's stream
+            u = torch.view_as_real(torch.from_numpy(mm)).reshape(-1).to(self.amps.device)
+        check(lib().qs_apply_kq(self._h, _ptr(qs), len(qs), ctypes.c_void_p(u.data_ptr())))
+        u.record_stream(self._stream)  # not reused before the gate has run
+
+    def collapse(self, q: int, outcome: int) -> torch.Tensor:
+        """Project qubit q onto `outcome` and renormalise; returns P(outcome) (device)."""
+        o = self._out(1)
+        check(lib().qs_collapse(self._h, q, outcome, ctypes.c_void_p(o.data_ptr())))
+        return o
+
+    def measure(self, q: int, seed: int):
+        """Born-rule measurement of qubit q (decided on the device); returns
+        (outcome int32 [1], its probability float64 [1]) device tensors."""
+        out = self._out(1, torch.int32)
+        pr = self._out(1)
+        check(lib().qs_measure(self._h, q, seed, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(pr.data_ptr())))
+        return out, pr
+
+    # -- named gates (matrices from the gates module; every one runs the C-ABI gate kernels)
+    def h(self, q): self.apply_1q(q, G.H); return self
+    def x(self, q): self.apply_1q(q, G.X); return self
+    def y(self, q): self.apply_1q(q, G.Y); return self
+    def z(self, q): self.apply_1q(q, G.Z); return self
+    def s(self, q): self.apply_1q(q, G.S); return self
+    def sdg(self, q): self.apply_1q(q, G.SDG); return self
+    def t(self, q): self.apply_1q(q, G.T); return self
+    def tdg(self, q): self.apply_1q(q, G.TDG); return self
+    def sx(self, q): self.apply_1q(q, G.SX); return self
+    def rx(self, q, theta): self.apply_1q(q, G.rx(theta)); return self
+    def ry(self, q, theta): self.apply_1q(q, G.ry(theta)); return self
+    def rz(self, q, theta): self.apply_1q(q, G.rz(theta)); return self
+    def phase(self, q, phi): self.apply_1q(q, G.phase(phi)); return self
+    def u3(self, q, theta, phi, lam): self.apply_1q(q, G.u3(theta, phi, lam)); return self
+    def cnot(self, c, t): self.apply_c1q(c, t, G.X); return self
+    def cy(self, c, t): self.apply_c1q(c, t, G.Y); return self
+    def cz(self, a, b): self.apply_diag2(a, b, G.CZ_DIAG); return self
+    def cphase(self, a, b, phi): self.apply_diag2(a, b, G.cphase_diag(phi)); return self
+    def crx(self, c, t, theta): self.apply_c1q(c, t, G.rx(theta)); return self
+    def swap(self, a, b): self.apply_swap(a, b); return self
+    def iswap(self, a, b): self.apply_kq([a, b], G.ISWAP); return self
+    def toffoli(self, c0, c1, t): self.apply_kq([c0, c1, t], G.TOFFOLI); return self
+    def fredkin(self, c, a, b): self.apply_kq([c, a, b], G.FREDKIN); return self
 
     def apply_block(self, gates: np.ndarray):
         g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
@@ -289,13 +363,18 @@ class Pool:
     evaluates every <C> and (optionally) every adjoint gradient; the launch
     sequence is captured into a hipGraph on the first call and replayed after."""
 
-    def __init__(self, graphs, n_qubits, sets_per_graph: int, p: int, device="cuda", grad: bool = True, ws_bytes: int | None = None):
+    def __init__(self, graphs, n_qubits, sets_per_graph: int, p: int, device="cuda", grad: bool = True, ws_bytes: int | None = None,
+                 ws_circuits: int | None = None):
         self.n_qubits = np.ascontiguousarray(n_qubits, dtype=np.int32)
         self.edges = np.ascontiguousarray(np.concatenate([_edges(e) for e in graphs]).reshape(-1), dtype=np.int32)
         self.offsets = np.ascontiguousarray(np.concatenate([[0], np.cumsum([len(_edges(e)) for e in graphs])]), dtype=np.int32)
         self.sets, self.p = sets_per_graph, p
         self.count = len(graphs) * sets_per_graph
         self._desc = PoolDesc(len(graphs), sets_per_graph, p, self.n_qubits.ctypes.data, self.offsets.ctypes.data, self.edges.ctypes.data)
+        if ws_bytes is None and ws_circuits is not None:  # room for this many circuits of the largest size per launch
+            nbytes = ctypes.c_size_t()
+            check(lib().qs_pool_circuit_bytes(ctypes.byref(self._desc), int(grad), ctypes.byref(nbytes)))
+            ws_bytes = nbytes.value * ws_circuits
         if ws_bytes is None:
             nbytes = ctypes.c_size_t()
             check(lib().qs_pool_workspace_bytes(ctypes.byref(self._desc), ctypes.byref(nbytes)))
@@ -316,10 +395,67 @@ class Pool:
         return self.E, self.G
 
 
+def cut_max(graphs, n_qubits, w=None, device="cuda", stream=None):
+    """Exact Max-Cut value of each graph (and the smallest maximising
+    bipartition): float64 [G] and uint64-as-int64 [G] device tensors."""
+    nq = np.ascontiguousarray(n_qubits, dtype=np.int32)
+    es = [_edges(e) for e in graphs]
+    off = np.ascontiguousarray(np.concatenate([[0], np.cumsum([len(e) for e in es])]), dtype=np.int32)
+    edges = np.ascontiguousarray(np.concatenate(es).reshape(-1), dtype=np.int32)
+    desc = PoolDesc(len(es), 1, 1, nq.ctypes.data, off.ctypes.data, edges.ctypes.data)
+    warr = None if w is None else np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64) for x in w]))
+    mx = torch.empty(len(es), dtype=torch.float64, device=device)
+    arg = torch.empty(len(es), dtype=torch.int64, device=device)
+    check(lib().qs_cut_max(ctypes.byref(desc), None if warr is None else _ptr(warr), ctypes.c_void_p(mx.data_ptr()),
+                           ctypes.c_void_p(arg.data_ptr()), ctypes.c_void_p(_stream_ptr(stream))))
+    return mx, arg
+
+
+class Swarm:
+    """Particle swarm over a Pool (graph g's swarm = its sets_per_graph angle
+    vectors); the pool's angle and energy buffers are the swarm's positions
+    and evaluations.  All state is device tensors."""
+
+    def __init__(self, pool: Pool, omega=0.66, phi_p=1.6, phi_g=0.62, attract=1):
+        self.pool = pool
+        G, R, D = len(pool.n_qubits), pool.sets, 2 * pool.p
+        f64 = dict(dtype=torch.float64, device=pool.angles.device)
+        self.pos, self.E = pool.angles, pool.E
+        self.vel = torch.empty(G, R, D, **f64)
+        self.pbest = torch.empty(G, R, D, **f64)
+        self.pbest_val = torch.empty(G, R, **f64)
+        self.gbest = torch.empty(G, D, **f64)
+        self.gbest_val = torch.empty(G, **f64)
+        self.G, self.R, self.D = G, R, D
+        self.params = PsoParams(omega, phi_p, phi_g, attract)
+        self._sw = PsoSwarm(*[t.data_ptr() for t in (self.pos, self.vel, self.pbest, self.pbest_val, self.gbest,
+                                                     self.gbest_val, self.E)])
+
+    def init(self, seed: int, stream=None):
+        check(lib().qs_pso_init(ctypes.byref(self.pool._desc), seed, ctypes.byref(self._sw), ctypes.c_void_p(_stream_ptr(stream))))
+
+    def step(self, rnd: int, seed: int, move: bool = True, history: torch.Tensor | None = None, stream=None):
+        check(lib().qs_pso_step(ctypes.byref(self.pool._desc), ctypes.byref(self.params), rnd, int(move), seed,
+                                ctypes.byref(self._sw), None if history is None else ctypes.c_void_p(history.data_ptr()),
+                                ctypes.c_void_p(_stream_ptr(stream))))
+
+    def run(self, rounds: int, seed: int, stream=None) -> torch.Tensor:
+        """Whole run on the device; returns the global-best history [rounds, G]."""
+        hist = torch.empty(rounds, self.G, dtype=torch.float64, device=self.pos.device)
+        check(lib().qs_pso_run(ctypes.byref(self.pool._desc), ctypes.byref(self.params), rounds, seed, ctypes.byref(self._sw),
+                               ctypes.c_void_p(hist.data_ptr()), ctypes.c_void_p(self.pool.ws.data_ptr()), self.pool.ws.numel(),
+                               ctypes.c_void_p(_stream_ptr(stream))))
+        return hist
+
+
 def traj_run(n: int, gates: np.ndarray, basis_index: int, n_traj: int, p: float, seed: int, dtype=torch.complex128,
-             log_cap: int = 0, prob_mean: bool = True, device="cuda", stream=None) -> dict:
-    """Noise trajectories with stochastic Pauli insertion.  Returns device tensors:
-    z, x [n_traj, n]; fid [n_traj]; counts [n_traj]; prob_mean [2^n]; log [n_traj, log_cap]."""
+             log_cap: int = 0, prob_mean: bool = True, device="cuda", stream=None, T1: float = math.inf, T2: float = math.inf,
+             diag: torch.Tensor | None = None) -> dict:
+    """Noise trajectories with stochastic Pauli insertion (probability p per
+    touched qubit) and stochastic noise gates (kind 5, timescales T1, T2).
+    Returns device tensors: z, x [n_traj, n]; fid [n_traj]; counts [n_traj];
+    prob_mean [2^n]; log [n_traj, log_cap]; diag [n_traj] (per-trajectory
+    expectation of the diagonal observable `diag`, a float64 [2^n] device tensor)."""
     g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
     code = QS_C128 if dtype == torch.complex128 else QS_C64
     nbytes = ctypes.c_size_t()
@@ -332,11 +468,20 @@ def traj_run(n: int, gates: np.ndarray, basis_index: int, n_traj: int, p: float,
         res["prob_mean"] = torch.empty(1 << n, **f64)
     if log_cap:
         res["log"] = torch.zeros(n_traj, log_cap, dtype=torch.int32, device=device)
+    if diag is not None:
+        assert diag.dtype == torch.float64 and diag.is_cuda and diag.numel() == 1 << n
+        res["diag"] = torch.empty(n_traj, **f64)
     out = TrajOut(res["z"].data_ptr(), res["x"].data_ptr(), res["fid"].data_ptr(),
                   res["prob_mean"].data_ptr() if prob_mean else None, res["counts"].data_ptr(),
-                  res["log"].data_ptr() if log_cap else None, log_cap)
-    check(lib().qs_traj_run(n, code, _ptr(g), len(g), basis_index, n_traj, p, seed, ctypes.byref(out),
-                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream_ptr(stream))))
+                  res["log"].data_ptr() if log_cap else None, log_cap,
+                  diag.data_ptr() if diag is not None else None, res["diag"].data_ptr() if diag is not None else None)
+    if math.isinf(T1) and math.isinf(T2) and not np.any(g["kind"] == W.G_NOISE):
+        check(lib().qs_traj_run(n, code, _ptr(g), len(g), basis_index, n_traj, p, seed, ctypes.byref(out),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream_ptr(stream))))
+    else:
+        nz = Noise(p, T1, T2)
+        check(lib().qs_traj_run_noise(n, code, _ptr(g), len(g), basis_index, n_traj, ctypes.byref(nz), seed, ctypes.byref(out),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream_ptr(stream))))
     # ws is released to torch's caching allocator in stream order: later work
     # on this stream cannot overwrite it before the kernels above have run.
     return res

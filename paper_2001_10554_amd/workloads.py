@@ -28,6 +28,7 @@ G_1Q = 1      # 2x2 matrix u on qubit q0
 G_C1Q = 2     # 2x2 matrix u on target q1 iff control q0 is |1>
 G_DIAG2 = 3   # diagonal diag(d00, d01, d10, d11) on (q0, q1); entry index = 2*b(q1) + b(q0)
 G_SWAP = 4    # exchange qubits q0 and q1
+G_NOISE = 5   # stochastic noise gate on qubit q0 for the duration u[0] (trajectories only)
 
 GATE_DTYPE = np.dtype([("kind", np.int32), ("q0", np.int32), ("q1", np.int32),
                        ("pad", np.int32), ("u", np.float64, (8,))], align=True)
@@ -228,3 +229,35 @@ def pool_workload(num_graphs: int, sets_per_graph: int, p: int, seed: int,
 
 def random_basis_index(n: int, seed: int) -> int:
     return int(rng(seed).integers(2 ** n))
+
+
+def with_noise_gates(gates: np.ndarray, duration: float = 1.0) -> np.ndarray:
+    """Schedule for stochastic noise gates: after every gate, one noise gate of
+    `duration` on each qubit the gate touches (q0, then q1)."""
+    recs = []
+    for g in np.asarray(gates, dtype=GATE_DTYPE):
+        recs.append(g)
+        touched = [int(g["q0"])] if g["kind"] == G_1Q else [int(g["q0"]), int(g["q1"])]
+        for q in touched:
+            r = np.zeros((), dtype=GATE_DTYPE)
+            r["kind"], r["q0"], r["q1"] = G_NOISE, q, -1
+            r["u"][0] = duration
+            recs.append(r)
+    return gates_array(recs)
+
+
+def qaoa_circuit(n: int, edges, p: int, theta) -> np.ndarray:
+    """QAOA Max-Cut circuit as a gate list: H on every qubit, then per layer l
+    a two-qubit diagonal diag(1, e^{-i g}, e^{-i g}, 1) per edge (g = gamma_l)
+    and RX(2 beta_l) = exp(-i beta_l X) on every qubit."""
+    theta = np.asarray(theta, dtype=np.float64)
+    recs = [gate(G_1Q, q, -1, HADAMARD) for q in range(n)]
+    for l in range(p):
+        g, b = theta[l], theta[p + l]
+        d = np.array([1.0, np.exp(-1j * g), np.exp(-1j * g), 1.0])
+        for u, v in np.asarray(edges).reshape(-1, 2):
+            recs.append(gate(G_DIAG2, int(u), int(v), d))
+        rx = np.array([[math.cos(b), -1j * math.sin(b)], [-1j * math.sin(b), math.cos(b)]])
+        for q in range(n):
+            recs.append(gate(G_1Q, q, -1, rx))
+    return gates_array(recs)

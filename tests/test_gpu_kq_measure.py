@@ -1,0 +1,152 @@
+"""GPU parity for dense k-qubit gates, collapse, Born measurement and the
+named-gate methods, all through the C-ABI, against the oracle on the same
+seeded states (each side builds its own copy of the state)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_10554_amd import gates as G
+from paper_2001_10554_amd import workloads as W
+from gpu_util import TOL, max_err, require_gpu, to_host, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def rand_unitary(k, seed):
+    g = np.random.default_rng(seed)
+    a = g.standard_normal((1 << k, 1 << k)) + 1j * g.standard_normal((1 << k, 1 << k))
+    q, r = np.linalg.qr(a)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+LISTS = [[0], [13], [4, 9], [9, 0], [0, 1, 2], [13, 2, 7], [3, 12, 0, 8], [0, 1, 2, 3], [11, 0, 6, 13, 2], [4, 3, 2, 1, 0]]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_kq_vs_oracle(dt):
+    from paper_2001_10554_amd.qsim import State
+    n = 14
+    s = State(n, torch_dtype(dt)).init_random(3)
+    ref = oracle.init_random(n, 3)
+    for i, qs in enumerate(LISTS):
+        U = rand_unitary(len(qs), 100 + i)
+        s.apply_kq(qs, U)
+        oracle.apply_kq(ref, qs, U)
+        assert max_err(to_host(s), ref) < TOL[dt] * (i + 1), (qs, max_err(to_host(s), ref))
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_kq_24q(k):
+    from paper_2001_10554_amd.qsim import State
+    n = 24
+    qs = [23, 0, 12, 5, 17][:k]
+    U = rand_unitary(k, 7 + k)
+    s = State(n).init_random(4)
+    ref = oracle.init_random(n, 4)
+    s.apply_kq(qs, U)
+    oracle.apply_kq(ref, qs, U)
+    assert max_err(to_host(s), ref) < 1e-12
+
+
+def test_kq_validation():
+    from paper_2001_10554_amd.qsim import QsimError, State
+    s = State(6).init_basis(0)
+    for qs, m in (([0, 0], np.eye(4)), ([0, 6], np.eye(4)), (list(range(6)), np.eye(64)), ([], np.eye(1))):
+        with pytest.raises(QsimError):
+            s.apply_kq(qs, m)
+    with pytest.raises(QsimError):
+        s.collapse(0, 2)
+    with pytest.raises(QsimError):
+        s.measure(6, 1)
+    s3 = State(3).init_basis(5)
+    s3.apply_kq([0, 1, 2], G.TOFFOLI)  # 3 qubits on a 3-qubit register: a single group
+    assert abs(s3.amps[5].item() - 1) == 0
+
+
+@pytest.mark.parametrize("dt,n", [("c128", 6), ("c128", 17), ("c64", 15), ("c128", 23)])
+def test_collapse_vs_oracle(dt, n):
+    from paper_2001_10554_amd.qsim import State
+    s = State(n, torch_dtype(dt)).init_random(5)
+    ref = oracle.init_random(n, 5)
+    for q, out in ((0, 1), (n - 1, 0), (n // 2, 1)):
+        p = s.collapse(q, out).item()
+        p_ref = oracle.collapse(ref, q, out)
+        assert abs(p - p_ref) < (1e-13 if dt == "c128" else 1e-6)
+        assert max_err(to_host(s), ref) < TOL[dt] * 10
+    assert abs(s.norm2().item() - 1) < (1e-12 if dt == "c128" else 1e-5)
+    # the measured-away outcome has probability 0: the whole state becomes 0
+    assert s.collapse(0, 0).item() == 0.0
+    assert not s.amps.abs().max().item()
+
+
+def test_measure_vs_oracle():
+    from paper_2001_10554_amd.qsim import State
+    n = 12
+    g = oracle.init_random(n, 6)
+    ones = 0
+    for seed in range(40):
+        q = seed % n
+        s = State(n).init_random(6)
+        ref = g.copy()
+        out, pr = s.measure(q, seed)
+        o_ref, p_ref = oracle.measure(ref, q, seed)
+        assert out.item() == o_ref, seed
+        assert abs(pr.item() - p_ref) < 1e-13
+        assert max_err(to_host(s), ref) < 1e-12
+        ones += o_ref
+    assert 0 < ones < 40
+    # sequential measurement of every qubit leaves a basis state
+    s = State(n).init_random(6)
+    ref = g.copy()
+    for q in range(n):
+        s.measure(q, 1000 + q)
+        oracle.measure(ref, q, 1000 + q)
+    h = to_host(s)
+    assert max_err(h, ref) < 1e-12
+    assert np.count_nonzero(np.abs(h) > 0.5) == 1
+
+
+def test_named_gates_vs_oracle():
+    from paper_2001_10554_amd.qsim import State
+    n = 8
+    s = State(n).init_basis(0)
+    ref = oracle.init_basis(n, 0)
+    seq = [("h", (0,), G.H), ("x", (1,), G.X), ("y", (2,), G.Y), ("z", (0,), G.Z), ("s", (3,), G.S), ("t", (4,), G.T),
+           ("sdg", (3,), G.SDG), ("tdg", (5,), G.TDG), ("sx", (6,), G.SX), ("rx", (7, 0.3), G.rx(0.3)),
+           ("ry", (2, -1.1), G.ry(-1.1)), ("rz", (5, 2.2), G.rz(2.2)), ("phase", (4, 0.7), G.phase(0.7)),
+           ("u3", (1, 0.4, 0.5, -0.6), G.u3(0.4, 0.5, -0.6))]
+    for q in range(n):
+        s.h(q)
+        oracle.apply_1q(ref, q, G.H)
+    for name, args, m in seq:
+        getattr(s, name)(*args)
+        oracle.apply_1q(ref, args[0], m)
+    s.cnot(0, 5).cy(2, 7).crx(6, 1, 0.9).cz(3, 4).cphase(7, 0, 1.3).swap(1, 6).iswap(2, 5).toffoli(0, 3, 7).fredkin(4, 1, 2)
+    oracle.apply_c1q(ref, 0, 5, G.X)
+    oracle.apply_c1q(ref, 2, 7, G.Y)
+    oracle.apply_c1q(ref, 6, 1, G.rx(0.9))
+    oracle.apply_diag2(ref, 3, 4, G.CZ_DIAG)
+    oracle.apply_diag2(ref, 7, 0, G.cphase_diag(1.3))
+    oracle.apply_swap(ref, 1, 6)
+    oracle.apply_kq(ref, [2, 5], G.ISWAP)
+    oracle.apply_kq(ref, [0, 3, 7], G.TOFFOLI)
+    oracle.apply_kq(ref, [4, 1, 2], G.FREDKIN)
+    assert max_err(to_host(s), ref) < 1e-13
+
+
+def test_toffoli_truth_table_bit_exact():
+    from paper_2001_10554_amd.qsim import State
+    n = 5
+    for b in range(1 << n):
+        s = State(n).init_basis(b)
+        s.toffoli(4, 1, 2)
+        expect = b ^ 4 if (b >> 4) & 1 and (b >> 1) & 1 else b
+        h = to_host(s)
+        assert h[expect] == 1 and np.count_nonzero(h) == 1

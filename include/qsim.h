@@ -352,6 +352,10 @@ int qs_traj_workspace_bytes(int n, int dtype, int count, int n_traj, size_t *byt
 int qs_traj_run(int n, int dtype, const qs_gate *gates, int count, uint64_t basis_index, int n_traj,
                 double p_depol, uint64_t seed, const qs_traj_out *out, void *ws, size_t ws_bytes, void *stream);
 
+/* Device workspace for qs_traj_run_noise: qs_traj_workspace_bytes plus one
+ * 2x2 matrix per (trajectory, noise gate of the list). */
+int qs_traj_noise_workspace_bytes(int n, int dtype, const qs_gate *gates, int count, int n_traj, size_t *bytes);
+
 /* Noise models of a trajectory run. */
 typedef struct qs_noise {
     double p_depol; /* Pauli insertion probability per touched qubit after each gate, as in qs_traj_run */

@@ -8,11 +8,22 @@
 namespace qs {
 
 // A gate of a pass, with its qubits also given as tile-bit positions.
+//
+// Sweeps: the gates of a pass are further cut into runs whose non-diagonal
+// targets (1Q / noise target, C1Q target, both SWAP qubits) lie in at most
+// three tile bits, the sweep's group bits g[0] < g[1] < g[2].  A sweep is
+// applied to groups of 8 amplitudes that differ only in those bits, held in
+// registers: one LDS read, one LDS write and one barrier per sweep instead of
+// per gate.  Diagonal gates and the controls of C1Q gates may sit on any bit.
 struct DGate {
     int32_t kind;
     int8_t p0, p1;  // tile-bit positions of q0 / q1, -1 when outside the tile
     int8_t q0, q1;
-    int32_t pad;
+    int8_t s0, s1;  // group slot (0..2) of p0 / p1 in the gate's sweep, -1 if not a group bit
+    int8_t g[3];    // first gate of a sweep: the group bits (ascending); unused otherwise
+    int8_t pad0;
+    int16_t run;    // first gate of a sweep: gates in the sweep; 0 for the others
+    int16_t nidx;   // noise gates: index among the list's noise gates
     double u[8];
 };
 
@@ -30,7 +41,8 @@ inline int tile_bits_max(int dtype) { return dtype == QS_C128 ? 12 : 13; }
 // Greedy split of a gate list into passes: a pass takes the longest prefix of
 // the remaining gates whose targets (1Q target, C1Q target, both SWAP qubits)
 // fit in a tile of tile_bits_max(dtype) qubits that also holds the lowest
-// qubits; diagonal gates and controls outside the tile ride along.
+// qubits; diagonal gates and controls outside the tile ride along.  Each
+// pass of at least 3 tile bits is then cut into sweeps (see DGate).
 void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg);
 
 template <typename R> __device__ __forceinline__ Mat2<R> load_mat(const double *u) {
@@ -84,13 +96,17 @@ __device__ __forceinline__ void lds_apply_gate(cx<R> *sh, u64 TS, u64 base, int 
             sh[m1] = b;
         }
     } else if (kind == QS_G_DIAG2) {
+        cx<R> d[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            d[e].x = (R)u[2 * e];
+            d[e].y = (R)u[2 * e + 1];
+        }
         for (u64 mm = threadIdx.x; mm < TS; mm += NT) {
             const int b0 = p0 >= 0 ? (int)((mm >> p0) & 1) : (int)((base >> q0) & 1);
             const int b1 = p1 >= 0 ? (int)((mm >> p1) & 1) : (int)((base >> q1) & 1);
             const int e = 2 * b1 + b0;
-            cx<R> f;
-            f.x = (R)u[2 * e];
-            f.y = (R)u[2 * e + 1];
+            const cx<R> f = e == 0 ? d[0] : e == 1 ? d[1] : e == 2 ? d[2] : d[3];
             sh[mm] = cmul<R>(sh[mm], f);
         }
     } else if (kind == QS_G_SWAP) {
@@ -104,6 +120,188 @@ __device__ __forceinline__ void lds_apply_gate(cx<R> *sh, u64 TS, u64 base, int 
         }
     }
     __syncthreads();
+}
+
+// ------------------------------------------------------------------ sweeps in registers
+
+// Tile index of amplitude j (0..7) of a group whose slot bits are clear in m0.
+__device__ __forceinline__ u32 grp_off(int j, int g0, int g1, int g2) {
+    return ((u32)(j & 1) << g0) | ((u32)((j >> 1) & 1) << g1) | ((u32)((j >> 2) & 1) << g2);
+}
+
+template <typename R, int S> __device__ __forceinline__ void regs_2x2(cx<R> *v, const Mat2<R> &m) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (!((j >> S) & 1)) apply2<R>(m, v[j], v[j | (1 << S)]);
+}
+
+// Controlled: the pair (j, j | 1 << S) changes iff the control bit of its
+// tile index equals cval (both members share the control bit).
+template <typename R, int S>
+__device__ __forceinline__ void regs_c2x2(cx<R> *v, const Mat2<R> &m, u32 m0, int g0, int g1, int g2, int pc, int cval) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (!((j >> S) & 1))
+            if ((int)(((m0 | grp_off(j, g0, g1, g2)) >> pc) & 1u) == cval) apply2<R>(m, v[j], v[j | (1 << S)]);
+}
+
+template <typename R> __device__ __forceinline__ void swap2(cx<R> &a, cx<R> &b) {
+    const cx<R> t = a;
+    a = b;
+    b = t;
+}
+
+// The 2x2 matrix (1Q, C1Q) or the 4 diagonal entries (DIAG2) of a gate.
+template <typename R> struct GateVals {
+    Mat2<R> m;
+    cx<R> d[4];
+};
+
+template <typename R> __device__ __forceinline__ GateVals<R> gate_vals(int kind, const double *u) {
+    GateVals<R> gv;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) gv.m.m[k] = (R)u[k];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        gv.d[e].x = (R)u[2 * e];
+        gv.d[e].y = (R)u[2 * e + 1];
+    }
+    return gv;
+}
+
+// One gate of a sweep on one group.  base: the pass's fixed bits (for qubits
+// outside the tile).
+template <typename R>
+__device__ __forceinline__ void regs_apply_gate(cx<R> *v, u32 m0, int g0, int g1, int g2, u64 base, int kind, int p0, int p1, int q0,
+                                                int q1, int s0, int s1, int cval, const GateVals<R> &gv) {
+    const Mat2<R> &m = gv.m;
+    if (kind == QS_G_1Q || (kind == QS_G_C1Q && p0 < 0)) {
+        if (kind == QS_G_C1Q && (int)((base >> q0) & 1ull) != cval) return;
+        const int S = kind == QS_G_1Q ? s0 : s1;
+        if (S == 0) regs_2x2<R, 0>(v, m);
+        else if (S == 1) regs_2x2<R, 1>(v, m);
+        else regs_2x2<R, 2>(v, m);
+    } else if (kind == QS_G_C1Q) {
+        if (s1 == 0) regs_c2x2<R, 0>(v, m, m0, g0, g1, g2, p0, cval);
+        else if (s1 == 1) regs_c2x2<R, 1>(v, m, m0, g0, g1, g2, p0, cval);
+        else regs_c2x2<R, 2>(v, m, m0, g0, g1, g2, p0, cval);
+    } else if (kind == QS_G_DIAG2) {
+        const int c0 = p0 < 0 ? (int)((base >> q0) & 1ull) : 0, c1 = p1 < 0 ? (int)((base >> q1) & 1ull) : 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const u32 idx = m0 | grp_off(j, g0, g1, g2);
+            const int b0 = p0 < 0 ? c0 : (int)((idx >> p0) & 1u), b1 = p1 < 0 ? c1 : (int)((idx >> p1) & 1u);
+            const int e = 2 * b1 + b0;
+            const cx<R> f = e == 0 ? gv.d[0] : e == 1 ? gv.d[1] : e == 2 ? gv.d[2] : gv.d[3];
+            v[j] = cmul<R>(v[j], f);
+        }
+    } else if (kind == QS_G_SWAP) {
+        const int a = s0 < s1 ? s0 : s1, b = s0 < s1 ? s1 : s0;
+        if (a == 0 && b == 1) { swap2<R>(v[1], v[2]); swap2<R>(v[5], v[6]); }
+        else if (a == 0) { swap2<R>(v[1], v[4]); swap2<R>(v[3], v[6]); }
+        else { swap2<R>(v[2], v[4]); swap2<R>(v[3], v[5]); }
+    }
+}
+
+// A gate staged in LDS, ready to apply: kind 0 = skip; val = the 2x2 matrix
+// (1Q, C1Q) or the 4 diagonal entries (DIAG2), interleaved (re, im).
+template <typename R> struct SGate {
+    int8_t kind, p0, p1, q0, q1, s0, s1, cval;
+    int8_t g[3], pad0;
+    int16_t run, pad1;
+    R val[8];
+};
+
+// Gates are staged in LDS this many at a time (and sweeps hold at most this
+// many gates), so their parameters are fetched by all threads at once rather
+// than one dependent global load per gate.
+constexpr int kStage = 64;
+
+// Sweeps of one pass on the LDS tile `sh` (2^tb amplitudes, fixed bits
+// `base`), block size NT, at most GMAX groups of 8 per thread.
+// prep(gidx, gate, vals, cval, kind) fills a gate's values and may skip it
+// (return false) or change its kind / control value.
+template <typename R, int NT, int GMAX, typename Prep>
+__device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 base, const DGate *__restrict__ gates, int begin, int count,
+                                           Prep prep) {
+    const u32 groups = 1u << (tb - 3);
+    int cb = 0, ce = 0;
+    auto stage = [&](int at) {
+        const int cnt = count - at < kStage ? count - at : kStage;
+        __syncthreads();  // every thread is done with the previous chunk
+        if ((int)threadIdx.x < cnt) {
+            const DGate &x = gates[begin + at + threadIdx.x];
+            GateVals<R> gv;
+            int cval = 1, kind = x.kind;
+            if (!prep(begin + at + (int)threadIdx.x, x, gv, cval, kind)) kind = 0;
+            SGate<R> o;
+            o.kind = (int8_t)kind;
+            o.p0 = x.p0;
+            o.p1 = x.p1;
+            o.q0 = x.q0;
+            o.q1 = x.q1;
+            o.s0 = x.s0;
+            o.s1 = x.s1;
+            o.cval = (int8_t)cval;
+            o.g[0] = x.g[0];
+            o.g[1] = x.g[1];
+            o.g[2] = x.g[2];
+            o.run = x.run;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const cx<R> d = gv.d[e];
+                o.val[2 * e] = kind == QS_G_DIAG2 ? d.x : gv.m.m[2 * e];
+                o.val[2 * e + 1] = kind == QS_G_DIAG2 ? d.y : gv.m.m[2 * e + 1];
+            }
+            sg[threadIdx.x] = o;
+        }
+        cb = at;
+        ce = at + cnt;
+        __syncthreads();
+    };
+    int gi = 0;
+    while (gi < count) {
+        if (gi >= ce) stage(gi);
+        if (gi + sg[gi - cb].run > ce) stage(gi);
+        const SGate<R> &h = sg[gi - cb];
+        const int run = h.run, g0 = h.g[0], g1 = h.g[1], g2 = h.g[2];
+        cx<R> v[GMAX][8];
+        u32 m0[GMAX];
+#pragma unroll
+        for (int k = 0; k < GMAX; ++k) {
+            const u32 grp = threadIdx.x + (u32)k * NT;
+            m0[k] = (u32)insert0(insert0(insert0(grp, g0), g1), g2);
+            if (grp < groups) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[k][j] = sh[m0[k] | grp_off(j, g0, g1, g2)];
+            }
+        }
+        for (int r = 0; r < run; ++r) {
+            const SGate<R> &x = sg[gi - cb + r];
+            if (!x.kind) continue;
+            GateVals<R> gv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) gv.m.m[e] = x.val[e];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                gv.d[e].x = x.val[2 * e];
+                gv.d[e].y = x.val[2 * e + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < GMAX; ++k)
+                if (threadIdx.x + (u32)k * NT < groups)
+                    regs_apply_gate<R>(v[k], m0[k], g0, g1, g2, base, x.kind, x.p0, x.p1, x.q0, x.q1, x.s0, x.s1, x.cval, gv);
+        }
+#pragma unroll
+        for (int k = 0; k < GMAX; ++k) {
+            if (threadIdx.x + (u32)k * NT < groups) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) sh[m0[k] | grp_off(j, g0, g1, g2)] = v[k][j];
+            }
+        }
+        __syncthreads();
+        gi += run;
+    }
 }
 
 }  // namespace qs

@@ -26,6 +26,7 @@ namespace qs {
 template <typename R, int TBMAX>
 __global__ __launch_bounds__(kBlock) void k_tile_pass(cx<R> *__restrict__ psi, DPass P, const DGate *__restrict__ gates) {
     __shared__ cx<R> sh[1 << TBMAX];
+    __shared__ SGate<R> sg[kStage];
     const int tb = P.tb;
     const u64 TS = 1ull << tb;
     u64 base = 0;
@@ -38,9 +39,17 @@ __global__ __launch_bounds__(kBlock) void k_tile_pass(cx<R> *__restrict__ psi, D
     }
     __syncthreads();
 
-    for (int gi = 0; gi < P.gate_count; ++gi) {
-        const DGate &g = gates[P.gate_begin + gi];
-        lds_apply_gate<R, kBlock>(sh, TS, base, g.kind, g.p0, g.p1, g.q0, g.q1, 1, g.u);
+    if (tb >= 3) {
+        run_sweeps<R, kBlock, (1 << (TBMAX - 3)) / kBlock>(sh, sg, tb, base, gates, P.gate_begin, P.gate_count,
+                                                            [](int, const DGate &x, GateVals<R> &gv, int &, int &) {
+                                                                gv = gate_vals<R>(x.kind, x.u);
+                                                                return true;
+                                                            });
+    } else {
+        for (int gi = 0; gi < P.gate_count; ++gi) {
+            const DGate &g = gates[P.gate_begin + gi];
+            lds_apply_gate<R, kBlock>(sh, TS, base, g.kind, g.p0, g.p1, g.q0, g.q1, 1, g.u);
+        }
     }
 
     for (u64 m = threadIdx.x; m < TS; m += kBlock) {
@@ -61,12 +70,54 @@ struct PlanCache {
     std::unordered_map<std::string, Plan> plans;
 };
 
+// Cut a pass's gates into sweeps: maximal runs whose non-diagonal targets
+// span at most 3 tile bits, padded with the lowest free tile bits.
+static void make_sweeps(int tb, DGate *d, int cnt) {
+    int i = 0;
+    while (i < cnt) {
+        int gp[3], ng = 0;
+        auto has = [&](int p) {
+            for (int a = 0; a < ng; ++a)
+                if (gp[a] == p) return true;
+            return false;
+        };
+        int j = i;
+        for (; j < cnt; ++j) {
+            int need[2], nn = 0;
+            const int k = d[j].kind;
+            if (k == QS_G_1Q || k == QS_G_NOISE) need[nn++] = d[j].p0;
+            else if (k == QS_G_C1Q) need[nn++] = d[j].p1;
+            else if (k == QS_G_SWAP) { need[nn++] = d[j].p0; need[nn++] = d[j].p1; }
+            int fresh = 0;
+            for (int a = 0; a < nn; ++a) fresh += !has(need[a]) && !(a == 1 && need[1] == need[0]);
+            if (ng + fresh > 3 || j - i == kStage) break;
+            for (int a = 0; a < nn; ++a)
+                if (!has(need[a])) gp[ng++] = need[a];
+        }
+        for (int p = 0; ng < 3 && p < tb; ++p)
+            if (!has(p)) gp[ng++] = p;
+        std::sort(gp, gp + 3);
+        auto slot = [&](int p) -> int8_t {
+            for (int a = 0; a < 3; ++a)
+                if (gp[a] == p) return (int8_t)a;
+            return (int8_t)-1;
+        };
+        d[i].run = (int16_t)(j - i);
+        for (int a = 0; a < 3; ++a) d[i].g[a] = (int8_t)gp[a];
+        for (int t = i; t < j; ++t) {
+            d[t].s0 = d[t].p0 >= 0 ? slot(d[t].p0) : (int8_t)-1;
+            d[t].s1 = d[t].p1 >= 0 ? slot(d[t].p1) : (int8_t)-1;
+        }
+        i = j;
+    }
+}
+
 // Split the list into passes (see the file comment) and encode each gate's
 // qubits as tile-bit positions of its pass.
 void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg) {
     const int tbmax = std::min(tile_bits_max(dtype), n);
     const int r = std::min(dtype == QS_C128 ? 3 : 4, tbmax);  // contiguous low qubits: 128-byte rows
-    int k = 0;
+    int k = 0, nnoise = 0;
     while (k < count) {
         u64 T = (1ull << r) - 1;
         int begin = k;
@@ -104,8 +155,12 @@ void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass>
             d.p0 = (int8_t)pos[g[j].q0];
             d.p1 = (int8_t)(one ? -1 : pos[g[j].q1]);
             memcpy(d.u, g[j].u, sizeof(d.u));
+            d.s0 = d.s1 = -1;
+            d.nidx = (int16_t)nnoise;
+            if (g[j].kind == QS_G_NOISE) ++nnoise;
             dg.push_back(d);
         }
+        if (P.tb >= 3) make_sweeps(P.tb, dg.data() + P.gate_begin, P.gate_count);
         passes.push_back(P);
     }
 }

@@ -122,12 +122,31 @@ __device__ __forceinline__ void noise_matrix(double *u, double d, double inv_T1,
     u[6] = cz * m11r - sz * m11i; u[7] = cz * m11i + sz * m11r;
 }
 
+// Noise matrices of every (noisy trajectory, noise gate), computed once:
+// nm[(t * nnoise + nidx) * 8].
+__global__ void k_traj_noise_mats(const DGate *__restrict__ gates, int count, int n_traj, int nnoise, u32 k0, u32 k1, double inv_T1,
+                                  double inv_T2, double *__restrict__ nm) {
+    const u64 id = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (u64)n_traj * count) return;
+    const u32 t = (u32)(id / count), gidx = (u32)(id % count);
+    const DGate &g = gates[gidx];
+    if (g.kind != QS_G_NOISE) return;
+    double u[8];
+    noise_matrix(u, g.u[0], inv_T1, inv_T2, t, gidx, k0, k1);
+    double *o = nm + ((u64)t * nnoise + g.nidx) * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = u[k];
+}
+
+// One pass of every simulated trajectory: block = (trajectory, tile).  Gates
+// act on the stored state as F^dagger G F for the trajectory's frame F before
+// the gate; sweeps of gates run in registers (see DGate).
 template <typename R, int TBMAX>
 __global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states, u64 N, int tiles_log2, DPass P, const DGate *__restrict__ gates,
                                                       const uint64_t *__restrict__ frames, int count, int first_pass, u64 basis,
-                                                      const int32_t *__restrict__ nins, int n_traj, u32 k0, u32 k1, double inv_T1,
-                                                      double inv_T2) {
+                                                      const int32_t *__restrict__ nins, int n_traj, const double *__restrict__ nm, int nnoise) {
     __shared__ cx<R> sh[1 << TBMAX];
+    __shared__ SGate<R> sg[kStage];
     const u64 tile = blockIdx.x & ((1ull << tiles_log2) - 1);
     const u64 t = blockIdx.x >> tiles_log2;
     if (!traj_simulated(nins, t, n_traj)) return;  // whole block: shares the noiseless state
@@ -146,33 +165,63 @@ __global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states
         sh[m] = v;
     }
     __syncthreads();
-    for (int gi = 0; gi < P.gate_count; ++gi) {
-        const int gidx = P.gate_begin + gi;
-        const DGate &g = gates[gidx];
+    const bool ideal = t == (u64)n_traj;
+    auto prep = [&](int gidx, const DGate &g, GateVals<R> &gv, int &cval, int &kind) -> bool {
         const u64 f = frames[t * count + gidx];
         const u32 a = (u32)f, b = (u32)(f >> 32);
         double u[8];
-        for (int k = 0; k < 8; ++k) u[k] = g.u[k];
-        int cval = 1, kind = g.kind;
         if (kind == QS_G_NOISE) {
-            if (t == (u64)n_traj) continue;  // the noiseless reference run
-            noise_matrix(u, g.u[0], inv_T1, inv_T2, (u32)t, (u32)gidx, k0, k1);
+            if (ideal) return false;  // the noiseless reference run
+            const double *src = nm + ((u64)t * nnoise + g.nidx) * 8;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = src[k];
             conj_pauli(u, (a >> g.q0) & 1, (b >> g.q0) & 1);
             kind = QS_G_1Q;
-        } else if (g.kind == QS_G_1Q) {
-            conj_pauli(u, (a >> g.q0) & 1, (b >> g.q0) & 1);
-        } else if (g.kind == QS_G_C1Q) {
-            cval = 1 ^ (int)((a >> g.q0) & 1);
-            conj_pauli(u, (a >> g.q1) & 1, (b >> g.q1) & 1);
-        } else if (g.kind == QS_G_DIAG2) {
-            const int x0 = (a >> g.q0) & 1, x1 = (a >> g.q1) & 1;
-            for (int e = 0; e < 4; ++e) {
-                const int src = ((((e >> 1) ^ x1) << 1) | ((e & 1) ^ x0));
-                u[2 * e] = g.u[2 * src];
-                u[2 * e + 1] = g.u[2 * src + 1];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = g.u[k];
+            if (kind == QS_G_1Q) {
+                conj_pauli(u, (a >> g.q0) & 1, (b >> g.q0) & 1);
+            } else if (kind == QS_G_C1Q) {
+                cval = 1 ^ (int)((a >> g.q0) & 1);
+                conj_pauli(u, (a >> g.q1) & 1, (b >> g.q1) & 1);
             }
         }
-        lds_apply_gate<R, kBlock>(sh, TS, base, kind, g.p0, g.p1, g.q0, g.q1, cval, u);
+        gv = gate_vals<R>(kind, u);
+        if (kind == QS_G_DIAG2) {  // entries permuted by the frame's X part on q0 / q1
+            if ((a >> g.q0) & 1) {
+                swap2<R>(gv.d[0], gv.d[1]);
+                swap2<R>(gv.d[2], gv.d[3]);
+            }
+            if ((a >> g.q1) & 1) {
+                swap2<R>(gv.d[0], gv.d[2]);
+                swap2<R>(gv.d[1], gv.d[3]);
+            }
+        }
+        return true;
+    };
+    if (P.tb >= 3) {
+        run_sweeps<R, kBlock, (1 << (TBMAX - 3)) / kBlock>(sh, sg, P.tb, base, gates, P.gate_begin, P.gate_count, prep);
+    } else {
+        for (int gi = 0; gi < P.gate_count; ++gi) {
+            const int gidx = P.gate_begin + gi;
+            const DGate &g = gates[gidx];
+            GateVals<R> gv;
+            int cval = 1, kind = g.kind;
+            if (!prep(gidx, g, gv, cval, kind)) continue;
+            double u[8];
+            if (kind == QS_G_DIAG2) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    u[2 * e] = (double)gv.d[e].x;
+                    u[2 * e + 1] = (double)gv.d[e].y;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) u[k] = (double)gv.m.m[k];
+            }
+            lds_apply_gate<R, kBlock>(sh, TS, base, kind, g.p0, g.p1, g.q0, g.q1, cval, u);
+        }
     }
     for (u64 m = threadIdx.x; m < TS; m += kBlock) st<true>(psi + (base | pass_off(P, m)), sh[m]);
 }
@@ -319,11 +368,18 @@ __global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restri
 // ------------------------------------------------------------------ host side
 
 struct TrajLayout {
-    size_t states, frames, final_frame, nins, pzf, px, gates, dgates, total;
+    size_t states, frames, final_frame, nins, pzf, px, gates, dgates, nm, total;
     int chunk_log2, chunks_log2;
 };
 
-static TrajLayout traj_layout(int n, int dtype, int count, int n_traj) {
+static int count_noise(const qs_gate *gates, int count) {
+    int c = 0;
+    for (int k = 0; k < count; ++k) c += gates[k].kind == QS_G_NOISE;
+    return c;
+}
+
+// nnoise: noise gates in the list (their matrices are stored per trajectory).
+static TrajLayout traj_layout(int n, int dtype, int count, int n_traj, int nnoise) {
     TrajLayout L{};
     const u64 N = 1ull << n;
     auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -346,6 +402,8 @@ static TrajLayout traj_layout(int n, int dtype, int count, int n_traj) {
     off = align(off + (size_t)count * sizeof(TGate));
     L.dgates = off;
     off = align(off + (size_t)count * sizeof(DGate));
+    L.nm = off;
+    off = align(off + (size_t)n_traj * nnoise * 8 * sizeof(double));
     L.total = off;
     return L;
 }
@@ -353,7 +411,8 @@ static TrajLayout traj_layout(int n, int dtype, int count, int n_traj) {
 template <typename R, int TBMAX>
 static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 basis, int n_traj, double p, double inv_T1, double inv_T2, u64 seed,
                       const qs_traj_out *out, char *ws, hipStream_t st) {
-    const TrajLayout L = traj_layout(n, dtype, count, n_traj);
+    const int nnoise = count_noise(gates, count);
+    const TrajLayout L = traj_layout(n, dtype, count, n_traj, nnoise);
     const u64 N = 1ull << n;
     std::vector<DPass> passes;
     std::vector<DGate> dg;
@@ -374,6 +433,13 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
                        (u32)seed, (u32)(seed >> 32), frames, final_frame, nins, out->counts, out->log, out->log ? out->log_cap : 0,
                        noisy_gates ? 1 : 0);
     QS_LAUNCH_CHECK("traj_frames");
+    double *nm = (double *)(ws + L.nm);
+    if (nnoise) {
+        const u64 work = (u64)n_traj * count;
+        hipLaunchKernelGGL(k_traj_noise_mats, dim3(grid_for(work, 256)), dim3(256), 0, st, (const DGate *)(ws + L.dgates), count, n_traj, nnoise,
+                           (u32)seed, (u32)(seed >> 32), inv_T1, inv_T2, nm);
+        QS_LAUNCH_CHECK("traj_noise_mats");
+    }
     cx<R> *states = (cx<R> *)(ws + L.states);
     const int T1 = n_traj + 1;
     bool first = true;
@@ -381,8 +447,7 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
         const int tiles_log2 = P.nrest;
         const u64 blocks = (u64)T1 << tiles_log2;
         hipLaunchKernelGGL((k_traj_pass<R, TBMAX>), dim3((unsigned)blocks), dim3(kBlock), 0, st, states, N, tiles_log2, P, (const DGate *)(ws + L.dgates),
-                           (const uint64_t *)frames, count, first ? 1 : 0, basis, (const int32_t *)nins, n_traj, (u32)seed, (u32)(seed >> 32),
-                           inv_T1, inv_T2);
+                           (const uint64_t *)frames, count, first ? 1 : 0, basis, (const int32_t *)nins, n_traj, (const double *)nm, nnoise);
         QS_LAUNCH_CHECK("traj_pass");
         first = false;
     }
@@ -429,7 +494,8 @@ static int traj_run_any(int n, int dtype, const qs_gate *gates, int count, u64 b
     if (!(nz.p_depol >= 0.0 && nz.p_depol <= 1.0)) return fail(QS_ERR_ARG, "p must be in [0, 1]");
     if (!(nz.T1 > 0.0) || !(nz.T2 > 0.0) || !(nz.T2 <= 2.0 * nz.T1)) return fail(QS_ERR_ARG, "need T1 > 0 and 0 < T2 <= 2 T1");
     if (int rc = validate_gates(n, gates, count, true)) return rc;
-    if (ws_bytes < traj_layout(n, dtype, count, n_traj).total) return fail(QS_ERR_SIZE, "trajectory workspace too small");
+    if (ws_bytes < traj_layout(n, dtype, count, n_traj, count_noise(gates, count)).total)
+        return fail(QS_ERR_SIZE, "trajectory workspace too small");
     const double inv_T1 = nz.T1 < INFINITY ? 1.0 / nz.T1 : 0.0, inv_T2 = nz.T2 < INFINITY ? 1.0 / nz.T2 : 0.0;
     hipStream_t st = (hipStream_t)stream;
     return dtype == QS_C128
@@ -446,7 +512,16 @@ QS_API int qs_traj_workspace_bytes(int n, int dtype, int count, int n_traj, size
     if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_ERR_DTYPE, "dtype must be QS_C64 or QS_C128");
     if (n < 1 || n > kTrajMaxQubits) return fail(QS_ERR_ARG, "trajectories need 1 <= n <= 20");
     if (count < 1 || count > kTrajMaxGates || n_traj < 1) return fail(QS_ERR_ARG, "bad gate or trajectory count");
-    *bytes = traj_layout(n, dtype, count, n_traj).total;
+    *bytes = traj_layout(n, dtype, count, n_traj, 0).total;
+    return QS_OK;
+}
+
+QS_API int qs_traj_noise_workspace_bytes(int n, int dtype, const qs_gate *gates, int count, int n_traj, size_t *bytes) {
+    if (!bytes || !gates) return fail(QS_ERR_ARG, "null output or gate list");
+    if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_ERR_DTYPE, "dtype must be QS_C64 or QS_C128");
+    if (n < 1 || n > kTrajMaxQubits) return fail(QS_ERR_ARG, "trajectories need 1 <= n <= 20");
+    if (count < 1 || count > kTrajMaxGates || n_traj < 1) return fail(QS_ERR_ARG, "bad gate or trajectory count");
+    *bytes = traj_layout(n, dtype, count, n_traj, count_noise(gates, count)).total;
     return QS_OK;
 }
 

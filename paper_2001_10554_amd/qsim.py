@@ -111,6 +111,7 @@ def lib():
             "qs_traj_workspace_bytes": [i, i, i, i, vp],
             "qs_traj_run": [i, i, vp, i, u64, i, d, u64, vp, vp, sz, vp],
             "qs_traj_run_noise": [i, i, vp, i, u64, i, vp, u64, vp, vp, sz, vp],
+            "qs_traj_noise_workspace_bytes": [i, i, vp, i, i, vp],
         }
         for name, args in sigs.items():
             f = getattr(L, name, None)
@@ -459,7 +460,7 @@ def traj_run(n: int, gates: np.ndarray, basis_index: int, n_traj: int, p: float,
     g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
     code = QS_C128 if dtype == torch.complex128 else QS_C64
     nbytes = ctypes.c_size_t()
-    check(lib().qs_traj_workspace_bytes(n, code, len(g), n_traj, ctypes.byref(nbytes)))
+    check(lib().qs_traj_noise_workspace_bytes(n, code, _ptr(g), len(g), n_traj, ctypes.byref(nbytes)))
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
     f64 = dict(dtype=torch.float64, device=device)
     res = {"z": torch.empty(n_traj, n, **f64), "x": torch.empty(n_traj, n, **f64), "fid": torch.empty(n_traj, **f64),

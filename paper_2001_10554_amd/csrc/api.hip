@@ -41,8 +41,7 @@ int make_graph(int n, const int32_t *edges, const double *w, int ne, Graph &g, W
     for (int e = 0; e < ne; ++e) {
         const int a = edges[2 * e], b = edges[2 * e + 1];
         if (a < 0 || b < 0 || a >= n || b >= n || a == b) return fail(QS_ERR_ARG, "edge endpoint out of range or self-loop");
-        g.u[e] = (uint8_t)a;
-        g.v[e] = (uint8_t)b;
+        g.uv[e] = pack_edge(a, b);
         if (w) wt.w[e] = w[e];
     }
     return QS_OK;

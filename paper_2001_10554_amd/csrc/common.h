@@ -120,26 +120,34 @@ __device__ __forceinline__ double u53(u32 lo, u32 hi) {
 
 // ------------------------------------------------------------------ Max-Cut graph (kernel argument)
 constexpr int kMaxEdges = 256;
+// Edge e joins qubits uv[e] & 0xff and uv[e] >> 8.  Packed into dwords so a
+// kernel reads an edge with one scalar load (there is no scalar byte load).
 struct Graph {
     int ne;
     int weighted;
-    uint8_t u[kMaxEdges], v[kMaxEdges];
+    uint32_t uv[kMaxEdges];
 };
 struct Weights {
     double w[kMaxEdges];
 };
+__host__ __device__ inline uint32_t pack_edge(int a, int b) { return (uint32_t)a | ((uint32_t)b << 8); }
 
 // C(k) for unit weights: number of edges cut by bipartition k.
 __device__ __forceinline__ int cut_count(u64 k, const Graph &g) {
     int c = 0;
-    for (int e = 0; e < g.ne; ++e) c += (int)(((k >> g.u[e]) ^ (k >> g.v[e])) & 1u);
+    for (int e = 0; e < g.ne; ++e) {
+        const uint32_t x = g.uv[e];
+        c += (int)(((k >> (x & 0xffu)) ^ (k >> (x >> 8))) & 1u);
+    }
     return c;
 }
 
 __device__ __forceinline__ double cut_weighted(u64 k, const Graph &g, const double *w) {
     double c = 0.0;
-    for (int e = 0; e < g.ne; ++e)
-        if (((k >> g.u[e]) ^ (k >> g.v[e])) & 1u) c += w[e];
+    for (int e = 0; e < g.ne; ++e) {
+        const uint32_t x = g.uv[e];
+        if (((k >> (x & 0xffu)) ^ (k >> (x >> 8))) & 1u) c += w[e];
+    }
     return c;
 }
 

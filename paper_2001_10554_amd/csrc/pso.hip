@@ -208,8 +208,7 @@ QS_API int qs_cut_max(const qs_pool_desc *d, const double *w, double *max_dev, u
             for (int e = 0; e < ne; ++e) {
                 const int a = d->edges[2 * (e0 + e)], b = d->edges[2 * (e0 + e) + 1];
                 if (a < 0 || b < 0 || a >= n || b >= n || a == b) return fail(QS_ERR_ARG, "cut max: edge out of range or self-loop");
-                g.u[e] = (uint8_t)a;
-                g.v[e] = (uint8_t)b;
+                g.uv[e] = pack_edge(a, b);
                 W.w[e] = w ? w[e0 + e] : 1.0;
             }
             const u64 half = 1ull << (n - 1);

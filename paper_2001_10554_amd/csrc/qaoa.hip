@@ -116,15 +116,22 @@ __device__ __forceinline__ void cut_values(const QPass &P, int list, const QWeig
     }
 }
 
+// Bit deposits through the pass's qubit maps, over the arrays' full static
+// length: each entry is read at a fixed kernel-argument offset (hoisted scalar
+// loads) instead of one dependent memory access per bit.
 __device__ __forceinline__ u64 qtile_base(const QPass &P, u64 tile) {
     u64 base = 0;
-    for (int b = 0; b < P.nrest; ++b) base |= ((tile >> b) & 1ull) << P.rest[b];
+#pragma unroll
+    for (int b = 0; b < 40; ++b)
+        if (b < P.nrest) base |= ((tile >> b) & 1ull) << P.rest[b];
     return base;
 }
 
 __device__ __forceinline__ u64 qtile_off(const QPass &P, u64 m) {
     u64 off = 0;
-    for (int b = 0; b < P.tb; ++b) off |= ((m >> b) & 1ull) << P.T[b];
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+        if (b < P.tb) off |= ((m >> b) & 1ull) << P.T[b];
     return off;
 }
 

@@ -7,6 +7,11 @@
 
 namespace qs {
 
+// Threads of an LDS-pass workgroup: one 8-amplitude register group each for a
+// 12-bit c128 tile (two for a 13-bit c64 tile), and 8 waves per workgroup so
+// that LDS and barrier latency is hidden within the CU.
+constexpr int kTileThreads = 512;
+
 // A gate of a pass, with its qubits also given as tile-bit positions.
 //
 // Sweeps: the gates of a pass are further cut into runs whose non-diagonal
@@ -34,9 +39,12 @@ struct DPass {
     uint8_t T[16];     // tile bit -> qubit (ascending)
     uint8_t rest[40];  // remaining bits -> qubit (ascending)
     int gate_begin, gate_count;
+    u64 hi[16];        // state offset of tile index k * kTileThreads (its bits are tile bits >= 9)
 };
 
 inline int tile_bits_max(int dtype) { return dtype == QS_C128 ? 12 : 13; }
+
+
 
 // Greedy split of a gate list into passes: a pass takes the longest prefix of
 // the remaining gates whose targets (1Q target, C1Q target, both SWAP qubits)
@@ -45,6 +53,14 @@ inline int tile_bits_max(int dtype) { return dtype == QS_C128 ? 12 : 13; }
 // pass of at least 3 tile bits is then cut into sweeps (see DGate).
 void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg);
 
+// LDS tiles are stored swizzled: amplitude m of a tile sits at slot swz(m),
+// the low 3 bits (the 16-byte slot within a 128-byte row) XORed with bits
+// 3..5.  Any 8 consecutive lanes then touch 8 distinct slots of a row, also
+// when each lane walks 8 consecutive amplitudes (a sweep over the lowest tile
+// bits), which would otherwise put every lane of a b128 access on the same
+// banks.  A bijection on [0, 2^tb) for every tb.
+__device__ __forceinline__ u32 swz(u64 m) { return (u32)m ^ ((u32)(m >> 3) & 7u); }
+
 template <typename R> __device__ __forceinline__ Mat2<R> load_mat(const double *u) {
     Mat2<R> m;
 #pragma unroll
@@ -52,15 +68,23 @@ template <typename R> __device__ __forceinline__ Mat2<R> load_mat(const double *
     return m;
 }
 
+// Bit deposits through the pass's qubit maps.  The loops run over the
+// arrays' full static length so that every entry is read at a fixed offset of
+// the kernel argument (a hoisted scalar load, not a dependent memory access
+// per bit).
 __device__ __forceinline__ u64 pass_base(const DPass &P, u64 tile) {
     u64 base = 0;
-    for (int b = 0; b < P.nrest; ++b) base |= ((tile >> b) & 1ull) << P.rest[b];
+#pragma unroll
+    for (int b = 0; b < 40; ++b)
+        if (b < P.nrest) base |= ((tile >> b) & 1ull) << P.rest[b];
     return base;
 }
 
 __device__ __forceinline__ u64 pass_off(const DPass &P, u64 m) {
     u64 off = 0;
-    for (int b = 0; b < P.tb; ++b) off |= ((m >> b) & 1ull) << P.T[b];
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+        if (b < P.tb) off |= ((m >> b) & 1ull) << P.T[b];
     return off;
 }
 
@@ -78,10 +102,10 @@ __device__ __forceinline__ void lds_apply_gate(cx<R> *sh, u64 TS, u64 base, int 
             const Mat2<R> m = load_mat<R>(u);
             for (u64 k = threadIdx.x; k < TS / 2; k += NT) {
                 const u64 m0 = insert0(k, p), m1 = m0 | (1ull << p);
-                cx<R> a = sh[m0], b = sh[m1];
+                cx<R> a = sh[swz(m0)], b = sh[swz(m1)];
                 apply2<R>(m, a, b);
-                sh[m0] = a;
-                sh[m1] = b;
+                sh[swz(m0)] = a;
+                sh[swz(m1)] = b;
             }
         }
     } else if (kind == QS_G_C1Q) {
@@ -90,10 +114,10 @@ __device__ __forceinline__ void lds_apply_gate(cx<R> *sh, u64 TS, u64 base, int 
         const u64 cbit = cval ? (1ull << p0) : 0ull;
         for (u64 k = threadIdx.x; k < TS / 4; k += NT) {
             const u64 m0 = insert0(insert0(k, lo), hi) | cbit, m1 = m0 | (1ull << p1);
-            cx<R> a = sh[m0], b = sh[m1];
+            cx<R> a = sh[swz(m0)], b = sh[swz(m1)];
             apply2<R>(m, a, b);
-            sh[m0] = a;
-            sh[m1] = b;
+            sh[swz(m0)] = a;
+            sh[swz(m1)] = b;
         }
     } else if (kind == QS_G_DIAG2) {
         cx<R> d[4];
@@ -107,19 +131,74 @@ __device__ __forceinline__ void lds_apply_gate(cx<R> *sh, u64 TS, u64 base, int 
             const int b1 = p1 >= 0 ? (int)((mm >> p1) & 1) : (int)((base >> q1) & 1);
             const int e = 2 * b1 + b0;
             const cx<R> f = e == 0 ? d[0] : e == 1 ? d[1] : e == 2 ? d[2] : d[3];
-            sh[mm] = cmul<R>(sh[mm], f);
+            sh[swz(mm)] = cmul<R>(sh[swz(mm)], f);
         }
     } else if (kind == QS_G_SWAP) {
         const int lo = p0 < p1 ? p0 : p1, hi = p0 < p1 ? p1 : p0;
         for (u64 k = threadIdx.x; k < TS / 4; k += NT) {
             const u64 b = insert0(insert0(k, lo), hi);
             const u64 i = b | (1ull << p0), j = b | (1ull << p1);
-            const cx<R> x = sh[i], y = sh[j];
-            sh[i] = y;
-            sh[j] = x;
+            const cx<R> x = sh[swz(i)], y = sh[swz(j)];
+            sh[swz(i)] = y;
+            sh[swz(j)] = x;
         }
     }
     __syncthreads();
+}
+
+// Tile load / store: each thread issues all of its global accesses before it
+// touches LDS (PER = 2^TBMAX / NT amplitudes per thread at most).  With
+// `fill`, the tile is not read but set to the basis state |basis>.
+template <typename R, int NT, int PER, bool NTEMP>
+__device__ __forceinline__ void tile_load(cx<R> *sh, const cx<R> *psi, const DPass &P, u64 base, bool fill, u64 basis) {
+    static_assert(NT == kTileThreads, "hi[] is laid out for kTileThreads");
+    // m = thread + k NT: the deposit splits into a per-thread part and the
+    // precomputed part hi[k] of the higher tile bits (disjoint bits).
+    const u64 ot = base | pass_off(P, threadIdx.x);
+    if (P.tb == 31 - __builtin_clz(PER * NT)) {  // a full tile: every slot is in range
+        cx<R> v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const u64 idx = ot | P.hi[k];
+            if (fill) {
+                v[k].x = idx == basis ? (R)1 : (R)0;
+                v[k].y = (R)0;
+            } else {
+                v[k] = NTEMP ? __builtin_nontemporal_load(psi + idx) : psi[idx];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) sh[swz(threadIdx.x + (u32)k * NT)] = v[k];
+    } else {
+        for (u32 m = threadIdx.x; m < (1u << P.tb); m += NT) {
+            const u64 idx = base | pass_off(P, m);
+            cx<R> v;
+            if (fill) {
+                v.x = idx == basis ? (R)1 : (R)0;
+                v.y = (R)0;
+            } else {
+                v = psi[idx];
+            }
+            sh[swz(m)] = v;
+        }
+    }
+}
+
+template <typename R, int NT, int PER, bool NTEMP>
+__device__ __forceinline__ void tile_store(const cx<R> *sh, cx<R> *psi, const DPass &P, u64 base) {
+    if (P.tb == 31 - __builtin_clz(PER * NT)) {
+        const u64 ot = base | pass_off(P, threadIdx.x);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const cx<R> v = sh[swz(threadIdx.x + (u32)k * NT)];
+            if (NTEMP)
+                __builtin_nontemporal_store(v, psi + (ot | P.hi[k]));
+            else
+                psi[ot | P.hi[k]] = v;
+        }
+    } else {
+        for (u32 m = threadIdx.x; m < (1u << P.tb); m += NT) psi[base | pass_off(P, m)] = sh[swz(m)];
+    }
 }
 
 // ------------------------------------------------------------------ sweeps in registers
@@ -273,7 +352,7 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
             m0[k] = (u32)insert0(insert0(insert0(grp, g0), g1), g2);
             if (grp < groups) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[k][j] = sh[m0[k] | grp_off(j, g0, g1, g2)];
+                for (int j = 0; j < 8; ++j) v[k][j] = sh[swz(m0[k] | grp_off(j, g0, g1, g2))];
             }
         }
         for (int r = 0; r < run; ++r) {
@@ -296,7 +375,7 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
         for (int k = 0; k < GMAX; ++k) {
             if (threadIdx.x + (u32)k * NT < groups) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) sh[m0[k] | grp_off(j, g0, g1, g2)] = v[k][j];
+                for (int j = 0; j < 8; ++j) sh[swz(m0[k] | grp_off(j, g0, g1, g2))] = v[k][j];
             }
         }
         __syncthreads();

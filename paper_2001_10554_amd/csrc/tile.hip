@@ -24,39 +24,27 @@
 namespace qs {
 
 template <typename R, int TBMAX>
-__global__ __launch_bounds__(kBlock) void k_tile_pass(cx<R> *__restrict__ psi, DPass P, const DGate *__restrict__ gates) {
+__global__ __launch_bounds__(kTileThreads) void k_tile_pass(cx<R> *__restrict__ psi, DPass P, const DGate *__restrict__ gates) {
+    constexpr int NT = kTileThreads, PER = (1 << TBMAX) / NT;
     __shared__ cx<R> sh[1 << TBMAX];
     __shared__ SGate<R> sg[kStage];
     const int tb = P.tb;
-    const u64 TS = 1ull << tb;
-    u64 base = 0;
-    for (int b = 0; b < P.nrest; ++b) base |= (((u64)blockIdx.x >> b) & 1ull) << P.rest[b];
-
-    for (u64 m = threadIdx.x; m < TS; m += kBlock) {
-        u64 off = base;
-        for (int b = 0; b < tb; ++b) off |= ((m >> b) & 1ull) << P.T[b];
-        sh[m] = psi[off];
-    }
+    const u64 base = pass_base(P, blockIdx.x);
+    tile_load<R, NT, PER, false>(sh, psi, P, base, false, 0);
     __syncthreads();
-
     if (tb >= 3) {
-        run_sweeps<R, kBlock, (1 << (TBMAX - 3)) / kBlock>(sh, sg, tb, base, gates, P.gate_begin, P.gate_count,
-                                                            [](int, const DGate &x, GateVals<R> &gv, int &, int &) {
-                                                                gv = gate_vals<R>(x.kind, x.u);
-                                                                return true;
-                                                            });
+        run_sweeps<R, NT, ((1 << (TBMAX - 3)) + NT - 1) / NT>(sh, sg, tb, base, gates, P.gate_begin, P.gate_count,
+                                                              [](int, const DGate &x, GateVals<R> &gv, int &, int &) {
+                                                                  gv = gate_vals<R>(x.kind, x.u);
+                                                                  return true;
+                                                              });
     } else {
         for (int gi = 0; gi < P.gate_count; ++gi) {
             const DGate &g = gates[P.gate_begin + gi];
-            lds_apply_gate<R, kBlock>(sh, TS, base, g.kind, g.p0, g.p1, g.q0, g.q1, 1, g.u);
+            lds_apply_gate<R, NT>(sh, 1ull << tb, base, g.kind, g.p0, g.p1, g.q0, g.q1, 1, g.u);
         }
     }
-
-    for (u64 m = threadIdx.x; m < TS; m += kBlock) {
-        u64 off = base;
-        for (int b = 0; b < tb; ++b) off |= ((m >> b) & 1ull) << P.T[b];
-        psi[off] = sh[m];
-    }
+    tile_store<R, NT, PER, false>(sh, psi, P, base);
 }
 
 // ------------------------------------------------------------------ planning
@@ -144,6 +132,13 @@ void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass>
                 P.rest[P.nrest++] = (uint8_t)q;
             }
         }
+        for (int k = 0; k < 16; ++k) {
+            u64 o = 0;
+            const u64 m = (u64)k * kTileThreads;
+            for (int b = 0; b < P.tb; ++b)
+                if ((m >> b) & 1) o |= 1ull << P.T[b];
+            P.hi[k] = o;
+        }
         P.gate_begin = (int)dg.size();
         P.gate_count = k - begin;
         for (int j = begin; j < k; ++j) {
@@ -191,9 +186,9 @@ int run_block(qs_state *s, const qs_gate *gates, int count) {
     for (const DPass &P : plan->passes) {
         const unsigned grid = 1u << P.nrest;
         if (s->dtype == QS_C128)
-            hipLaunchKernelGGL((k_tile_pass<double, 12>), dim3(grid), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, P, plan->dev_gates);
+            hipLaunchKernelGGL((k_tile_pass<double, 12>), dim3(grid), dim3(kTileThreads), 0, s->stream, (cx<double> *)s->buf, P, plan->dev_gates);
         else
-            hipLaunchKernelGGL((k_tile_pass<float, 13>), dim3(grid), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, P, plan->dev_gates);
+            hipLaunchKernelGGL((k_tile_pass<float, 13>), dim3(grid), dim3(kTileThreads), 0, s->stream, (cx<float> *)s->buf, P, plan->dev_gates);
         QS_LAUNCH_CHECK("tile_pass");
     }
     return QS_OK;

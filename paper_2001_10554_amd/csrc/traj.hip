@@ -142,7 +142,7 @@ __global__ void k_traj_noise_mats(const DGate *__restrict__ gates, int count, in
 // act on the stored state as F^dagger G F for the trajectory's frame F before
 // the gate; sweeps of gates run in registers (see DGate).
 template <typename R, int TBMAX>
-__global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states, u64 N, int tiles_log2, DPass P, const DGate *__restrict__ gates,
+__global__ __launch_bounds__(kTileThreads) void k_traj_pass(cx<R> *__restrict__ states, u64 N, int tiles_log2, DPass P, const DGate *__restrict__ gates,
                                                       const uint64_t *__restrict__ frames, int count, int first_pass, u64 basis,
                                                       const int32_t *__restrict__ nins, int n_traj, const double *__restrict__ nm, int nnoise) {
     __shared__ cx<R> sh[1 << TBMAX];
@@ -150,20 +150,11 @@ __global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states
     const u64 tile = blockIdx.x & ((1ull << tiles_log2) - 1);
     const u64 t = blockIdx.x >> tiles_log2;
     if (!traj_simulated(nins, t, n_traj)) return;  // whole block: shares the noiseless state
+    constexpr int NT = kTileThreads, PER = (1 << TBMAX) / NT;
     cx<R> *psi = states + t * N;
     const u64 TS = 1ull << P.tb;
     const u64 base = pass_base(P, tile);
-    for (u64 m = threadIdx.x; m < TS; m += kBlock) {
-        const u64 idx = base | pass_off(P, m);
-        cx<R> v;
-        if (first_pass) {
-            v.x = idx == basis ? (R)1 : (R)0;
-            v.y = (R)0;
-        } else {
-            v = ld<true>(psi + idx);
-        }
-        sh[m] = v;
-    }
+    tile_load<R, NT, PER, true>(sh, psi, P, base, first_pass != 0, basis);
     __syncthreads();
     const bool ideal = t == (u64)n_traj;
     auto prep = [&](int gidx, const DGate &g, GateVals<R> &gv, int &cval, int &kind) -> bool {
@@ -201,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states
         return true;
     };
     if (P.tb >= 3) {
-        run_sweeps<R, kBlock, (1 << (TBMAX - 3)) / kBlock>(sh, sg, P.tb, base, gates, P.gate_begin, P.gate_count, prep);
+        run_sweeps<R, NT, ((1 << (TBMAX - 3)) + NT - 1) / NT>(sh, sg, P.tb, base, gates, P.gate_begin, P.gate_count, prep);
     } else {
         for (int gi = 0; gi < P.gate_count; ++gi) {
             const int gidx = P.gate_begin + gi;
@@ -220,10 +211,10 @@ __global__ __launch_bounds__(kBlock) void k_traj_pass(cx<R> *__restrict__ states
 #pragma unroll
                 for (int k = 0; k < 8; ++k) u[k] = (double)gv.m.m[k];
             }
-            lds_apply_gate<R, kBlock>(sh, TS, base, kind, g.p0, g.p1, g.q0, g.q1, cval, u);
+            lds_apply_gate<R, NT>(sh, TS, base, kind, g.p0, g.p1, g.q0, g.q1, cval, u);
         }
     }
-    for (u64 m = threadIdx.x; m < TS; m += kBlock) st<true>(psi + (base | pass_off(P, m)), sh[m]);
+    tile_store<R, NT, PER, true>(sh, psi, P, base);
 }
 
 __device__ __forceinline__ double tblock_sum(double v, double *red) {
@@ -446,7 +437,7 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     for (const DPass &P : passes) {
         const int tiles_log2 = P.nrest;
         const u64 blocks = (u64)T1 << tiles_log2;
-        hipLaunchKernelGGL((k_traj_pass<R, TBMAX>), dim3((unsigned)blocks), dim3(kBlock), 0, st, states, N, tiles_log2, P, (const DGate *)(ws + L.dgates),
+        hipLaunchKernelGGL((k_traj_pass<R, TBMAX>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, states, N, tiles_log2, P, (const DGate *)(ws + L.dgates),
                            (const uint64_t *)frames, count, first ? 1 : 0, basis, (const int32_t *)nins, n_traj, (const double *)nm, nnoise);
         QS_LAUNCH_CHECK("traj_pass");
         first = false;

@@ -126,17 +126,23 @@ __device__ __forceinline__ u64 logical_block(u32 chunk) {
 // line, so the whole line is moved anyway; these kernels then stream all
 // pairs and leave the control-0 ones unchanged, keeping loads and stores
 // full-line.
+// dlog: the thread's PPT pairs are 2^dlog pairs apart (8: consecutive
+// 256-pair slices of one block); a block then covers 256 pairs in each of PPT
+// slices of a region of PPT * 2^dlog pairs.  The host uses dlog > 8 only when
+// npairs is a multiple of that region.
 template <typename R, int PPT, bool NT, bool CTRL = false>
-__global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u64 npairs, int q, Mat2<R> u, u32 chunk, int c = 0) {
+__global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u64 npairs, int q, Mat2<R> u, u32 chunk, int c = 0,
+                                                     int dlog = 8) {
     const u64 s = 1ull << q;
     const u64 lb = logical_block(chunk);
-    const u64 first = lb * (kBlock * PPT) + threadIdx.x;
+    const int rlog = dlog - 8;  // blocks per region, log2
+    const u64 first = ((lb >> rlog) * PPT << dlog) + ((lb & ((1ull << rlog) - 1)) << 8) + threadIdx.x;
     cx<R> a[PPT], b[PPT];
     u64 i0[PPT];
     if ((lb + 1) * (kBlock * PPT) <= npairs) {
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            i0[j] = insert0(first + (u64)j * kBlock, q);
+            i0[j] = insert0(first + ((u64)j << dlog), q);
             a[j] = ld<NT>(psi + i0[j]);
             b[j] = ld<NT>(psi + i0[j] + s);
         }
@@ -165,9 +171,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q(cx<R> *__restrict__ psi, u6
 // covers one contiguous 1 KiB (c128) run and the partner arrives by a lane
 // shuffle (lane xor 2^q).  Lane with bit q clear computes U00 a + U01 b, the
 // other U10 a + U11 b.  Requires 2^n to be a multiple of 256 * APT.
+// dlog / chunk: as for the pair kernel (the thread's APT amplitudes are
+// 2^dlog apart; chunk remaps blocks to XCD runs).
 template <typename R, int APT, bool NT, bool CTRL = false>
-__global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ psi, int q, Mat2<R> u, int c = 0) {
-    const u64 first = (u64)blockIdx.x * (kBlock * APT) + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ psi, int q, Mat2<R> u, int c = 0, int dlog = 8,
+                                                          u32 chunk = 0) {
+    const u64 lb = logical_block(chunk);
+    const int rlog = dlog - 8;
+    const u64 first = ((lb >> rlog) * APT << dlog) + ((lb & ((1ull << rlog) - 1)) << 8) + threadIdx.x;
     const int lane = threadIdx.x & 63, mask = 1 << q;
     const bool upper = lane & mask;
     // own coefficient (diagonal) and partner coefficient (off-diagonal) of this lane's row
@@ -175,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ ps
     const R oth_re = upper ? u.m[4] : u.m[2], oth_im = upper ? u.m[5] : u.m[3];
     cx<R> a[APT];
 #pragma unroll
-    for (int j = 0; j < APT; ++j) a[j] = ld<NT>(psi + first + (u64)j * kBlock);
+    for (int j = 0; j < APT; ++j) a[j] = ld<NT>(psi + first + ((u64)j << dlog));
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
         cx<R> b;
@@ -184,8 +195,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ ps
         cx<R> r;
         r.x = own_re * a[j].x - own_im * a[j].y + oth_re * b.x - oth_im * b.y;
         r.y = own_re * a[j].y + own_im * a[j].x + oth_re * b.y + oth_im * b.x;
-        if (CTRL && !(((first + (u64)j * kBlock) >> c) & 1)) r = a[j];
-        st<NT>(psi + first + (u64)j * kBlock, r);
+        if (CTRL && !(((first + ((u64)j << dlog)) >> c) & 1)) r = a[j];
+        st<NT>(psi + first + ((u64)j << dlog), r);
     }
 }
 
@@ -195,8 +206,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ ps
 // CHUNK: block remap, 0 = hardware order, -1 = XCD eighths, C = runs of C
 // blocks; LANE: lane-shuffle kernel for q < 6, 0/1).
 struct Shape1q {
-    int ppt, nt, lane;
-    u32 chunk;
+    int ppt, nt, lane, dlog, ldlog, cdlog;
+    u32 chunk, lchunk;
 };
 
 static Shape1q shape_1q() {
@@ -210,6 +221,10 @@ static Shape1q shape_1q() {
         v.nt = (int)env("QSIM_1Q_NT", 1);
         v.lane = (int)env("QSIM_1Q_LANE", 1);
         v.chunk = (u32)env("QSIM_1Q_CHUNK", 0x7fffffff);  // 0x7fffffff: per-target schedule below
+        v.dlog = (int)env("QSIM_1Q_SPREAD", 11);
+        v.ldlog = (int)env("QSIM_1Q_LSPREAD", 11);
+        v.cdlog = (int)env("QSIM_C1Q_SPREAD", 8);  // controlled gates: no gain from spreading (measured)
+        v.lchunk = (u32)env("QSIM_1Q_LCHUNK", 0);
         return v;
     }();
     return sh;
@@ -233,13 +248,19 @@ template <typename R> static int launch_1q_t(qs_state *s, int q, const double *u
     const Shape1q v = shape_1q();
     const u32 chunk = v.chunk == 0x7fffffffu ? chunk_for_target(q) : v.chunk;
     hipStream_t st = s->stream;
+    int dlog = v.dlog >= 8 && v.dlog < 40 ? v.dlog : 8;
+    if (npairs % ((u64)v.ppt << dlog)) dlog = 8;
 #define PAIR(PPT, NT) \
-    hipLaunchKernelGGL((k_apply_1q<R, PPT, NT>), dim3(grid_for(npairs, kBlock * PPT)), dim3(kBlock), 0, st, psi, npairs, q, m, chunk)
+    hipLaunchKernelGGL((k_apply_1q<R, PPT, NT>), dim3(grid_for(npairs, kBlock * PPT)), dim3(kBlock), 0, st, psi, npairs, q, m, chunk, 0, dlog)
     if (v.lane && q < 6 && N >= (u64)kBlock * 2) {
+        int ldlog = v.ldlog >= 8 && v.ldlog < 40 ? v.ldlog : 8;
+        if (N % (2ull << ldlog)) ldlog = 8;
         if (v.nt)
-            hipLaunchKernelGGL((k_apply_1q_lane<R, 2, true>), dim3((unsigned)(N / (kBlock * 2))), dim3(kBlock), 0, st, psi, q, m);
+            hipLaunchKernelGGL((k_apply_1q_lane<R, 2, true>), dim3((unsigned)(N / (kBlock * 2))), dim3(kBlock), 0, st, psi, q, m, 0, ldlog,
+                               v.lchunk);
         else
-            hipLaunchKernelGGL((k_apply_1q_lane<R, 2, false>), dim3((unsigned)(N / (kBlock * 2))), dim3(kBlock), 0, st, psi, q, m);
+            hipLaunchKernelGGL((k_apply_1q_lane<R, 2, false>), dim3((unsigned)(N / (kBlock * 2))), dim3(kBlock), 0, st, psi, q, m, 0, ldlog,
+                               v.lchunk);
     } else if (v.nt) {
         if (v.ppt == 1) PAIR(1, true);
         else if (v.ppt == 4) PAIR(4, true);
@@ -262,16 +283,18 @@ int launch_apply_1q(qs_state *s, int q, const double *u) {
 // Only the 2^{n-2} pairs whose control bit is 1 are read and written.
 
 template <typename R, int PPT>
-__global__ __launch_bounds__(kBlock) void k_apply_c1q(cx<R> *__restrict__ psi, u64 nquads, int c, int t, Mat2<R> u, u32 chunk) {
+__global__ __launch_bounds__(kBlock) void k_apply_c1q(cx<R> *__restrict__ psi, u64 nquads, int c, int t, Mat2<R> u, u32 chunk, int dlog = 8) {
     const int lo = c < t ? c : t, hi = c < t ? t : c;
     const u64 sc = 1ull << c, st_ = 1ull << t;
-    const u64 first = logical_block(chunk) * (kBlock * PPT) + threadIdx.x;
+    const u64 lb = logical_block(chunk);
+    const int rlog = dlog - 8;  // the thread's quads are 2^dlog apart (see k_apply_1q)
+    const u64 first = ((lb >> rlog) * PPT << dlog) + ((lb & ((1ull << rlog) - 1)) << 8) + threadIdx.x;
     cx<R> a[PPT], b[PPT];
     u64 i0[PPT];
     bool ok[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const u64 k = first + (u64)j * kBlock;
+        const u64 k = first + ((u64)j << dlog);
         ok[j] = k < nquads;
         i0[j] = insert0(insert0(k, lo), hi) | sc;
         if (ok[j]) {
@@ -304,7 +327,11 @@ template <typename R> static int launch_c1q_t(qs_state *s, int c, int t, const d
             hipLaunchKernelGGL((k_apply_1q<R, 2, true, true>), dim3(grid_for(N >> 1, kBlock * 2)), dim3(kBlock), 0, st, psi, N >> 1, t, m,
                                chunk_for_target(t), c);
     } else {
-        hipLaunchKernelGGL((k_apply_c1q<R, 2>), dim3(grid_for(nquads, kBlock * 2)), dim3(kBlock), 0, st, psi, nquads, c, t, m, chunk_for_target(t));
+        const Shape1q v = shape_1q();
+        int dlog = v.cdlog >= 8 && v.cdlog < 40 ? v.cdlog : 8;
+        if (nquads % (2ull << dlog)) dlog = 8;
+        hipLaunchKernelGGL((k_apply_c1q<R, 2>), dim3(grid_for(nquads, kBlock * 2)), dim3(kBlock), 0, st, psi, nquads, c, t, m, chunk_for_target(t),
+                           dlog);
     }
     QS_LAUNCH_CHECK("apply_c1q");
     return QS_OK;

@@ -44,7 +44,7 @@ def test_init_parity(n, dt):
 
 
 @pytest.mark.parametrize("dt", DTS)
-@pytest.mark.parametrize("n", [1, 2, 3, 7, 12, 13, 16, 19])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 16, 19, 20])
 def test_1q_every_target(n, dt):
     mats = W.haar_list(n, n)
     s = _state(n, dt).init_random(7)

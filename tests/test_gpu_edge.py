@@ -86,3 +86,21 @@ def test_single_qubit_register():
     assert abs(s.prob_one(0).item() - 0.5) < 1e-15
     sm = s.sample(4000, 3).cpu().numpy()
     assert set(np.unique(sm)) <= {0, 1} and 1700 < sm.sum() < 2300
+
+
+def test_30q_full_state_selected_targets():
+    """A 30-qubit complex128 register (16 GiB) checked amplitude by amplitude
+    after one-qubit gates on low, middle and top targets and a CNOT on the top
+    qubits."""
+    from paper_2001_10554_amd.qsim import State
+    n = 30
+    mats = W.haar_list(31, 6)
+    s = State(n).init_random(30)
+    ref = oracle.init_random(n, 30)
+    for i, q in enumerate((0, 5, 11, 17, 29)):
+        s.apply_1q(q, mats[i])
+        oracle.apply_1q(ref, q, mats[i])
+    s.apply_c1q(28, 29, W.PAULI_X)
+    oracle.apply_c1q(ref, 28, 29, W.PAULI_X)
+    h = s.amps.cpu().numpy()
+    assert max_err(h, ref) < 1e-12

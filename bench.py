@@ -21,7 +21,9 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -34,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=32, help="qubits of the sweep register")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -177,6 +179,11 @@ def pool_bench(reps=2):
     from paper_2001_10554_amd import workloads as W
     from paper_2001_10554_amd.qsim import Pool
     w = W.pool_workload(256, 64, 4, seed=4)
+    # The autotuner appends its choice per size class ("n:p:sets:grad TB r") to this file.
+    fd, tune_path = tempfile.mkstemp(suffix=".txt")
+    os.close(fd)
+    os.unlink(tune_path)
+    os.environ["QSIM_AUTOTUNE_CACHE"] = tune_path
     pool = Pool(w.graphs, w.n_qubits, 64, 4)
     a = torch.tensor(np.concatenate(w.angles), device="cuda")
     t0 = time.perf_counter()
@@ -184,10 +191,27 @@ def pool_bench(reps=2):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     t = _time_cuda(lambda: pool.run(), reps)
+    tuned = {}
+    if os.path.exists(tune_path):
+        for line in open(tune_path):
+            key, tb, r = line.split()
+            tuned[int(key.split(":")[0])] = (int(tb), int(r))
+        os.unlink(tune_path)
+    del os.environ["QSIM_AUTOTUNE_CACHE"]
+    # State transfers per circuit: p*P forward passes (read + write, the first
+    # only writes) and p*P backward passes (checkpoint, lambda in, lambda out).
+    p = 4
+    moved = 0
+    for n in w.n_qubits:
+        tb, r = tuned.get(n, (min(n, 12), 3))
+        P = 1 if n <= tb else 1 + -(-(n - tb) // (tb - r))
+        moved += (5 * p * P - 1) * (1 << n) * 16
     out = {"workload": "pool: 256 graphs x 64 angle sets, n ~ U{14..22}, p=4, complex128, E + gradients",
            "circuits": pool.count, "seconds_per_pool": round(t, 4), "circuits_per_s": round(pool.count / t, 1),
            "gradients_per_s": round(pool.count / t, 1), "setup_s": round(t_setup, 2),
            "workspace_GiB": round(pool.ws.numel() / 2**30, 2),
+           "autotuned_TB_r_by_n": {str(k): list(v) for k, v in sorted(tuned.items())},
+           "state_GB_moved": round(moved / 1e9, 1), "effective_GB_per_s": round(moved / t / 1e9, 1),
            "finite": bool(torch.isfinite(pool.E).all().item())}
     del pool
     torch.cuda.empty_cache()
@@ -334,6 +358,49 @@ def noise_bench(T=1024):
     return out
 
 
+def readout_bench(n=30):
+    """Every single-state row at 30 qubits complex128 (16 GiB), as effective
+    HBM GB/s of the algorithmic bytes: initialisation, the cost layer, the
+    two-qubit diagonal and SWAP gates, the read-outs and sampling."""
+    import numpy as np
+    import torch
+
+    from paper_2001_10554_amd import workloads as W
+    from paper_2001_10554_amd.qsim import State
+    S = (1 << n) * 16
+    s = State(n).init_random(1)
+    t2 = State(n).init_random(2)
+    edges = W.random_regular_graph(n, 3, seed=3)
+    diag = torch.rand(1 << n, dtype=torch.float64, device="cuda")
+    cz = np.array([1, 1, 1, -1], dtype=np.complex128)
+    out = {"workload": f"{n}-qubit complex128 register (16 GiB), seeded random state; random 3-regular graph for the cut"}
+
+    def rate(name, fn, nbytes, reps=3, **extra):
+        t = _time_cuda(fn, reps)
+        out[name] = {"ms": round(t * 1e3, 3), "GB_per_s": round(nbytes / t / 1e9, 1), **extra}
+
+    rate("init_basis", lambda: s.init_basis(5), S)                      # write every amplitude
+    rate("init_uniform", lambda: s.init_uniform(), S)
+    rate("init_random", lambda: s.init_random(1), 4 * S)                # write, read for the norm, read + write to scale
+    rate("cut_phase", lambda: s.apply_cut_phase(edges, 0.3), 2 * S)
+    rate("diag2_cz", lambda: s.apply_diag2(3, 17, cz), 2 * S // 4)      # only the |11> quarter moves
+    rate("swap", lambda: s.apply_swap(2, 25), 2 * S // 2)               # the (1,0)/(0,1) halves
+    rate("expect_z_all", lambda: s.expect_z_all(), S)
+    rate("norm2", lambda: s.norm2(), S)
+    rate("prob_one", lambda: s.prob_one(7), S)
+    rate("expect_cut", lambda: s.expect_cut(edges), S)
+    rate("expect_diag", lambda: s.expect_diag(diag), S + (1 << n) * 8)
+    rate("expect_pauli_xyz", lambda: s.expect_pauli(0b1010101, 0b1100011), S)
+    rate("inner", lambda: s.inner(t2), 2 * S)
+    shots = 1 << 20
+    t = _time_cuda(lambda: s.sample(shots, 11), 3)
+    out["sample"] = {"shots": shots, "ms": round(t * 1e3, 3), "shots_per_s": round(shots / t, 1),
+                     "GB_per_s_of_state": round(S / t / 1e9, 1)}
+    del s, t2, diag
+    torch.cuda.empty_cache()
+    return out
+
+
 def kq_bench(n=30):
     """Dense k-qubit gates (k = 1..5, random unitaries) and one Born
     measurement on a 30-qubit complex128 register (16 GiB)."""
@@ -432,10 +499,11 @@ def main():
     launches_1q = sum(len(v) for v in per_1q.values())
     avg_1q = t1q / launches_1q
     gbs = bytes_1q * launches_1q / t1q / 1e9
-    per_q = {q: round(bytes_1q / (sum(v) / len(v)) / 1e9, 1) for q, v in per_1q.items()}
+    # Per target: the median launch time of the timed steps.
+    per_q = {q: round(bytes_1q / statistics.median(v) / 1e9, 1) for q, v in per_1q.items()}
     # CNOT: only the control-1 half is read and written (2^(n-1) amplitudes, R+W).
     bytes_cx = 2 * (1 << (n - 1)) * 16
-    per_c = {q: round(bytes_cx / (sum(v) / len(v)) / 1e9, 1) for q, v in per_cx.items()}
+    per_c = {q: round(bytes_cx / statistics.median(v) / 1e9, 1) for q, v in per_cx.items()}
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
@@ -481,6 +549,8 @@ def main():
         out["brick12"] = brick_bench()
         log("particle swarm")
         out["pso"] = pso_bench()
+        log("single-state rows at 30 qubits")
+        out["rows30"] = readout_bench()
         log("k-qubit gates and measurement")
         out["kq"] = kq_bench()
         log("noisy QAOA trajectories")

@@ -151,6 +151,66 @@ __device__ __forceinline__ double cut_weighted(u64 k, const Graph &g, const doub
     return c;
 }
 
+// Cut values of a chunk of 2^c amplitudes i = base + j 2^8 + t (thread t < 256,
+// loop index j < 2^(c - 8) <= 2^kCutLoopBits), for kernels that sweep a chunk
+// per block.  An edge's cut bit depends on its endpoints' regions: thread bits
+// [0, 8), loop bits [8, c), chunk bits [c, n).  Everything without a loop bit
+// goes into the per-thread constant ct; loop-loop and loop-chunk edges into
+// the per-block table tab[j] (shared memory, filled by all threads; the caller
+// synchronises before reading it); a loop-thread edge (u loop, v thread) adds
+// b_v + bit_u(j) (1 - 2 b_v), i.e. a per-thread coefficient of loop bit u.
+// Then C(i) = ct + tab[j] + sum over set bits x of j of coef[x].
+constexpr int kCutLoopBits = 11;
+
+template <typename CT, bool W>
+__device__ __forceinline__ void cut_split(const Graph &g, const double *w, u32 t, u64 base, int c, CT &ct, CT (&coef)[kCutLoopBits], CT *tab,
+                                          int nthreads) {
+    ct = (CT)0;
+#pragma unroll
+    for (int x = 0; x < kCutLoopBits; ++x) coef[x] = (CT)0;
+    for (int e = 0; e < g.ne; ++e) {
+        const uint32_t uv = g.uv[e];
+        int a = (int)(uv & 0xffu), b = (int)(uv >> 8);
+        const CT we = W ? (CT)w[e] : (CT)1;
+        if (a >= 8 && a < c && !(b >= 8 && b < c)) {  // the loop endpoint (if exactly one) is b
+            const int tmp = a;
+            a = b;
+            b = tmp;
+        }
+        const bool la = a >= 8 && a < c, lb = b >= 8 && b < c;
+        if (la || (lb && a >= c)) continue;  // loop-loop, loop-chunk: in the table
+        if (lb) {                              // a is a thread bit
+            const int tb = (int)((t >> a) & 1u);
+            ct += tb ? we : (CT)0;
+#pragma unroll
+            for (int x = 0; x < kCutLoopBits; ++x)
+                if (x == b - 8) coef[x] += tb ? -we : we;
+            continue;
+        }
+        const u64 ia = a < 8 ? (u64)t : base, ib = b < 8 ? (u64)t : base;
+        if (((ia >> a) ^ (ib >> b)) & 1u) ct += we;
+    }
+    for (u32 j = t; j < (1u << (c - 8)); j += nthreads) {
+        const u64 idx = base | ((u64)j << 8);
+        CT v = (CT)0;
+        for (int e = 0; e < g.ne; ++e) {
+            const uint32_t uv = g.uv[e];
+            const int a = (int)(uv & 0xffu), b = (int)(uv >> 8);
+            if (a < 8 || b < 8 || !((a < c) || (b < c))) continue;  // needs a loop endpoint and no thread endpoint
+            if (((idx >> a) ^ (idx >> b)) & 1u) v += W ? (CT)w[e] : (CT)1;
+        }
+        tab[j] = v;
+    }
+}
+
+template <typename CT> __device__ __forceinline__ CT cut_at(CT ct, const CT (&coef)[kCutLoopBits], const CT *tab, u32 j) {
+    CT v = ct + tab[j];
+#pragma unroll
+    for (int x = 0; x < kCutLoopBits; ++x)
+        if ((j >> x) & 1u) v += coef[x];
+    return v;
+}
+
 // ------------------------------------------------------------------ launch geometry
 constexpr int kBlock = 256;
 

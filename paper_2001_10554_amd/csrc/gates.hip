@@ -431,6 +431,33 @@ __global__ __launch_bounds__(kBlock) void k_cut_phase(cx<R> *__restrict__ psi, u
     }
 }
 
+// Unit weights, chunks of 2^c amplitudes per block: integer cut values from
+// cut_split and the phase table e^{-i gamma c}, c = 0..|E|.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cut_phase_chunk(cx<R> *__restrict__ psi, int c, Graph g, double gamma) {
+    __shared__ double2 ph[kMaxEdges + 1];
+    __shared__ int tab[1 << kCutLoopBits];
+    for (int k = threadIdx.x; k <= g.ne; k += kBlock) {
+        double sn, cs;
+        sincos(gamma * (double)k, &sn, &cs);
+        ph[k] = make_double2(cs, -sn);
+    }
+    const u64 base = (u64)blockIdx.x << c;
+    const u32 t = threadIdx.x;
+    int ct, coef[kCutLoopBits];
+    cut_split<int, false>(g, nullptr, t, base, c, ct, coef, tab, kBlock);
+    __syncthreads();
+    for (u32 j = 0; j < (1u << (c - 8)); ++j) {
+        const u64 i = base + ((u64)j << 8) + t;
+        const double2 f = ph[cut_at<int>(ct, coef, tab, j)];
+        const cx<R> a = psi[i];
+        cx<R> r;
+        r.x = (R)(a.x * f.x - a.y * f.y);
+        r.y = (R)(a.x * f.y + a.y * f.x);
+        psi[i] = r;
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_cut_phase_w(cx<R> *__restrict__ psi, u64 N, Graph g, Weights w, double gamma) {
     for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < N; i += (u64)gridDim.x * kBlock) {
@@ -454,6 +481,14 @@ int launch_cut_phase(qs_state *s, const Graph &g, const Weights *w, double gamma
             hipLaunchKernelGGL(k_cut_phase_w<double>, grid, dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, N, g, *w, gamma);
         else
             hipLaunchKernelGGL(k_cut_phase_w<float>, grid, dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, N, g, *w, gamma);
+    } else if (s->n >= 12) {
+        int c = s->n - 11 > 12 ? s->n - 11 : 12;  // at most 2048 blocks while the loop fits the table
+        if (c > 8 + kCutLoopBits) c = 8 + kCutLoopBits;
+        const dim3 cg((unsigned)(N >> c));
+        if (s->dtype == QS_C128)
+            hipLaunchKernelGGL(k_cut_phase_chunk<double>, cg, dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, c, g, gamma);
+        else
+            hipLaunchKernelGGL(k_cut_phase_chunk<float>, cg, dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, c, g, gamma);
     } else {
         if (s->dtype == QS_C128)
             hipLaunchKernelGGL(k_cut_phase<double>, grid, dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, N, g, gamma);

@@ -758,7 +758,7 @@ QShape qaoa_default_shape(int n) {
     if (n < 10) return QShape{n, 8, n < 3 ? n : 3};
     if (env_tb >= 10 && env_tb <= 13) {
         const int tb = env_tb < n ? env_tb : n;
-        return QShape{tb, threads_bits_for(tb), env_r == 2 || env_r == 3 ? env_r : 3};
+        return QShape{tb, threads_bits_for(tb), env_r >= 2 && env_r <= 4 ? env_r : 3};
     }
     // Measured on MI355X (adjoint gradient, p = 8, one angle set): small
     // registers are latency-bound and favour the 16 KiB tiles (more blocks);

@@ -218,8 +218,57 @@ template <typename R> struct DiagTerm {
     __device__ void operator()(u64 i, double *acc) const { acc[0] += d[i] * norm2d<R>(psi[i]); }
 };
 
+// <C> over chunks of 2^c amplitudes per block, cut values from cut_split
+// (a table read and a few adds per amplitude instead of |E| bit tests).
+template <typename R, bool W>
+__global__ __launch_bounds__(kBlock) void k_cut_expect(const cx<R> *__restrict__ psi, int c, Graph g, Weights w, double *__restrict__ partial) {
+    __shared__ double tab[1 << kCutLoopBits];
+    __shared__ double red[kBlock / 64];
+    const u64 base = (u64)blockIdx.x << c;
+    const u32 t = threadIdx.x;
+    double ct, coef[kCutLoopBits];
+    cut_split<double, W>(g, w.w, t, base, c, ct, coef, tab, kBlock);
+    __syncthreads();
+    double acc = 0.0;
+    for (u32 j = 0; j < (1u << (c - 8)); ++j) acc += cut_at<double>(ct, coef, tab, j) * norm2d<R>(psi[base + ((u64)j << 8) + t]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((t & 63) == 0) red[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 int launch_expect_cut(qs_state *s, const Graph &g, const Weights *w, double *out_dev) {
     const u64 N = 1ull << s->n;
+    if (s->n >= 8 + 4) {
+        // chunk 2^c: at most 2^kCutLoopBits loop steps and at most 2048 blocks
+        int c = s->n - 11 > 12 ? s->n - 11 : 12;
+        if (c > 8 + kCutLoopBits) c = 8 + kCutLoopBits;
+        const u64 G = N >> c;
+        const Weights none{};
+        if (G <= 2048 * 64) {
+            const bool wt = w != nullptr;
+            if (s->dtype == QS_C128) {
+                if (wt)
+                    hipLaunchKernelGGL((k_cut_expect<double, true>), dim3((unsigned)G), dim3(kBlock), 0, s->stream, (const cx<double> *)s->buf, c, g, *w,
+                                       s->scratch);
+                else
+                    hipLaunchKernelGGL((k_cut_expect<double, false>), dim3((unsigned)G), dim3(kBlock), 0, s->stream, (const cx<double> *)s->buf, c, g,
+                                       none, s->scratch);
+            } else {
+                if (wt)
+                    hipLaunchKernelGGL((k_cut_expect<float, true>), dim3((unsigned)G), dim3(kBlock), 0, s->stream, (const cx<float> *)s->buf, c, g, *w,
+                                       s->scratch);
+                else
+                    hipLaunchKernelGGL((k_cut_expect<float, false>), dim3((unsigned)G), dim3(kBlock), 0, s->stream, (const cx<float> *)s->buf, c, g,
+                                       none, s->scratch);
+            }
+            QS_LAUNCH_CHECK("expect_cut");
+            hipLaunchKernelGGL(k_reduce_final<1>, dim3(1), dim3(kBlock), 0, s->stream, s->scratch, (int)G, out_dev);
+            QS_LAUNCH_CHECK("expect_cut");
+            return QS_OK;
+        }
+    }
     if (s->dtype == QS_C128) {
         if (w) return run_reduce<1>(s, N, CutTermW<double>{(const cx<double> *)s->buf, g, *w}, out_dev, "expect_cut");
         return run_reduce<1>(s, N, CutTerm<double>{(const cx<double> *)s->buf, g}, out_dev, "expect_cut");

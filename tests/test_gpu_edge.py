@@ -104,3 +104,21 @@ def test_30q_full_state_selected_targets():
     oracle.apply_c1q(ref, 28, 29, W.PAULI_X)
     h = s.amps.cpu().numpy()
     assert max_err(h, ref) < 1e-12
+
+
+@pytest.mark.parametrize("n", [26, 30])
+def test_cut_layer_and_expectation_large(n):
+    """The chunked cut kernels (per-thread constants, loop-bit coefficients
+    and a per-block table) at sizes where the loop spans 7 and 11 bits."""
+    from paper_2001_10554_amd.qsim import State
+    edges = W.random_regular_graph(n, 3, seed=n)
+    w = np.random.default_rng(n).uniform(0.2, 1.5, len(edges))
+    s = State(n).init_random(n)
+    ref = oracle.init_random(n, n)
+    assert abs(s.expect_cut(edges).item() - oracle.expect_cut(ref, edges)) < 1e-12 * len(edges)
+    assert abs(s.expect_cut(edges, w).item() - oracle.expect_cut(ref, edges, w)) < 2e-12 * len(edges)
+    if n <= 26:
+        s.apply_cut_phase(edges, 0.37)
+        oracle.apply_cut_phase(ref, edges, 0.37)
+        assert max_err(s.amps.cpu().numpy(), ref) < 1e-12
+        assert abs(s.expect_cut(edges).item() - oracle.expect_cut(ref, edges)) < 1e-12 * len(edges)

@@ -284,12 +284,16 @@ __device__ __forceinline__ void regs_apply_gate(cx<R> *v, u32 m0, int g0, int g1
 
 // A gate staged in LDS, ready to apply: kind 0 = skip; val = the 2x2 matrix
 // (1Q, C1Q) or the 4 diagonal entries (DIAG2), interleaved (re, im).
-template <typename R> struct SGate {
-    int8_t kind, p0, p1, q0, q1, s0, s1, cval;
-    int8_t g[3], pad0;
-    int16_t run, pad1;
+// The header is one 16-byte word and the values whole 16-byte vectors, so a
+// gate is read with a few wide LDS reads rather than one read per field:
+//   h.x = kind | p0 << 8 | p1 << 16 | q0 << 24,  h.y = q1 | s0 << 8 | s1 << 16 | cval << 24,
+//   h.z = g0 | g1 << 8 | g2 << 16,               h.w = run   (fields as signed bytes).
+template <typename R> struct alignas(16) SGate {
+    uint4 h;
     R val[8];
 };
+
+__device__ __forceinline__ int sbyte(uint32_t w, int k) { return (int)(int8_t)(uint8_t)(w >> (8 * k)); }
 
 // Gates are staged in LDS this many at a time (and sweeps hold at most this
 // many gates), so their parameters are fetched by all threads at once rather
@@ -314,18 +318,11 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
             int cval = 1, kind = x.kind;
             if (!prep(begin + at + (int)threadIdx.x, x, gv, cval, kind)) kind = 0;
             SGate<R> o;
-            o.kind = (int8_t)kind;
-            o.p0 = x.p0;
-            o.p1 = x.p1;
-            o.q0 = x.q0;
-            o.q1 = x.q1;
-            o.s0 = x.s0;
-            o.s1 = x.s1;
-            o.cval = (int8_t)cval;
-            o.g[0] = x.g[0];
-            o.g[1] = x.g[1];
-            o.g[2] = x.g[2];
-            o.run = x.run;
+            auto byte = [](int v) { return (uint32_t)(uint8_t)(int8_t)v; };
+            o.h.x = byte(kind) | byte(x.p0) << 8 | byte(x.p1) << 16 | byte(x.q0) << 24;
+            o.h.y = byte(x.q1) | byte(x.s0) << 8 | byte(x.s1) << 16 | byte(cval) << 24;
+            o.h.z = byte(x.g[0]) | byte(x.g[1]) << 8 | byte(x.g[2]) << 16;
+            o.h.w = (uint32_t)x.run;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const cx<R> d = gv.d[e];
@@ -341,9 +338,9 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
     int gi = 0;
     while (gi < count) {
         if (gi >= ce) stage(gi);
-        if (gi + sg[gi - cb].run > ce) stage(gi);
-        const SGate<R> &h = sg[gi - cb];
-        const int run = h.run, g0 = h.g[0], g1 = h.g[1], g2 = h.g[2];
+        if (gi + (int)sg[gi - cb].h.w > ce) stage(gi);
+        const uint4 hh = sg[gi - cb].h;
+        const int run = (int)hh.w, g0 = sbyte(hh.z, 0), g1 = sbyte(hh.z, 1), g2 = sbyte(hh.z, 2);
         cx<R> v[GMAX][8];
         u32 m0[GMAX];
 #pragma unroll
@@ -357,19 +354,24 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
         }
         for (int r = 0; r < run; ++r) {
             const SGate<R> &x = sg[gi - cb + r];
-            if (!x.kind) continue;
+            const uint4 h = x.h;
+            cx<R> val[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) val[e] = reinterpret_cast<const cx<R> *>(x.val)[e];
+            const int kind = sbyte(h.x, 0);
+            if (!kind) continue;
             GateVals<R> gv;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) gv.m.m[e] = x.val[e];
-#pragma unroll
             for (int e = 0; e < 4; ++e) {
-                gv.d[e].x = x.val[2 * e];
-                gv.d[e].y = x.val[2 * e + 1];
+                gv.m.m[2 * e] = val[e].x;
+                gv.m.m[2 * e + 1] = val[e].y;
+                gv.d[e] = val[e];
             }
 #pragma unroll
             for (int k = 0; k < GMAX; ++k)
                 if (threadIdx.x + (u32)k * NT < groups)
-                    regs_apply_gate<R>(v[k], m0[k], g0, g1, g2, base, x.kind, x.p0, x.p1, x.q0, x.q1, x.s0, x.s1, x.cval, gv);
+                    regs_apply_gate<R>(v[k], m0[k], g0, g1, g2, base, kind, sbyte(h.x, 1), sbyte(h.x, 2), sbyte(h.x, 3), sbyte(h.y, 0),
+                                       sbyte(h.y, 1), sbyte(h.y, 2), sbyte(h.y, 3), gv);
         }
 #pragma unroll
         for (int k = 0; k < GMAX; ++k) {

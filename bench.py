@@ -205,7 +205,7 @@ def pool_bench(reps=2):
     for n in w.n_qubits:
         tb, r = tuned.get(n, (min(n, 12), 3))
         P = 1 if n <= tb else 1 + -(-(n - tb) // (tb - r))
-        moved += (5 * p * P - 1) * (1 << n) * 16
+        moved += 64 * (5 * p * P - 1) * (1 << n) * 16  # 64 angle sets per graph
     out = {"workload": "pool: 256 graphs x 64 angle sets, n ~ U{14..22}, p=4, complex128, E + gradients",
            "circuits": pool.count, "seconds_per_pool": round(t, 4), "circuits_per_s": round(pool.count / t, 1),
            "gradients_per_s": round(pool.count / t, 1), "setup_s": round(t_setup, 2),
@@ -486,7 +486,7 @@ def cpu_baseline(seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

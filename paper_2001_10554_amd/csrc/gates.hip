@@ -201,10 +201,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ ps
 }
 
 // Launch shape of the one-qubit gate.  Defaults come from timing every target
-// of a 32-qubit complex128 sweep; the QSIM_1Q_* variables override them for
-// tuning runs (PPT: pairs per thread 1/2/4; NT: non-temporal hints 0/1;
-// CHUNK: block remap, 0 = hardware order, -1 = XCD eighths, C = runs of C
-// blocks; LANE: lane-shuffle kernel for q < 6, 0/1).
+// of a 32-qubit complex128 sweep; environment variables override them for
+// tuning runs: QSIM_1Q_PPT pairs per thread 1/2/4; QSIM_1Q_NT non-temporal
+// hints 0/1; QSIM_1Q_CHUNK block remap (0 = hardware order, -1 = XCD eighths,
+// C = runs of C blocks); QSIM_1Q_LANE lane-shuffle kernel for q < 6, 0/1;
+// QSIM_1Q_SPREAD / QSIM_1Q_LSPREAD log2 of the distance between a thread's
+// pairs / amplitudes (pair / lane kernel); QSIM_1Q_LCHUNK the lane kernel's
+// block remap; QSIM_C1Q_SPREAD the controlled kernel's spread.
 struct Shape1q {
     int ppt, nt, lane, dlog, ldlog, cdlog;
     u32 chunk, lchunk;

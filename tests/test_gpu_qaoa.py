@@ -121,3 +121,36 @@ def test_config3_24q_p8_vs_oracle_and_fd():
     # E ~ 36 in magnitude: rounding of each forward ~ 1e-13 relative -> eps_E/h ~ 4e-6 / ... bound:
     tau = 10 * (abs(E.item()) * 1e-14 / h + h * h * 1e3)
     assert np.max(np.abs(fd - g)) < tau
+
+
+def test_fd_error_vs_step_has_truncation_and_rounding_branches():
+    """Central differences of the GPU forward against the adjoint gradient over
+    h = 1e-2 ... 1e-8: the error first falls as h^2 (truncation, so a tenfold
+    smaller h gives about a hundredfold smaller error) and then grows as eps/h
+    (rounding), with the adjoint inside the valley."""
+    import torch
+    n, p = 14, 3
+    edges = W.random_regular_graph(n, 3, seed=6)
+    theta = W.qaoa_angles(p, seed=6)
+    prob = _problem(n, edges, p)
+    _, G = prob.run(torch.tensor(theta, device="cuda"))
+    g = G.cpu().numpy()[0]
+    hs = [1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8]
+    err = []
+    for h in hs:
+        shifts = np.repeat(theta[None, :], 4 * p, axis=0)
+        for k in range(2 * p):
+            shifts[2 * k, k] += h
+            shifts[2 * k + 1, k] -= h
+        Es, _ = prob.run(torch.tensor(shifts, device="cuda"), grad=False)
+        Es = Es.cpu().numpy()
+        err.append(np.abs((Es[0::2] - Es[1::2]) / (2 * h) - g))
+    err = np.array(err)  # [h, component]
+    big = err[0] > 1e-6  # components whose truncation term is well above rounding at h = 1e-2
+    assert big.any()
+    ratio = err[0][big] / err[1][big]
+    assert np.all((ratio > 50) & (ratio < 200)), ratio
+    worst = err.max(axis=1)
+    valley = worst[3:5].min()  # h = 1e-5, 1e-6: the oracle's own curve bottoms out near 1e-8 here
+    assert valley < 5e-8
+    assert worst[-1] > 10 * valley

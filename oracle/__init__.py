@@ -6,7 +6,8 @@ Python binding) never imports it, and it never imports the product: the two
 share only the seeded inputs of ``paper_2001_10554_amd.workloads``.
 
 The arithmetic lives in ``qsim_ref.c`` (plain complex128 C, one gate at a time,
-long-double sequential reductions).  This module is ctypes marshalling plus a
+long-double sequential reductions, chunked for whole-register expectations).
+This module is ctypes marshalling plus a
 few numpy-level compositions that are plain definitions (trajectory averages).
 
 Every function here is pinned by a ``-m "not gpu"`` test against something
@@ -34,7 +35,8 @@ _c_u64_p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (OpenMP on element-wise loops only)."""
+    """Compile the oracle with gcc (OpenMP on element-wise loops and on the
+    fixed chunks of its long sums)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + f".tmp{os.getpid()}"
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-fvisibility=hidden",

@@ -15,8 +15,10 @@
  *
  * Element-wise loops may run on several OpenMP threads: each pair or element
  * is updated independently, so the result does not depend on the thread
- * count.  Every reduction is a single sequential sum accumulated in long
- * double, in index order.
+ * count.  Every reduction is a sequential sum accumulated in long double, in
+ * index order; the cut and diagonal expectations over whole registers sum
+ * fixed 2^16-term chunks that way and then add the chunk sums in order, so
+ * their result does not depend on the thread count either.
  */
 #include <complex.h>
 #include <math.h>
@@ -369,26 +371,52 @@ EXPORT void ref_expect_z_all(const cplx *psi, int n, double *out)
 }
 
 /* <C> = sum_k C(k) |a_k|^2. */
+/* Long sums over k are taken in fixed chunks of 2^16 terms: each chunk is a
+ * plain sequential long-double sum, and the chunk sums are added in chunk
+ * order.  The result does not depend on the thread count, and the chunks may
+ * run in parallel. */
+#define SUM_CHUNK_BITS 16
+
 EXPORT double ref_expect_cut(const cplx *psi, int n, int E, const int32_t *edges, const double *w)
 {
     const uint64_t N = 1ull << n;
-    ldbl s = 0;
-    for (uint64_t k = 0; k < N; ++k) {
-        const ldbl p = (ldbl)creal(psi[k]) * creal(psi[k]) + (ldbl)cimag(psi[k]) * cimag(psi[k]);
-        s += (ldbl)cut_value(k, E, edges, w) * p;
+    const uint64_t C = N > (1ull << SUM_CHUNK_BITS) ? N >> SUM_CHUNK_BITS : 1, L = N / C;
+    ldbl *part = (ldbl *)malloc(C * sizeof(ldbl));
+    if (!part) return NAN;
+#pragma omp parallel for schedule(static)
+    for (uint64_t c = 0; c < C; ++c) {
+        ldbl s = 0;
+        for (uint64_t k = c * L; k < (c + 1) * L; ++k) {
+            const ldbl p = (ldbl)creal(psi[k]) * creal(psi[k]) + (ldbl)cimag(psi[k]) * cimag(psi[k]);
+            s += (ldbl)cut_value(k, E, edges, w) * p;
+        }
+        part[c] = s;
     }
+    ldbl s = 0;
+    for (uint64_t c = 0; c < C; ++c) s += part[c];
+    free(part);
     return (double)s;
 }
 
-/* sum_k d_k |a_k|^2 for a real diagonal observable d. */
+/* sum_k d_k |a_k|^2 for a real diagonal observable d (chunked as above). */
 EXPORT double ref_expect_diag(const cplx *psi, int n, const double *d)
 {
     const uint64_t N = 1ull << n;
-    ldbl s = 0;
-    for (uint64_t k = 0; k < N; ++k) {
-        const ldbl p = (ldbl)creal(psi[k]) * creal(psi[k]) + (ldbl)cimag(psi[k]) * cimag(psi[k]);
-        s += (ldbl)d[k] * p;
+    const uint64_t C = N > (1ull << SUM_CHUNK_BITS) ? N >> SUM_CHUNK_BITS : 1, L = N / C;
+    ldbl *part = (ldbl *)malloc(C * sizeof(ldbl));
+    if (!part) return NAN;
+#pragma omp parallel for schedule(static)
+    for (uint64_t c = 0; c < C; ++c) {
+        ldbl s = 0;
+        for (uint64_t k = c * L; k < (c + 1) * L; ++k) {
+            const ldbl p = (ldbl)creal(psi[k]) * creal(psi[k]) + (ldbl)cimag(psi[k]) * cimag(psi[k]);
+            s += (ldbl)d[k] * p;
+        }
+        part[c] = s;
     }
+    ldbl s = 0;
+    for (uint64_t c = 0; c < C; ++c) s += part[c];
+    free(part);
     return (double)s;
 }
 

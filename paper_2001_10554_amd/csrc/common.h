@@ -219,6 +219,17 @@ inline unsigned grid_for(u64 work, u64 per_block) {
     return (unsigned)(g ? g : 1);
 }
 
+// A HIP grid holds fewer than 2^32 work-items.  Kernels with one work unit per
+// thread take a workgroup offset `blk0` and are launched in pieces of at most
+// 2^23 workgroups (2^31 work-items at 256 threads); f(blocks, blk0) issues one
+// piece.  Registers up to 2^31 units are a single piece.
+constexpr u64 kPieceBlocks = 1ull << 23;
+
+template <typename F> inline void for_pieces(u64 nblocks, F f) {
+    if (nblocks == 0) nblocks = 1;
+    for (u64 b0 = 0; b0 < nblocks; b0 += kPieceBlocks) f((unsigned)(nblocks - b0 < kPieceBlocks ? nblocks - b0 : kPieceBlocks), b0);
+}
+
 }  // namespace qs
 
 // ------------------------------------------------------------------ handle

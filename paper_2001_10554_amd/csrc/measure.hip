@@ -133,9 +133,9 @@ struct KqArgs {
 };
 
 template <typename R, int K>
-__global__ __launch_bounds__(kBlock) void k_apply_kq(cx<R> *__restrict__ psi, u64 groups, KqArgs a, const d2v *__restrict__ U) {
+__global__ __launch_bounds__(kBlock) void k_apply_kq(cx<R> *__restrict__ psi, u64 groups, KqArgs a, const d2v *__restrict__ U, u64 blk0) {
     constexpr int D = 1 << K;
-    const u64 g = (u64)blockIdx.x * kBlock + threadIdx.x;
+    const u64 g = (blk0 + blockIdx.x) * kBlock + threadIdx.x;
     if (g >= groups) return;
     u64 base = g;
 #pragma unroll
@@ -166,15 +166,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_kq(cx<R> *__restrict__ psi, u6
 }
 
 template <typename R>
-static void launch_kq_t(qs_state *s, int k, u64 groups, const KqArgs &a, const d2v *U, unsigned grid) {
+static void launch_kq_t(qs_state *s, int k, u64 groups, const KqArgs &a, const d2v *U, u64 blocks) {
     cx<R> *psi = (cx<R> *)s->buf;
-    switch (k) {
-    case 1: hipLaunchKernelGGL((k_apply_kq<R, 1>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U); break;
-    case 2: hipLaunchKernelGGL((k_apply_kq<R, 2>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U); break;
-    case 3: hipLaunchKernelGGL((k_apply_kq<R, 3>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U); break;
-    case 4: hipLaunchKernelGGL((k_apply_kq<R, 4>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U); break;
-    default: hipLaunchKernelGGL((k_apply_kq<R, 5>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U); break;
-    }
+    for_pieces(blocks, [&](unsigned grid, u64 b0) {
+        switch (k) {
+        case 1: hipLaunchKernelGGL((k_apply_kq<R, 1>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U, b0); break;
+        case 2: hipLaunchKernelGGL((k_apply_kq<R, 2>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U, b0); break;
+        case 3: hipLaunchKernelGGL((k_apply_kq<R, 3>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U, b0); break;
+        case 4: hipLaunchKernelGGL((k_apply_kq<R, 4>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U, b0); break;
+        default: hipLaunchKernelGGL((k_apply_kq<R, 5>), dim3(grid), dim3(kBlock), 0, s->stream, psi, groups, a, U, b0); break;
+        }
+    });
 }
 
 int launch_apply_kq(qs_state *s, const int32_t *qubits, int k, const double *U_dev) {
@@ -193,7 +195,7 @@ int launch_apply_kq(qs_state *s, const int32_t *qubits, int k, const double *U_d
             a.sorted[j - 1] = t;
         }
     const u64 groups = 1ull << (s->n - k);
-    const unsigned grid = grid_for(groups, kBlock);  // at most 2^34 / 256 blocks
+    const u64 grid = (groups + kBlock - 1) / kBlock;  // launched in pieces of at most 2^23 blocks
     if (s->dtype == QS_C128)
         launch_kq_t<double>(s, k, groups, a, (const d2v *)U_dev, grid);
     else

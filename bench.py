@@ -198,14 +198,17 @@ def pool_bench(reps=2):
             tuned[int(key.split(":")[0])] = (int(tb), int(r))
         os.unlink(tune_path)
     del os.environ["QSIM_AUTOTUNE_CACHE"]
-    # State transfers per circuit: p*P forward passes (read + write, the first
-    # only writes) and p*P backward passes (checkpoint, lambda in, lambda out).
+    # State transfers per circuit over its np passes: forward 2 per pass (the
+    # first only writes), backward 3 per pass (checkpoint, lambda in, lambda
+    # out; the last pass computes lambda, the first stores none): 5 np - 3.
+    # With P qubit groups, layer boundaries are merged passes: np = p(P-1) + 1.
     p = 4
     moved = 0
     for n in w.n_qubits:
         tb, r = tuned.get(n, (min(n, 12), 3))
         P = 1 if n <= tb else 1 + -(-(n - tb) // (tb - r))
-        moved += 64 * (5 * p * P - 1) * (1 << n) * 16  # 64 angle sets per graph
+        npass = p * (P - 1) + 1 if P >= 2 else p
+        moved += 64 * (5 * npass - 3) * (1 << n) * 16  # 64 angle sets per graph
     out = {"workload": "pool: 256 graphs x 64 angle sets, n ~ U{14..22}, p=4, complex128, E + gradients",
            "circuits": pool.count, "seconds_per_pool": round(t, 4), "circuits_per_s": round(pool.count / t, 1),
            "gradients_per_s": round(pool.count / t, 1), "setup_s": round(t_setup, 2),

@@ -111,7 +111,7 @@ static int build_class(const qs_pool_desc *d, PoolClass &C, QShape shape, bool g
     C.proto.geo = plan.geo;
     C.proto.geo.num_edges = max_edges;  // phase tables cover every graph of the class
     C.proto.passes.clear();
-    C.np = d->p * C.proto.geo.P;
+    C.np = C.proto.geo.np;
     C.circ_bytes = qaoa_layout(C.proto.geo, grad).bytes;
     std::vector<int32_t> map;
     for (int g : C.graphs)

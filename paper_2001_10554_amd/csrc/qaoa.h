@@ -10,7 +10,17 @@ namespace qs {
 
 constexpr int kQMaxEdges = 128;
 
-enum { QF_FIRST = 1, QF_PHASE_END = 2, QF_LAST = 4 };
+// Pass flags.  FIRST: the cost phase exp(-i gamma_1 C) at the start, on the
+// uniform state generated in registers.  PHASE_END: exp(-i gamma_{l+1} C) at
+// the end (one qubit group per layer).  MERGE: the pass continues into the
+// next layer on the same qubit group: exp(-i gamma_{l+1} C), then the RX
+// gates of layer l+1 on the group.  LAST: the pass also accumulates E.
+enum { QF_FIRST = 1, QF_PHASE_END = 2, QF_LAST = 4, QF_MERGE = 8 };
+
+// Per (pass, tile) partial sums of the backward: 0 = gamma of the phase at the
+// end or in the middle of the pass, 1 = beta of the pass's layer, 2 = gamma_1
+// (first pass), 3 = beta of the next layer (merged passes).
+constexpr int kQSlots = 4;
 
 // Edge classes by where the endpoints sit for a thread map: thread-index bit
 // ("t"), register-index bit ("j"), or a qubit fixed per tile ("r").
@@ -36,8 +46,9 @@ struct QWeights {
     double w[kQMaxEdges];
 };
 
+// np: passes per circuit; merge: layer boundaries are merged passes (P >= 2).
 struct QGeom {
-    int n, p, P, tb, G, glog, num_edges, weighted;
+    int n, p, P, tb, G, glog, num_edges, weighted, np, merge;
 };
 
 // Where circuit c of a launch keeps its data: ws + c * circ_bytes + offset
@@ -65,7 +76,7 @@ struct QPlan {
     QShape shape;
     bool rt;
     QGeom geo;
-    std::vector<QPass> passes;  // forward order: pass (l, g) at index l*P + g
+    std::vector<QPass> passes;  // forward order (geo.np passes)
     QWeights W;
 };
 

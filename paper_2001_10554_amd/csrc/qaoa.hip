@@ -390,10 +390,11 @@ __global__ __launch_bounds__(kLdsThreads) void k_qaoa_bwd_lds(QPass Parg, QWeigh
     const double tbx = qblock_sum(ipb, red);
     const double tc1 = qblock_sum(ipc1, red);
     if (tid == 0) {
-        double *o = partial + ((u64)P.pidx * geo.G + q.tile) * 3;
+        double *o = partial + ((u64)P.pidx * geo.G + q.tile) * kQSlots;
         o[0] = tc;
         o[1] = tbx;
         o[2] = tc1;
+        o[3] = 0.0;
     }
 }
 
@@ -448,10 +449,61 @@ __device__ __forceinline__ void rt_transpose(d2v (&a)[1 << (TB - TT)], d2v *sh) 
     __syncthreads();
 }
 
-template <typename CT, int TB, int TT, bool POOLED>
+// Which register bits a helper covers: none, register bits 0..W-1 (the bits
+// the other layout holds as wave bits), or all.
+enum { kRegsNone = 0, kRegsLow = 1, kRegsAll = 2 };
+
+// RX(2 beta), (cb, sb) = (cos beta, sin beta), on the tile bits of `rx` that
+// layout L holds in the selected register bits and, when `lanes`, on the lane
+// bits.
+// Register-bit gates are applied without a branch, as the identity
+// (cos, sin) = (1, 0) where the bit takes no RX: a uniform branch around an
+// in-place update of the register array makes the compiler copy the whole
+// array, and register bits almost always take the gate.
+template <int TB, int TT, int L>
+__device__ __forceinline__ void rt_rx(d2v (&a)[1 << (TB - TT)], u32 rx, double cb, double sb, int regs, bool lanes) {
+    using G = RT<TB, TT>;
+#pragma unroll
+    for (int x = 0; x < G::JB; ++x) {
+        if (regs == kRegsNone || (regs == kRegsLow && x >= G::W)) continue;
+        const bool on = (rx >> G::reg_bit(L, x)) & 1;
+        const double c = on ? cb : 1.0, s = on ? sb : 0.0;
+#pragma unroll
+        for (int j = 0; j < G::R; ++j)
+            if (!((j >> x) & 1)) rx_pair(a[j], a[j | (1 << x)], c, s);
+    }
+    if (lanes) {
+#pragma unroll
+        for (int lb = 0; lb < 6; ++lb) {
+            const bool on = (rx >> lb) & 1;
+            const double c = on ? cb : 1.0, s = on ? sb : 0.0;
+#pragma unroll
+            for (int j = 0; j < G::R; ++j) a[j] = rx_half(a[j], shfl_xor2(a[j], on ? 1 << lb : 0), c, s);
+        }
+    }
+}
+
+// The same over every register bit of the layout the registers are in
+// (`in_l1` chosen at run time), so one copy of the code serves both layouts.
+template <int TB, int TT>
+__device__ __forceinline__ void rt_rx_cur(d2v (&a)[1 << (TB - TT)], u32 rx, double cb, double sb, bool in_l1, bool lanes) {
+    using G = RT<TB, TT>;
+#pragma unroll
+    for (int x = 0; x < G::JB; ++x) {
+        const int tbit = in_l1 ? G::reg_bit(1, x) : G::reg_bit(0, x);
+        const bool on = (rx >> tbit) & 1;
+        const double c = on ? cb : 1.0, s = on ? sb : 0.0;
+#pragma unroll
+        for (int j = 0; j < G::R; ++j)
+            if (!((j >> x) & 1)) rx_pair(a[j], a[j | (1 << x)], c, s);
+    }
+    if (lanes) rt_rx<TB, TT, 0>(a, rx, cb, sb, kRegsNone, true);
+}
+
+template <typename CT, int TB, int TT, bool POOLED, bool MERGE>
 __global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
     using G = RT<TB, TT>;
-    constexpr int R = G::R, JB = G::JB, Wb = G::W;
+    constexpr int R = G::R, JB = G::JB;
     __shared__ d2v sh[G::TS];
     __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
     __shared__ double red[16];
@@ -461,63 +513,65 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W,
     d2v *out = B.out_off >= 0 ? (d2v *)(q.region + B.out_off) : nullptr;
     const int t = threadIdx.x, l = P.layer, p = geo.p;
     const u64 base = qtile_base(P, q.tile);
-    const bool first = P.flags & QF_FIRST, pend = P.flags & QF_PHASE_END, last = P.flags & QF_LAST;
+    // Merged passes are never first or last and carry no end phase.
+    constexpr bool merge = MERGE;
+    const bool first = !MERGE && (P.flags & QF_FIRST), pend = !MERGE && (P.flags & QF_PHASE_END), last = !MERGE && (P.flags & QF_LAST);
     const bool l1 = P.use_l1;
-    const double g_a = q.theta[l], g_b = pend ? q.theta[l + 1] : 0.0;
+    const double g_a = q.theta[l], g_b = pend || merge ? q.theta[l + 1] : 0.0;
     if (!geo.weighted) {
         if (first) fill_table(tab_a, geo.num_edges, g_a);
-        if (pend) fill_table(tab_b, geo.num_edges, g_b);
+        if (pend || merge) fill_table(tab_b, geo.num_edges, g_b);
     }
     CT C0[R], C1[R];
     if (first) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, C0);
-    if (pend || last) cut_values<CT, JB>(P, l1 ? 1 : 0, W, geo.weighted, base, t, C1);
+    if (pend || last || merge) cut_values<CT, JB>(P, l1 ? 1 : 0, W, geo.weighted, base, t, C1);
     __syncthreads();
-    u64 off[R];
-    rt_offsets<TB, TT, 0>(P, t, off);
     const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
     d2v a[R];
+    {
+        u64 off[R];
+        rt_offsets<TB, TT, 0>(P, t, off);
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        if (first) {
-            const d2v f = Phase<CT>::get(tab_a, g_a, C0[j]);
-            a[j].x = amp0 * f.x;
-            a[j].y = amp0 * f.y;
-        } else {
-            a[j] = ld<true>(in + (base | off[j]));
+        for (int j = 0; j < R; ++j) {
+            if (first) {
+                const d2v f = Phase<CT>::get(tab_a, g_a, C0[j]);
+                a[j].x = amp0 * f.x;
+                a[j].y = amp0 * f.y;
+            } else {
+                a[j] = ld<true>(in + (base | off[j]));
+            }
         }
     }
     double sb, cb;
     sincos(q.theta[p + l], &sb, &cb);  // RX(2 beta): cos(beta), sin(beta)
     const u32 rx = P.rx_mask;
-    // Layout L0: register bits (tile bits TT..TB-1) and lane bits (0..5).
-#pragma unroll
-    for (int x = 0; x < JB; ++x) {
-        if ((rx >> (TT + x)) & 1) {
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-                if (!((j >> x) & 1)) rx_pair(a[j], a[j | (1 << x)], cb, sb);
-        }
-    }
-#pragma unroll
-    for (int lb = 0; lb < 6; ++lb) {
-        if ((rx >> lb) & 1) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) a[j] = rx_half(a[j], shfl_xor2(a[j], 1 << lb), cb, sb);
-        }
-    }
+    // Layout L0: register bits (tile bits TT..TB-1) and lane bits (0..5);
+    // then, if needed, layout L1 for the wave bits 6..6+W-1.
+    rt_rx<TB, TT, 0>(a, rx, cb, sb, kRegsAll, true);
     if (l1) {
-        // Layout L1: the wave bits 6..6+W-1 become register bits 0..W-1.
         rt_transpose<TB, TT, 0>(a, sh);
-#pragma unroll
-        for (int x = 0; x < Wb; ++x) {
-            if ((rx >> (6 + x)) & 1) {
-#pragma unroll
-                for (int j = 0; j < R; ++j)
-                    if (!((j >> x) & 1)) rx_pair(a[j], a[j | (1 << x)], cb, sb);
-            }
-        }
-        rt_offsets<TB, TT, 1>(P, t, off);
+        rt_rx<TB, TT, 1>(a, rx, cb, sb, kRegsLow, false);
     }
+    bool in_l1 = l1;
+    if constexpr (MERGE) {
+        // exp(-i gamma_{l+1} C), then layer l+1's RX gates on the same bits,
+        // starting in the layout the first set ended in and ending in L0.
+#pragma unroll
+        for (int j = 0; j < R; ++j) a[j] = cmul2(a[j], Phase<CT>::get(tab_b, g_b, C1[j]));
+        double sb2, cb2;
+        sincos(q.theta[p + l + 1], &sb2, &cb2);
+        rt_rx_cur<TB, TT>(a, rx, cb2, sb2, l1, true);
+        if (l1) {
+            rt_transpose<TB, TT, 1>(a, sh);
+            rt_rx<TB, TT, 0>(a, rx, cb2, sb2, kRegsLow, false);  // the register bits only L0 holds
+        }
+        in_l1 = false;
+    }
+    u64 off[R];
+    if (in_l1)
+        rt_offsets<TB, TT, 1>(P, t, off);
+    else
+        rt_offsets<TB, TT, 0>(P, t, off);
     double e_acc = 0.0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -532,23 +586,58 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W,
     }
 }
 
-// Inner product and RX(-2 beta) on register bit x of both vectors.
-template <int R>
-__device__ __forceinline__ void bwd_reg(d2v (&lm)[R], d2v (&ps)[R], int x, double c, double s, double &ipb) {
+// Inner products 2 Im<lam|X_j|psi> (without the factor 2) summed over the
+// tile bits j of `rx` that layout L reaches, with the same selection as rt_rx.
+// A lane pair contributes both of its terms, one in each lane.
+template <int TB, int TT, int L>
+__device__ __forceinline__ void rt_ip(const d2v (&lm)[1 << (TB - TT)], const d2v (&ps)[1 << (TB - TT)], u32 rx, int regs, bool lanes, double &acc) {
+    using G = RT<TB, TT>;
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        if ((j >> x) & 1) continue;
-        const int k = j | (1 << x);
-        ipb += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
-        rx_pair(lm[j], lm[k], c, s);
-        rx_pair(ps[j], ps[k], c, s);
+    for (int x = 0; x < G::JB; ++x) {
+        if (regs == kRegsNone || (regs == kRegsLow && x >= G::W)) continue;
+        if ((rx >> G::reg_bit(L, x)) & 1) {
+#pragma unroll
+            for (int j = 0; j < G::R; ++j) {
+                if ((j >> x) & 1) continue;
+                const int k = j | (1 << x);
+                acc += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
+            }
+        }
+    }
+    if (lanes) {
+#pragma unroll
+        for (int lb = 0; lb < 6; ++lb) {
+            if ((rx >> lb) & 1) {
+#pragma unroll
+                for (int j = 0; j < G::R; ++j) acc += im_conj_mul(lm[j], shfl_xor2(ps[j], 1 << lb));
+            }
+        }
     }
 }
 
-template <typename CT, int TB, int TT, bool POOLED>
+// The same for the inner products.
+template <int TB, int TT>
+__device__ __forceinline__ void rt_ip_cur(const d2v (&lm)[1 << (TB - TT)], const d2v (&ps)[1 << (TB - TT)], u32 rx, bool in_l1, bool lanes,
+                                          double &acc) {
+    using G = RT<TB, TT>;
+#pragma unroll
+    for (int x = 0; x < G::JB; ++x) {
+        const int tbit = in_l1 ? G::reg_bit(1, x) : G::reg_bit(0, x);
+        if (!((rx >> tbit) & 1)) continue;
+#pragma unroll
+        for (int j = 0; j < G::R; ++j) {
+            if ((j >> x) & 1) continue;
+            const int k = j | (1 << x);
+            acc += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
+        }
+    }
+    if (lanes) rt_ip<TB, TT, 0>(lm, ps, rx, kRegsNone, true, acc);
+}
+
+template <typename CT, int TB, int TT, bool POOLED, bool MERGE>
 __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
     using G = RT<TB, TT>;
-    constexpr int R = G::R, JB = G::JB, Wb = G::W;
+    constexpr int R = G::R, JB = G::JB;
     __shared__ d2v sh[G::TS];
     __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
     __shared__ double red[16];
@@ -559,22 +648,22 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
     double *partial = (double *)(q.region + B.part_off);
     const int t = threadIdx.x, l = P.layer, p = geo.p;
     const u64 base = qtile_base(P, q.tile);
-    const bool first = P.flags & QF_FIRST, pend = P.flags & QF_PHASE_END, last = P.flags & QF_LAST;
+    constexpr bool merge = MERGE;
+    const bool first = !MERGE && (P.flags & QF_FIRST), pend = !MERGE && (P.flags & QF_PHASE_END), last = !MERGE && (P.flags & QF_LAST);
     const bool l1 = P.use_l1;
-    const double g_a = q.theta[l], g_b = pend ? q.theta[l + 1] : 0.0;
+    const double g_a = q.theta[l], g_b = pend || merge ? q.theta[l + 1] : 0.0;
     if (!geo.weighted) {
         if (first) fill_table(tab_a, geo.num_edges, g_a);
-        if (pend) fill_table(tab_b, geo.num_edges, -g_b);  // exp(+i gamma C): undo the phase
+        if (pend || merge) fill_table(tab_b, geo.num_edges, -g_b);  // exp(+i gamma C): undo the phase
     }
-    // Order of work.  All inner products are taken before lambda is changed,
-    // with both vectors at the pass's end point, so psi needs no RX except on
-    // the wave bits that L0 reaches but L1 does not (B bits: tile bits
-    // TT..TT+W-1), which are undone on both vectors before the transpose; the
-    // inner products of the bits only L1 reaches (A bits: 6..6+W-1) are then
-    // taken at that common point.  Finally lambda alone gets RX(-2 beta) on
-    // the remaining bits and is stored from the layout it ends in.
+    // Register bits of the two layouts: A bits (tile 6..6+W-1) only in L1,
+    // B bits (tile TT..TT+W-1) only in L0, the rest of the register bits and
+    // the lane bits in both.  Inner products of one mixer may be taken at any
+    // point inside it as long as lambda and psi are at the same point (the RX
+    // gates of a mixer commute with every X_j); psi is transformed only as far
+    // as later inner products need it.
     d2v lm[R], ps[R];
-    double ipc = 0.0, ipb = 0.0, ipc1 = 0.0;
+    double ipc = 0.0, ipb = 0.0, ipc1 = 0.0, ipb2 = 0.0;
     {
         CT Cs[R];
         if (last || pend) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, Cs);
@@ -603,96 +692,99 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
     sincos(q.theta[p + l], &sb, &cb);
     const double sn = -sb;  // RX(-2 beta)
     const u32 rx = P.rx_mask;
-    // Inner products in L0: register bits (tile TT..TB-1) and lane bits.
-#pragma unroll
-    for (int x = 0; x < JB; ++x) {
-        if ((rx >> G::reg_bit(0, x)) & 1) {
+    bool in_l1 = false;
+    if constexpr (MERGE) {
+        // Layer l+1's RX gates: inner products at the end point, then undone
+        // on both vectors (psi is needed again below), L0 first, then L1.
+        double sb2, cb2;
+        sincos(q.theta[p + l + 1], &sb2, &cb2);
+        const double sn2 = -sb2;
+        rt_ip<TB, TT, 0>(lm, ps, rx, kRegsAll, true, ipb2);
+        rt_rx<TB, TT, 0>(lm, rx, cb2, sn2, kRegsAll, true);
+        rt_rx<TB, TT, 0>(ps, rx, cb2, sn2, kRegsAll, true);
+        if (l1) {
+            rt_transpose<TB, TT, 0>(lm, sh);
+            rt_transpose<TB, TT, 0>(ps, sh);
+            rt_ip<TB, TT, 1>(lm, ps, rx, kRegsLow, false, ipb2);
+            rt_rx<TB, TT, 1>(lm, rx, cb2, sn2, kRegsLow, false);
+            rt_rx<TB, TT, 1>(ps, rx, cb2, sn2, kRegsLow, false);
+            in_l1 = true;
+        }
+        // The cost phase between the two mixers, in the current layout.  Its
+        // inner product Im(conj(lam) C psi) is unchanged by the common unit
+        // factor, so it is taken after the undo, on the new values.
+        {
+            CT Cm[R];
+            cut_values<CT, JB>(P, l1 ? 1 : 0, W, geo.weighted, base, t, Cm);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                if ((j >> x) & 1) continue;
-                const int k = j | (1 << x);
-                ipb += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
+                const d2v f = Phase<CT>::get(tab_b, -g_b, Cm[j]);
+                lm[j] = cmul2(lm[j], f);
+                ps[j] = cmul2(ps[j], f);
+                ipc += (double)Cm[j] * im_conj_mul(lm[j], ps[j]);
             }
         }
-    }
-#pragma unroll
-    for (int lb = 0; lb < 6; ++lb) {
-        if ((rx >> lb) & 1) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) ipb += im_conj_mul(lm[j], shfl_xor2(ps[j], 1 << lb));  // both lanes: both terms
+        // Layer l's RX gates, back to L0: inner products of the bits the
+        // current layout reaches; with L1, the A bits undone on both, the
+        // transpose and the B-bit inner products; then lambda alone undoes
+        // the rest and is stored from L0.
+        rt_ip_cur<TB, TT>(lm, ps, rx, l1, true, ipb);
+        if (l1) {
+            rt_rx<TB, TT, 1>(lm, rx, cb, sn, kRegsLow, false);
+            rt_rx<TB, TT, 1>(ps, rx, cb, sn, kRegsLow, false);
+            rt_transpose<TB, TT, 1>(lm, sh);
+            rt_transpose<TB, TT, 1>(ps, sh);
+            rt_ip<TB, TT, 0>(lm, ps, rx, kRegsLow, false, ipb);
         }
-    }
-    if (l1) {
-        // Undo the B bits on both vectors, move both to L1, take the A-bit inner products.
-#pragma unroll
-        for (int x = 0; x < Wb; ++x) {
-            if ((rx >> (TT + x)) & 1) {
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    if ((j >> x) & 1) continue;
-                    const int k = j | (1 << x);
-                    rx_pair(lm[j], lm[k], cb, sn);
-                    rx_pair(ps[j], ps[k], cb, sn);
-                }
-            }
+        rt_rx<TB, TT, 0>(lm, rx, cb, sn, kRegsAll, true);
+        in_l1 = false;
+    } else {
+        // One mixer: inner products of the L0 bits; if some RX bit needs L1,
+        // undo the B bits on both, transpose, take the A-bit inner products;
+        // psi is then dead and lambda undoes every bit not yet undone.
+        rt_ip<TB, TT, 0>(lm, ps, rx, kRegsAll, true, ipb);
+        if (l1) {
+            rt_rx<TB, TT, 0>(lm, rx, cb, sn, kRegsLow, false);
+            rt_rx<TB, TT, 0>(ps, rx, cb, sn, kRegsLow, false);
+            rt_transpose<TB, TT, 0>(lm, sh);
+            rt_transpose<TB, TT, 0>(ps, sh);
+            rt_ip<TB, TT, 1>(lm, ps, rx, kRegsLow, false, ipb);
+            in_l1 = true;
         }
-        rt_transpose<TB, TT, 0>(lm, sh);
-        rt_transpose<TB, TT, 0>(ps, sh);
-#pragma unroll
-        for (int x = 0; x < Wb; ++x) {
-            if ((rx >> (6 + x)) & 1) {
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    if ((j >> x) & 1) continue;
-                    const int k = j | (1 << x);
-                    ipb += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
-                }
-            }
-        }
-    }
-    // psi is dead: RX(-2 beta) on lambda for every bit not yet undone.
-    const int L = l1 ? 1 : 0;
-#pragma unroll
-    for (int x = 0; x < JB; ++x) {
-        const int tbit = l1 ? G::reg_bit(1, x) : G::reg_bit(0, x);
-        if (l1 && x < Wb ? !((rx >> (6 + x)) & 1) : !((rx >> tbit) & 1)) continue;
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-            if (!((j >> x) & 1)) rx_pair(lm[j], lm[j | (1 << x)], cb, sn);
-    }
-#pragma unroll
-    for (int lb = 0; lb < 6; ++lb) {
-        if ((rx >> lb) & 1) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) lm[j] = rx_half(lm[j], shfl_xor2(lm[j], 1 << lb), cb, sn);
-        }
+        rt_rx_cur<TB, TT>(lm, rx, cb, sn, l1, true);
     }
     const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
     if (first) {
         CT Cf[R];
-        cut_values<CT, JB>(P, L, W, geo.weighted, base, t, Cf);
+        cut_values<CT, JB>(P, in_l1 ? 1 : 0, W, geo.weighted, base, t, Cf);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const d2v f = Phase<CT>::get(tab_a, g_a, Cf[j]);  // phi_1 = 2^{-n/2} exp(-i gamma_1 C)
             ipc1 += (double)Cf[j] * amp0 * (lm[j].x * f.y - lm[j].y * f.x);
         }
     } else {
+        // Recompute the store offsets rather than keep the load addresses
+        // live through the pass (an empty asm hides that t is unchanged).
+        int ts = t;
+        asm volatile("" : "+v"(ts));
         u64 off[R];
-        if (l1)
-            rt_offsets<TB, TT, 1>(P, t, off);
+        if (in_l1)
+            rt_offsets<TB, TT, 1>(P, ts, off);
         else
-            rt_offsets<TB, TT, 0>(P, t, off);
+            rt_offsets<TB, TT, 0>(P, ts, off);
 #pragma unroll
         for (int j = 0; j < R; ++j) st<true>(lam + (base | off[j]), lm[j]);
     }
     const double tc = qblock_sum(ipc, red);
     const double tbx = qblock_sum(ipb, red);
     const double tc1 = qblock_sum(ipc1, red);
+    const double tb2 = qblock_sum(ipb2, red);
     if (t == 0) {
-        double *o = partial + ((u64)P.pidx * geo.G + q.tile) * 3;
+        double *o = partial + ((u64)P.pidx * geo.G + q.tile) * kQSlots;
         o[0] = tc;
         o[1] = tbx;
         o[2] = tc1;
+        o[3] = tb2;
     }
 }
 
@@ -711,19 +803,31 @@ __global__ __launch_bounds__(256) void k_qaoa_final(QGeom geo, QBatch B, double 
     const char *region = B.ws + c * B.circ_bytes;
     const double *partial = (const double *)(region + B.part_off);
     const double *e_partial = (const double *)(region + B.epart_off);
+    // Which passes hold the component.  Without merging, layer l is passes
+    // lP .. lP + P - 1 and gamma_{l+1} (l >= 1, 0-based) sits at the end of
+    // pass lP - 1.  With merging, layer l is passes l(P - 1) .. l(P - 1) + P - 1;
+    // its first pass (l >= 1) is the merged pass that carries gamma_l in the
+    // middle and layer l's RX gates in slot 3.
+    auto sum_slot = [&](int pidx, int slot) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < G; b += blockDim.x) v += partial[((u64)pidx * G + b) * kQSlots + slot];
+        return v;
+    };
     double a = 0.0;
     if (k == 2 * p) {
         for (int b = threadIdx.x; b < G; b += blockDim.x) a += e_partial[b];
     } else if (k < p) {
-        // gamma_{k+1}: phase at the start of pass 0 (k = 0, slot 2) or the end of pass (k-1, P-1) (slot 0).
-        const int pidx = k == 0 ? 0 : (k - 1) * P + (P - 1);
-        const int slot = k == 0 ? 2 : 0;
-        for (int b = threadIdx.x; b < G; b += blockDim.x) a += partial[((u64)pidx * G + b) * 3 + slot];
+        if (k == 0)
+            a = sum_slot(0, 2);
+        else
+            a = sum_slot(geo.merge ? k * (P - 1) : k * P - 1, 0);
     } else {
         const int l = k - p;
         for (int g = 0; g < P; ++g) {
-            const int pidx = l * P + g;
-            for (int b = threadIdx.x; b < G; b += blockDim.x) a += partial[((u64)pidx * G + b) * 3 + 1];
+            if (geo.merge)
+                a += sum_slot(l * (P - 1) + g, g == 0 && l > 0 ? 3 : 1);
+            else
+                a += sum_slot(l * P + g, 1);
         }
     }
     const double t = qblock_sum(a, red);
@@ -814,14 +918,42 @@ int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double 
         }
     }
     const int P = (int)groups.size();
+    // Pass order.  With several qubit groups, odd layers walk the groups in
+    // reverse (the RX gates of one mixer commute), so every layer starts on
+    // the group the previous layer ended with and the two passes merge into
+    // one: p(P - 1) + 1 passes instead of pP.
+    static const bool merge_on = [] {
+        const char *e = getenv("QSIM_QAOA_MERGE");
+        return !(e && e[0] == '0');
+    }();
+    const bool merge = P >= 2 && merge_on;
+    struct Step {
+        int layer, g, flags;
+    };
+    std::vector<Step> seq;
+    for (int l = 0; l < p; ++l) {
+        for (int i = 0; i < P; ++i) {
+            const int g = merge && (l & 1) ? P - 1 - i : i;
+            if (merge && l > 0 && i == 0) {
+                seq.back().flags |= QF_MERGE;
+                continue;
+            }
+            int f = 0;
+            if (l == 0 && i == 0) f |= QF_FIRST;
+            if (!merge && i == P - 1 && l < p - 1) f |= QF_PHASE_END;
+            seq.push_back(Step{l, g, f});
+        }
+    }
+    seq.back().flags |= QF_LAST;
     plan.shape = shape;
     plan.rt = rt;
-    plan.geo = QGeom{n, p, P, tb, 1 << (n - tb), n - tb, num_edges, w != nullptr};
+    plan.geo = QGeom{n, p, P, tb, 1 << (n - tb), n - tb, num_edges, w != nullptr, (int)seq.size(), merge ? 1 : 0};
     for (int e = 0; e < num_edges; ++e) plan.W.w[e] = w ? w[e] : 1.0;
     plan.passes.clear();
     const int TT = shape.TT, Wb = TT - 6;
-    for (int l = 0; l < p; ++l) {
-        for (int g = 0; g < P; ++g) {
+    for (int k = 0; k < (int)seq.size(); ++k) {
+        {
+            const int l = seq[k].layer, g = seq[k].g;
             QPass Q{};
             uint64_t T = 0;
             if (g == 0) {
@@ -847,11 +979,8 @@ int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double 
             for (int q : groups[g]) Q.rx_mask |= 1u << pos[q];
             Q.use_l1 = rt && ((Q.rx_mask >> 6) & ((1u << Wb) - 1)) != 0;
             Q.layer = l;
-            Q.pidx = l * P + g;
-            Q.flags = 0;
-            if (l == 0 && g == 0) Q.flags |= QF_FIRST;
-            if (g == P - 1 && l < p - 1) Q.flags |= QF_PHASE_END;
-            if (g == P - 1 && l == p - 1) Q.flags |= QF_LAST;
+            Q.pidx = k;
+            Q.flags = seq[k].flags;
             for (int L = 0; L < (rt ? 2 : 1); ++L) {
                 std::vector<QEdge> cls[EC_N];
                 for (int e = 0; e < num_edges; ++e) {
@@ -889,7 +1018,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 QLayout qaoa_layout(const QGeom &g, int with_grad) {
     QLayout L{};
     const size_t sb = ((size_t)1 << g.n) * 16;
-    const size_t np = (size_t)g.p * g.P;
+    const size_t np = (size_t)g.np;
     size_t off = 0;
     if (with_grad) {
         L.ckpt = off;
@@ -897,7 +1026,7 @@ QLayout qaoa_layout(const QGeom &g, int with_grad) {
         L.lam = off;
         off += sb;
         L.part = off;
-        off = align256(off + np * (size_t)g.G * 3 * sizeof(double));
+        off = align256(off + np * (size_t)g.G * kQSlots * sizeof(double));
     } else {
         L.ckpt = off;  // the in-place state
         off += sb;
@@ -910,20 +1039,32 @@ QLayout qaoa_layout(const QGeom &g, int with_grad) {
 }
 
 // Kernel pair for one (weights, shape) choice.
+// Whether pass k of a plan with this geometry is a merged pass: with
+// merging, layer l >= 1 starts at pass l(P - 1), which merges with the last
+// pass of layer l - 1 (the order build_qplan lays out).
+static bool qpass_merged(const QGeom &g, int k) { return g.merge && k > 0 && k % (g.P - 1) == 0 && k < g.np - 1; }
+
 template <typename CT, int TB, int TT, bool POOLED> struct RtKernels {
     static constexpr int threads = 1 << TT;
-    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B) {
-        hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED>), grid, dim3(threads), 0, st, P, W, g, B);
+    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool merged) {
+        if (merged)
+            hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED, true>), grid, dim3(threads), 0, st, P, W, g, B);
+        else
+            hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED, false>), grid, dim3(threads), 0, st, P, W, g, B);
     }
-    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B) {
-        hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED>), grid, dim3(threads), 0, st, P, W, g, B);
+    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool merged) {
+        if (merged)
+            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, true>), grid, dim3(threads), 0, st, P, W, g, B);
+        else
+            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, false>), grid, dim3(threads), 0, st, P, W, g, B);
     }
 };
+// LDS kernels serve n < 10: one qubit group, so no merged passes.
 template <typename CT, bool POOLED> struct LdsKernels {
-    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B) {
+    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool) {
         hipLaunchKernelGGL((k_qaoa_fwd_lds<CT, POOLED>), grid, dim3(kLdsThreads), 0, st, P, W, g, B);
     }
-    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B) {
+    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool) {
         hipLaunchKernelGGL((k_qaoa_bwd_lds<CT, POOLED>), grid, dim3(kLdsThreads), 0, st, P, W, g, B);
     }
 };
@@ -935,7 +1076,7 @@ template <typename K, bool POOLED>
 static void launch_seq(const QGeom &g, const QPass *passes, const QWeights &W, QBatch B, int nb, double *E_out, double *grad_out, hipStream_t st) {
     const QLayout L = qaoa_layout(g, grad_out != nullptr);
     const size_t sb = ((size_t)1 << g.n) * 16;
-    const int np = g.p * g.P;
+    const int np = g.np;
     const dim3 grid((unsigned)((u64)nb << g.glog));
     B.lam_off = L.lam;
     B.part_off = L.part;
@@ -947,12 +1088,12 @@ static void launch_seq(const QGeom &g, const QPass *passes, const QWeights &W, Q
             B.k = k;
             B.in_off = k == 0 ? -1 : (long long)(L.ckpt + (size_t)(k - 1) * sb);
             B.out_off = (long long)(L.ckpt + (size_t)k * sb);
-            K::fwd(grid, st, pass(k), W, g, B);
+            K::fwd(grid, st, pass(k), W, g, B, qpass_merged(g, k));
         }
         for (int k = np - 1; k >= 0; --k) {
             B.k = k;
             B.in_off = (long long)(L.ckpt + (size_t)k * sb);
-            K::bwd(grid, st, pass(k), W, g, B);
+            K::bwd(grid, st, pass(k), W, g, B, qpass_merged(g, k));
         }
         hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(2 * g.p + 1, nb), dim3(256), 0, st, g, B, E_out, grad_out, 1);
     } else {
@@ -960,7 +1101,7 @@ static void launch_seq(const QGeom &g, const QPass *passes, const QWeights &W, Q
             B.k = k;
             B.in_off = k == 0 ? -1 : (long long)L.ckpt;
             B.out_off = k == np - 1 ? -1 : (long long)L.ckpt;
-            K::fwd(grid, st, pass(k), W, g, B);
+            K::fwd(grid, st, pass(k), W, g, B, qpass_merged(g, k));
         }
         hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(1, nb), dim3(256), 0, st, g, B, E_out, (double *)nullptr, 0);
     }

@@ -295,6 +295,17 @@ template <typename R> struct alignas(16) SGate {
 
 __device__ __forceinline__ int sbyte(uint32_t w, int k) { return (int)(int8_t)(uint8_t)(w >> (8 * k)); }
 
+// A staged header is the same in every lane (all lanes read one LDS address);
+// moving it to scalar registers lets the compiler branch on the gate kind and
+// bit positions with scalar branches instead of per-lane masks and selects.
+__device__ __forceinline__ uint4 uniform_header(uint4 h) {
+    h.x = __builtin_amdgcn_readfirstlane(h.x);
+    h.y = __builtin_amdgcn_readfirstlane(h.y);
+    h.z = __builtin_amdgcn_readfirstlane(h.z);
+    h.w = __builtin_amdgcn_readfirstlane(h.w);
+    return h;
+}
+
 // Gates are staged in LDS this many at a time (and sweeps hold at most this
 // many gates), so their parameters are fetched by all threads at once rather
 // than one dependent global load per gate.
@@ -338,8 +349,8 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
     int gi = 0;
     while (gi < count) {
         if (gi >= ce) stage(gi);
-        if (gi + (int)sg[gi - cb].h.w > ce) stage(gi);
-        const uint4 hh = sg[gi - cb].h;
+        if (gi + (int)__builtin_amdgcn_readfirstlane(sg[gi - cb].h.w) > ce) stage(gi);
+        const uint4 hh = uniform_header(sg[gi - cb].h);
         const int run = (int)hh.w, g0 = sbyte(hh.z, 0), g1 = sbyte(hh.z, 1), g2 = sbyte(hh.z, 2);
         cx<R> v[GMAX][8];
         u32 m0[GMAX];
@@ -354,7 +365,7 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
         }
         for (int r = 0; r < run; ++r) {
             const SGate<R> &x = sg[gi - cb + r];
-            const uint4 h = x.h;
+            const uint4 h = uniform_header(x.h);
             cx<R> val[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) val[e] = reinterpret_cast<const cx<R> *>(x.val)[e];

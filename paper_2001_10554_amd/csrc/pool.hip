@@ -103,12 +103,14 @@ static int build_class(const qs_pool_desc *d, PoolClass &C, QShape shape, bool g
     for (int g : C.graphs) {
         const int ne = d->edge_offset[g + 1] - d->edge_offset[g];
         max_edges = ne > max_edges ? ne : max_edges;
-        build_qplan(C.n, d->p, ne, d->edges + 2 * (size_t)d->edge_offset[g], nullptr, shape, plan);
+        if (int rc = build_qplan(C.n, d->p, ne, d->edges + 2 * (size_t)d->edge_offset[g], nullptr, shape, plan)) return rc;
         all.insert(all.end(), plan.passes.begin(), plan.passes.end());
     }
     C.proto.shape = plan.shape;
     C.proto.rt = plan.rt;
     C.proto.geo = plan.geo;
+    C.proto.merged = plan.merged;  // the same pass structure for every graph of the class
+    C.proto.map = plan.map;
     C.proto.geo.num_edges = max_edges;  // phase tables cover every graph of the class
     C.proto.passes.clear();
     C.np = C.proto.geo.np;
@@ -209,7 +211,7 @@ static size_t max_circ_bytes(const qs_pool_desc *d, bool grad) {
         QPlan plan;
         const int ne = d->edge_offset[g + 1] - d->edge_offset[g];
         for (QShape s : qaoa_candidate_shapes(d->n_qubits[g])) {
-            build_qplan(d->n_qubits[g], d->p, ne, d->edges + 2 * (size_t)d->edge_offset[g], nullptr, s, plan);
+            if (build_qplan(d->n_qubits[g], d->p, ne, d->edges + 2 * (size_t)d->edge_offset[g], nullptr, s, plan)) continue;  // shape unusable
             const size_t b = qaoa_layout(plan.geo, grad).bytes;
             m = b > m ? b : m;
         }

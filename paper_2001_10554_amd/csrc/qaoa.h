@@ -46,9 +46,18 @@ struct QWeights {
     double w[kQMaxEdges];
 };
 
-// np: passes per circuit; merge: layer boundaries are merged passes (P >= 2).
+// np: passes per circuit.
 struct QGeom {
-    int n, p, P, tb, G, glog, num_edges, weighted, np, merge;
+    int n, p, P, tb, G, glog, num_edges, weighted, np;
+};
+
+// Which (pass, slot) partial sums make up each output of the final
+// reduction: component c < 2p (gamma_1..gamma_p, beta_1..beta_p) sums items
+// start[c] .. start[c+1]-1, item = pass << 2 | slot, in pass order.
+constexpr int kQMaxP = 64, kQMaxItems = 512;
+struct QMap {
+    uint16_t start[2 * kQMaxP + 1];
+    uint16_t item[kQMaxItems];
 };
 
 // Where circuit c of a launch keeps its data: ws + c * circ_bytes + offset
@@ -76,7 +85,9 @@ struct QPlan {
     QShape shape;
     bool rt;
     QGeom geo;
-    std::vector<QPass> passes;  // forward order (geo.np passes)
+    std::vector<QPass> passes;   // forward order (geo.np passes)
+    std::vector<uint8_t> merged; // per pass: a merged pass (its own kernel instantiation)
+    QMap map;
     QWeights W;
 };
 

@@ -473,12 +473,18 @@ __device__ __forceinline__ void rt_rx(d2v (&a)[1 << (TB - TT)], u32 rx, double c
             if (!((j >> x) & 1)) rx_pair(a[j], a[j | (1 << x)], c, s);
     }
     if (lanes) {
-#pragma unroll
-        for (int lb = 0; lb < 6; ++lb) {
-            const bool on = (rx >> lb) & 1;
+        // The lane bits that take RX form a top range [lo, 5] (a pass's tile
+        // holds its new qubits on the highest positions); a run-time loop over
+        // that range does no shuffles for the others, and identity
+        // coefficients keep any other mask correct.
+        const u32 lm = rx & 63u;
+        const int lo = lm ? __builtin_ctz(lm) : 6;
+#pragma unroll 1
+        for (int lb = lo; lb < 6; ++lb) {
+            const bool on = (lm >> lb) & 1;
             const double c = on ? cb : 1.0, s = on ? sb : 0.0;
 #pragma unroll
-            for (int j = 0; j < G::R; ++j) a[j] = rx_half(a[j], shfl_xor2(a[j], on ? 1 << lb : 0), c, s);
+            for (int j = 0; j < G::R; ++j) a[j] = rx_half(a[j], shfl_xor2(a[j], 1 << lb), c, s);
         }
     }
 }
@@ -605,12 +611,14 @@ __device__ __forceinline__ void rt_ip(const d2v (&lm)[1 << (TB - TT)], const d2v
         }
     }
     if (lanes) {
+        const u32 lmask = rx & 63u;
+        const int lo = lmask ? __builtin_ctz(lmask) : 6;
+#pragma unroll 1
+        for (int lb = lo; lb < 6; ++lb) {
+            double t = 0.0;
 #pragma unroll
-        for (int lb = 0; lb < 6; ++lb) {
-            if ((rx >> lb) & 1) {
-#pragma unroll
-                for (int j = 0; j < G::R; ++j) acc += im_conj_mul(lm[j], shfl_xor2(ps[j], 1 << lb));
-            }
+            for (int j = 0; j < G::R; ++j) t += im_conj_mul(lm[j], shfl_xor2(ps[j], 1 << lb));
+            if ((lmask >> lb) & 1) acc += t;
         }
     }
 }
@@ -794,40 +802,25 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
 // in a fixed order.  Output k < 2p: gradient component; k = 2p: E.  Without a
 // gradient the grid has one block per circuit, which computes E.
 template <bool POOLED>
-__global__ __launch_bounds__(256) void k_qaoa_final(QGeom geo, QBatch B, double *__restrict__ E_out, double *__restrict__ grad_out, int with_grad) {
+__global__ __launch_bounds__(256) void k_qaoa_final(QGeom geo, QBatch B, QMap map, double *__restrict__ E_out, double *__restrict__ grad_out,
+                                                     int with_grad) {
     __shared__ double red[16];
-    const int p = geo.p, P = geo.P, G = geo.G;
+    const int p = geo.p, G = geo.G;
     const int k = with_grad ? (int)blockIdx.x : 2 * p;
     const u64 c = blockIdx.y;
     const u64 cid = POOLED ? (u64)B.circ_map[B.c0 + c] : c;
     const char *region = B.ws + c * B.circ_bytes;
     const double *partial = (const double *)(region + B.part_off);
     const double *e_partial = (const double *)(region + B.epart_off);
-    // Which passes hold the component.  Without merging, layer l is passes
-    // lP .. lP + P - 1 and gamma_{l+1} (l >= 1, 0-based) sits at the end of
-    // pass lP - 1.  With merging, layer l is passes l(P - 1) .. l(P - 1) + P - 1;
-    // its first pass (l >= 1) is the merged pass that carries gamma_l in the
-    // middle and layer l's RX gates in slot 3.
-    auto sum_slot = [&](int pidx, int slot) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < G; b += blockDim.x) v += partial[((u64)pidx * G + b) * kQSlots + slot];
-        return v;
-    };
     double a = 0.0;
     if (k == 2 * p) {
         for (int b = threadIdx.x; b < G; b += blockDim.x) a += e_partial[b];
-    } else if (k < p) {
-        if (k == 0)
-            a = sum_slot(0, 2);
-        else
-            a = sum_slot(geo.merge ? k * (P - 1) : k * P - 1, 0);
     } else {
-        const int l = k - p;
-        for (int g = 0; g < P; ++g) {
-            if (geo.merge)
-                a += sum_slot(l * (P - 1) + g, g == 0 && l > 0 ? 3 : 1);
-            else
-                a += sum_slot(l * P + g, 1);
+        for (int i = map.start[k]; i < map.start[k + 1]; ++i) {
+            const int pidx = map.item[i] >> 2, slot = map.item[i] & 3;
+            double v = 0.0;
+            for (int b = threadIdx.x; b < G; b += blockDim.x) v += partial[((u64)pidx * G + b) * kQSlots + slot];
+            a += v;
         }
     }
     const double t = qblock_sum(a, red);
@@ -918,36 +911,74 @@ int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double 
         }
     }
     const int P = (int)groups.size();
-    // Pass order.  With several qubit groups, odd layers walk the groups in
-    // reverse (the RX gates of one mixer commute), so every layer starts on
-    // the group the previous layer ended with and the two passes merge into
-    // one: p(P - 1) + 1 passes instead of pP.
-    static const bool merge_on = [] {
+    // Pass order.  With several qubit groups the RX gates of one mixer may be
+    // applied in any group order, so odd layers walk the groups in the reverse
+    // of even layers and every layer starts on the group the previous layer
+    // ended with; the two passes on that group can merge into one (RX of
+    // layer l, the cost phase of layer l+1, RX of layer l+1): p(P-1)+1 passes
+    // instead of pP.  A merged pass does twice the arithmetic on the same
+    // traffic; on the first group, whose lane bits all take RX (lane-bit gates
+    // need wavefront shuffles), that costs more than the saved pass at 24
+    // qubits, so with three or more groups the first group sits in the middle
+    // of every layer and is never a boundary.  Tuning knob QSIM_QAOA_MERGE:
+    // 0 never merge, 1 merge every boundary (default), 2 skip boundaries on
+    // the first group.
+    static const int merge_mode = [] {
         const char *e = getenv("QSIM_QAOA_MERGE");
-        return !(e && e[0] == '0');
+        return e ? atoi(e) : 1;
     }();
-    const bool merge = P >= 2 && merge_on;
+    std::vector<int> order;  // even layers; odd layers use the reverse
+    if (P >= 3) {
+        order.push_back(1);
+        order.push_back(0);
+        for (int g = 2; g < P; ++g) order.push_back(g);
+    } else {
+        for (int g = 0; g < P; ++g) order.push_back(g);
+    }
     struct Step {
         int layer, g, flags;
     };
     std::vector<Step> seq;
     for (int l = 0; l < p; ++l) {
         for (int i = 0; i < P; ++i) {
-            const int g = merge && (l & 1) ? P - 1 - i : i;
-            if (merge && l > 0 && i == 0) {
+            const int g = P >= 2 && (l & 1) ? order[P - 1 - i] : order[i];
+            const bool boundary = l > 0 && i == 0 && P >= 2;  // same group as the previous pass
+            if (boundary && (merge_mode == 1 || (merge_mode == 2 && g != 0))) {
                 seq.back().flags |= QF_MERGE;
                 continue;
             }
-            int f = 0;
-            if (l == 0 && i == 0) f |= QF_FIRST;
-            if (!merge && i == P - 1 && l < p - 1) f |= QF_PHASE_END;
-            seq.push_back(Step{l, g, f});
+            if (l > 0 && i == 0) seq.back().flags |= QF_PHASE_END;  // the previous layer's last pass
+            seq.push_back(Step{l, g, l == 0 && i == 0 ? QF_FIRST : 0});
         }
     }
     seq.back().flags |= QF_LAST;
+    // Output map: gamma_1 from the first pass (slot 2); gamma_{l+1} from the
+    // pass that applies that phase (slot 0); beta_l from every pass holding
+    // layer l's RX gates (slot 1, or slot 3 for the second layer of a merged pass).
+    {
+        std::vector<std::vector<uint16_t>> comp(2 * p);
+        for (int k = 0; k < (int)seq.size(); ++k) {
+            const int l = seq[k].layer, f = seq[k].flags;
+            if (f & QF_FIRST) comp[0].push_back((uint16_t)(k << 2 | 2));
+            if (f & (QF_PHASE_END | QF_MERGE)) comp[l + 1].push_back((uint16_t)(k << 2 | 0));
+            comp[p + l].push_back((uint16_t)(k << 2 | 1));
+            if (f & QF_MERGE) comp[p + l + 1].push_back((uint16_t)(k << 2 | 3));
+        }
+        int at = 0;
+        for (int c = 0; c < 2 * p; ++c) {
+            plan.map.start[c] = (uint16_t)at;
+            for (uint16_t x : comp[c]) {
+                if (at >= kQMaxItems) return fail(QS_ERR_UNSUPPORTED, "QAOA plan exceeds the output map");
+                plan.map.item[at++] = x;
+            }
+        }
+        plan.map.start[2 * p] = (uint16_t)at;
+    }
+    plan.merged.clear();
+    for (const Step &st : seq) plan.merged.push_back((st.flags & QF_MERGE) ? 1 : 0);
     plan.shape = shape;
     plan.rt = rt;
-    plan.geo = QGeom{n, p, P, tb, 1 << (n - tb), n - tb, num_edges, w != nullptr, (int)seq.size(), merge ? 1 : 0};
+    plan.geo = QGeom{n, p, P, tb, 1 << (n - tb), n - tb, num_edges, w != nullptr, (int)seq.size()};
     for (int e = 0; e < num_edges; ++e) plan.W.w[e] = w ? w[e] : 1.0;
     plan.passes.clear();
     const int TT = shape.TT, Wb = TT - 6;
@@ -1039,11 +1070,6 @@ QLayout qaoa_layout(const QGeom &g, int with_grad) {
 }
 
 // Kernel pair for one (weights, shape) choice.
-// Whether pass k of a plan with this geometry is a merged pass: with
-// merging, layer l >= 1 starts at pass l(P - 1), which merges with the last
-// pass of layer l - 1 (the order build_qplan lays out).
-static bool qpass_merged(const QGeom &g, int k) { return g.merge && k > 0 && k % (g.P - 1) == 0 && k < g.np - 1; }
-
 template <typename CT, int TB, int TT, bool POOLED> struct RtKernels {
     static constexpr int threads = 1 << TT;
     static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool merged) {
@@ -1073,7 +1099,9 @@ template <typename CT, bool POOLED> struct LdsKernels {
 // takes the pass descriptors by value from `passes`; pooled mode reads them
 // from B.passes on the device.
 template <typename K, bool POOLED>
-static void launch_seq(const QGeom &g, const QPass *passes, const QWeights &W, QBatch B, int nb, double *E_out, double *grad_out, hipStream_t st) {
+static void launch_seq(const QPlan &plan, const QPass *passes, const QWeights &W, QBatch B, int nb, double *E_out, double *grad_out,
+                       hipStream_t st) {
+    const QGeom &g = plan.geo;
     const QLayout L = qaoa_layout(g, grad_out != nullptr);
     const size_t sb = ((size_t)1 << g.n) * 16;
     const int np = g.np;
@@ -1083,39 +1111,39 @@ static void launch_seq(const QGeom &g, const QPass *passes, const QWeights &W, Q
     B.epart_off = L.epart;
     static const QPass dummy{};
     auto pass = [&](int k) -> const QPass & { return POOLED ? dummy : passes[k]; };
+    auto merged = [&](int k) { return plan.merged[k] != 0; };
     if (grad_out) {
         for (int k = 0; k < np; ++k) {
             B.k = k;
             B.in_off = k == 0 ? -1 : (long long)(L.ckpt + (size_t)(k - 1) * sb);
             B.out_off = (long long)(L.ckpt + (size_t)k * sb);
-            K::fwd(grid, st, pass(k), W, g, B, qpass_merged(g, k));
+            K::fwd(grid, st, pass(k), W, g, B, merged(k));
         }
         for (int k = np - 1; k >= 0; --k) {
             B.k = k;
             B.in_off = (long long)(L.ckpt + (size_t)k * sb);
-            K::bwd(grid, st, pass(k), W, g, B, qpass_merged(g, k));
+            K::bwd(grid, st, pass(k), W, g, B, merged(k));
         }
-        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(2 * g.p + 1, nb), dim3(256), 0, st, g, B, E_out, grad_out, 1);
+        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(2 * g.p + 1, nb), dim3(256), 0, st, g, B, plan.map, E_out, grad_out, 1);
     } else {
         for (int k = 0; k < np; ++k) {
             B.k = k;
             B.in_off = k == 0 ? -1 : (long long)L.ckpt;
             B.out_off = k == np - 1 ? -1 : (long long)L.ckpt;
-            K::fwd(grid, st, pass(k), W, g, B, qpass_merged(g, k));
+            K::fwd(grid, st, pass(k), W, g, B, merged(k));
         }
-        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(1, nb), dim3(256), 0, st, g, B, E_out, (double *)nullptr, 0);
+        hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(1, nb), dim3(256), 0, st, g, B, plan.map, E_out, (double *)nullptr, 0);
     }
 }
 
 template <typename CT, bool POOLED>
 static void launch_ct(const QPlan &plan, const QPass *passes, const QWeights &W, const QBatch &B, int nb, double *E_out, double *grad_out, hipStream_t st) {
-    const QGeom &g = plan.geo;
-    if (!plan.rt) return launch_seq<LdsKernels<CT, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
+    if (!plan.rt) return launch_seq<LdsKernels<CT, POOLED>, POOLED>(plan, passes, W, B, nb, E_out, grad_out, st);
     switch (plan.shape.TB) {
-    case 10: return launch_seq<RtKernels<CT, 10, 8, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
-    case 11: return launch_seq<RtKernels<CT, 11, 8, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
-    case 12: return launch_seq<RtKernels<CT, 12, 9, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
-    default: return launch_seq<RtKernels<CT, 13, 9, POOLED>, POOLED>(g, passes, W, B, nb, E_out, grad_out, st);
+    case 10: return launch_seq<RtKernels<CT, 10, 8, POOLED>, POOLED>(plan, passes, W, B, nb, E_out, grad_out, st);
+    case 11: return launch_seq<RtKernels<CT, 11, 8, POOLED>, POOLED>(plan, passes, W, B, nb, E_out, grad_out, st);
+    case 12: return launch_seq<RtKernels<CT, 12, 9, POOLED>, POOLED>(plan, passes, W, B, nb, E_out, grad_out, st);
+    default: return launch_seq<RtKernels<CT, 13, 9, POOLED>, POOLED>(plan, passes, W, B, nb, E_out, grad_out, st);
     }
 }
 
@@ -1168,7 +1196,7 @@ QS_API int qs_qaoa_workspace_bytes(const qs_qaoa_desc *d, int with_grad, size_t 
         if (int rc = check_desc(d)) return rc;
         if (!bytes) return fail(QS_ERR_ARG, "null output");
         QPlan plan;
-        build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_shape(d->n), plan);
+        if (int rc = build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_shape(d->n), plan)) return rc;
         *bytes = qaoa_layout(plan.geo, with_grad).bytes;
         return QS_OK;
     } catch (...) {
@@ -1182,7 +1210,7 @@ QS_API int qs_qaoa_run(const qs_qaoa_desc *d, const double *angles_dev, int B, d
         if (int rc = check_desc(d)) return rc;
         if (!angles_dev || !E_dev || !ws || B < 0) return fail(QS_ERR_ARG, "null angles, energies or workspace");
         QPlan plan;
-        build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_shape(d->n), plan);
+        if (int rc = build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_shape(d->n), plan)) return rc;
         const size_t circ = qaoa_layout(plan.geo, grad_dev != nullptr).bytes;
         if (ws_bytes < circ) return fail(QS_ERR_SIZE, "QAOA workspace too small");
         // As many angle sets per launch as the workspace holds.

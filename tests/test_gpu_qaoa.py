@@ -154,3 +154,43 @@ def test_fd_error_vs_step_has_truncation_and_rounding_branches():
     valley = worst[3:5].min()  # h = 1e-5, 1e-6: the oracle's own curve bottoms out near 1e-8 here
     assert valley < 5e-8
     assert worst[-1] > 10 * valley
+
+
+_MERGE_CHILD = r"""
+import json, sys
+import numpy as np
+import torch
+from paper_2001_10554_amd import workloads as W
+from paper_2001_10554_amd.qsim import Qaoa
+out = []
+for n, p in json.loads(sys.argv[1]):
+    edges = W.random_regular_graph(n, 3, seed=n + p)
+    theta = W.qaoa_angles(p, seed=n)
+    E, G = Qaoa(n, edges, p).run(torch.tensor(theta, device="cuda"))
+    out.append([E.item(), G.cpu().numpy()[0].tolist()])
+print(json.dumps(out))
+"""
+
+
+@pytest.mark.parametrize("mode", ["0", "1", "2"])
+def test_merge_policies_match_oracle(mode):
+    """Every layer-boundary policy (never merge, merge every boundary, the
+    default that skips the first group) with two and three qubit groups
+    (10-qubit tiles force three groups at 20 and 22 qubits)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    cases = [(16, 3), (20, 4), (22, 2)]
+    env = dict(os.environ, QSIM_QAOA_MERGE=mode, QSIM_QAOA_TB="10", QSIM_QAOA_R="3")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _MERGE_CHILD, json.dumps(cases)], env=env, cwd=root, capture_output=True, text=True,
+                       timeout=110)
+    assert r.returncode == 0, r.stderr[-2000:]
+    got = json.loads(r.stdout.strip().splitlines()[-1])
+    for (n, p), (e, g) in zip(cases, got):
+        edges = W.random_regular_graph(n, 3, seed=n + p)
+        theta = W.qaoa_angles(p, seed=n)
+        e_ref, g_ref = oracle.qaoa_grad(n, edges, p, theta)
+        assert abs(e - e_ref) < E_TOL, (mode, n, p)
+        assert np.max(np.abs(np.array(g) - g_ref)) < GRAD_TOL, (mode, n, p)

@@ -250,9 +250,11 @@ template <typename R> __device__ __forceinline__ GateVals<R> gate_vals(int kind,
 
 // One gate of a sweep on one group.  base: the pass's fixed bits (for qubits
 // outside the tile).
+// dv: the gate's four diagonal entries in LDS (DIAG2), read with a per-lane
+// index.
 template <typename R>
 __device__ __forceinline__ void regs_apply_gate(cx<R> *v, u32 m0, int g0, int g1, int g2, u64 base, int kind, int p0, int p1, int q0,
-                                                int q1, int s0, int s1, int cval, const GateVals<R> &gv) {
+                                                int q1, int s0, int s1, int cval, const GateVals<R> &gv, const cx<R> *dv) {
     const Mat2<R> &m = gv.m;
     if (kind == QS_G_1Q || (kind == QS_G_C1Q && p0 < 0)) {
         if (kind == QS_G_C1Q && (int)((base >> q0) & 1ull) != cval) return;
@@ -265,14 +267,17 @@ __device__ __forceinline__ void regs_apply_gate(cx<R> *v, u32 m0, int g0, int g1
         else if (s1 == 1) regs_c2x2<R, 1>(v, m, m0, g0, g1, g2, p0, cval);
         else regs_c2x2<R, 2>(v, m, m0, g0, g1, g2, p0, cval);
     } else if (kind == QS_G_DIAG2) {
-        const int c0 = p0 < 0 ? (int)((base >> q0) & 1ull) : 0, c1 = p1 < 0 ? (int)((base >> q1) & 1ull) : 0;
+        // Entry d[2 b1 + b0] comes from LDS with a per-lane index instead of a
+        // select over the four entries.  A qubit outside the tile contributes
+        // the pass's fixed bit, parked on bit 31 / 30 of the index (tile
+        // indices stay below 2^13).
+        const int P0 = p0 < 0 ? 31 : p0, P1 = p1 < 0 ? 30 : p1;
+        const u32 X = (p0 < 0 ? (u32)((base >> q0) & 1ull) << 31 : 0u) | (p1 < 0 ? (u32)((base >> q1) & 1ull) << 30 : 0u);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const u32 idx = m0 | grp_off(j, g0, g1, g2);
-            const int b0 = p0 < 0 ? c0 : (int)((idx >> p0) & 1u), b1 = p1 < 0 ? c1 : (int)((idx >> p1) & 1u);
-            const int e = 2 * b1 + b0;
-            const cx<R> f = e == 0 ? gv.d[0] : e == 1 ? gv.d[1] : e == 2 ? gv.d[2] : gv.d[3];
-            v[j] = cmul<R>(v[j], f);
+            const u32 idx = m0 | grp_off(j, g0, g1, g2) | X;
+            const u32 e = ((idx >> P0) & 1u) | (((idx >> P1) & 1u) << 1);
+            v[j] = cmul<R>(v[j], dv[e]);
         }
     } else if (kind == QS_G_SWAP) {
         const int a = s0 < s1 ? s0 : s1, b = s0 < s1 ? s1 : s0;
@@ -369,8 +374,7 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
             cx<R> val[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) val[e] = reinterpret_cast<const cx<R> *>(x.val)[e];
-            const int kind = sbyte(h.x, 0);
-            if (!kind) continue;
+            const int kind = sbyte(h.x, 0);  // 0 (a skipped gate) matches no branch below
             GateVals<R> gv;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -382,7 +386,7 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
             for (int k = 0; k < GMAX; ++k)
                 if (threadIdx.x + (u32)k * NT < groups)
                     regs_apply_gate<R>(v[k], m0[k], g0, g1, g2, base, kind, sbyte(h.x, 1), sbyte(h.x, 2), sbyte(h.x, 3), sbyte(h.y, 0),
-                                       sbyte(h.y, 1), sbyte(h.y, 2), sbyte(h.y, 3), gv);
+                                       sbyte(h.y, 1), sbyte(h.y, 2), sbyte(h.y, 3), gv, reinterpret_cast<const cx<R> *>(x.val));
         }
 #pragma unroll
         for (int k = 0; k < GMAX; ++k) {

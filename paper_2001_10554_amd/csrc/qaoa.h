@@ -36,9 +36,9 @@ struct QPass {
     int tb, nrest, layer, flags, pidx;
     uint32_t rx_mask;  // tile bits that receive RX
     int use_l1;        // some RX bit is only reachable in the second layout
-    uint8_t T[16];
-    uint8_t rest[40];
-    uint16_t cnt[2][EC_N];
+    alignas(4) uint8_t T[16];     // read as 32-bit words on the device
+    alignas(4) uint8_t rest[40];
+    int32_t cnt[2][EC_N];  // 32-bit: read with scalar loads at a run-time layout index
     QEdge e[2][kQMaxEdges];
 };
 

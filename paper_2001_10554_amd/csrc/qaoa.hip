@@ -65,16 +65,19 @@ __device__ __forceinline__ void cut_values(const QPass &P, int list, const QWeig
     CT coef[JB > 0 ? JB : 1] = {};
     int k = 0;
     const QEdge *E = P.e[list];
-    const uint16_t *cnt = P.cnt[list];
+    const int32_t *cnt = P.cnt[list];
     auto wt = [&](const QEdge &e) -> CT { return weighted ? (CT)W.w[e.wi] : (CT)1; };
+#pragma unroll 4
     for (int i = 0; i < cnt[EC_TT]; ++i, ++k) {
         const QEdge e = E[k];
         cb += (((tid >> e.a) ^ (tid >> e.b)) & 1) ? wt(e) : (CT)0;
     }
+#pragma unroll 4
     for (int i = 0; i < cnt[EC_TR]; ++i, ++k) {
         const QEdge e = E[k];
         cb += (((tid >> e.a) & 1) != (int)((base >> e.b) & 1)) ? wt(e) : (CT)0;
     }
+#pragma unroll 4
     for (int i = 0; i < cnt[EC_TJ]; ++i, ++k) {
         const QEdge e = E[k];
         const int ta = (tid >> e.a) & 1;
@@ -86,6 +89,7 @@ __device__ __forceinline__ void cut_values(const QPass &P, int list, const QWeig
     }
     const int kjj = k;
     k += cnt[EC_JJ];
+#pragma unroll 4
     for (int i = 0; i < cnt[EC_JR]; ++i, ++k) {
         const QEdge e = E[k];
         const int br = (int)((base >> e.b) & 1);
@@ -95,6 +99,7 @@ __device__ __forceinline__ void cut_values(const QPass &P, int list, const QWeig
         for (int x = 0; x < JB; ++x)
             if (x == e.a) coef[x] += br ? -w : w;
     }
+#pragma unroll 4
     for (int i = 0; i < cnt[EC_RR]; ++i, ++k) {
         const QEdge e = E[k];
         cb += (((base >> e.a) ^ (base >> e.b)) & 1) ? wt(e) : (CT)0;
@@ -107,6 +112,7 @@ __device__ __forceinline__ void cut_values(const QPass &P, int list, const QWeig
             if ((j >> x) & 1) c += coef[x];
         C[j] = c;
     }
+#pragma unroll 4
     for (int i = 0; i < cnt[EC_JJ]; ++i) {
         const QEdge e = E[kjj + i];
         const CT w = wt(e);
@@ -116,6 +122,14 @@ __device__ __forceinline__ void cut_values(const QPass &P, int list, const QWeig
     }
 }
 
+// Entry i of a byte array of the pass descriptor, read through its aligned
+// 32-bit word: gfx950 has no scalar byte load, so a byte read from a
+// descriptor in global memory (pooled launches) would be a vector load per
+// entry; the word is a scalar load.
+__device__ __forceinline__ int pbyte(const uint8_t *arr, int i) {
+    return (int)((reinterpret_cast<const uint32_t *>(arr)[i >> 2] >> (8 * (i & 3))) & 255u);
+}
+
 // Bit deposits through the pass's qubit maps, over the arrays' full static
 // length: each entry is read at a fixed kernel-argument offset (hoisted scalar
 // loads) instead of one dependent memory access per bit.
@@ -123,7 +137,7 @@ __device__ __forceinline__ u64 qtile_base(const QPass &P, u64 tile) {
     u64 base = 0;
 #pragma unroll
     for (int b = 0; b < 40; ++b)
-        if (b < P.nrest) base |= ((tile >> b) & 1ull) << P.rest[b];
+        if (b < P.nrest) base |= ((tile >> b) & 1ull) << pbyte(P.rest, b);
     return base;
 }
 
@@ -131,7 +145,7 @@ __device__ __forceinline__ u64 qtile_off(const QPass &P, u64 m) {
     u64 off = 0;
 #pragma unroll
     for (int b = 0; b < 16; ++b)
-        if (b < P.tb) off |= ((m >> b) & 1ull) << P.T[b];
+        if (b < P.tb) off |= ((m >> b) & 1ull) << pbyte(P.T, b);
     return off;
 }
 
@@ -413,25 +427,23 @@ template <int TB, int TT> struct RT {
 template <int TB, int TT, int L>
 __device__ __forceinline__ void rt_offsets(const QPass &P, int t, u64 (&off)[1 << (TB - TT)]) {
     using G = RT<TB, TT>;
+    // Branch-free in t, so the map entries are uniform scalar loads.
     u64 ot = 0;
     if (L == 0) {
 #pragma unroll
-        for (int b = 0; b < TT; ++b)
-            if ((t >> b) & 1) ot |= 1ull << P.T[b];
+        for (int b = 0; b < TT; ++b) ot |= (u64)((t >> b) & 1) << pbyte(P.T, b);
     } else {
 #pragma unroll
-        for (int b = 0; b < 6; ++b)
-            if ((t >> b) & 1) ot |= 1ull << P.T[b];
+        for (int b = 0; b < 6; ++b) ot |= (u64)((t >> b) & 1) << pbyte(P.T, b);
 #pragma unroll
-        for (int w = 0; w < G::W; ++w)
-            if ((t >> (6 + w)) & 1) ot |= 1ull << P.T[TT + w];
+        for (int w = 0; w < G::W; ++w) ot |= (u64)((t >> (6 + w)) & 1) << pbyte(P.T, TT + w);
     }
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
         u64 o = ot;
 #pragma unroll
         for (int x = 0; x < G::JB; ++x)
-            if ((j >> x) & 1) o |= 1ull << P.T[G::reg_bit(L, x)];
+            if ((j >> x) & 1) o |= 1ull << pbyte(P.T, G::reg_bit(L, x));
         off[j] = o;
     }
 }
@@ -1034,7 +1046,7 @@ int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double 
                 }
                 int k = 0;
                 for (int c = 0; c < EC_N; ++c) {
-                    Q.cnt[L][c] = (uint16_t)cls[c].size();
+                    Q.cnt[L][c] = (int32_t)cls[c].size();
                     for (auto &x : cls[c]) Q.e[L][k++] = x;
                 }
             }

@@ -48,9 +48,12 @@ def test_energy_and_gradient_vs_oracle(n, p):
     assert abs(E2.item() - e_ref) < E_TOL
 
 
-def test_weighted_graph():
+@pytest.mark.parametrize("n", [10, 16, 20])
+def test_weighted_graph(n):
+    """Real edge weights (per-amplitude phases): one qubit group at 10 qubits,
+    two groups with merged layer boundaries at 16 and 20."""
     import torch
-    n, p = 10, 2
+    p = 2
     edges = W.random_regular_graph(n, 3, seed=5)
     w = np.linspace(0.25, 2.0, len(edges))
     theta = W.qaoa_angles(p, seed=6)

@@ -469,14 +469,19 @@ __global__ __launch_bounds__(kBlock) void k_cut_phase_chunk(cx<R> *__restrict__ 
     int ct, coef[kCutLoopBits];
     cut_split<int, false>(g, nullptr, t, base, c, ct, coef, tab, kBlock);
     __syncthreads();
-    for (u32 j = 0; j < (1u << (c - 8)); ++j) {
-        const u64 i = base + ((u64)j << 8) + t;
-        const double2 f = ph[cut_at<int>(ct, coef, tab, j)];
-        const cx<R> a = psi[i];
-        cx<R> r;
-        r.x = (R)(a.x * f.x - a.y * f.y);
-        r.y = (R)(a.x * f.y + a.y * f.x);
-        psi[i] = r;
+    // Four loop steps per iteration (c >= 12: at least 16 steps), loads first.
+    for (u32 j = 0; j < (1u << (c - 8)); j += 4) {
+        cx<R> a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = psi[base + ((u64)(j + u) << 8) + t];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double2 f = ph[cut_at<int>(ct, coef, tab, j + u)];
+            cx<R> r;
+            r.x = (R)(a[u].x * f.x - a[u].y * f.y);
+            r.y = (R)(a[u].x * f.y + a[u].y * f.x);
+            psi[base + ((u64)(j + u) << 8) + t] = r;
+        }
     }
 }
 

@@ -230,7 +230,15 @@ __global__ __launch_bounds__(kBlock) void k_cut_expect(const cx<R> *__restrict__
     cut_split<double, W>(g, w.w, t, base, c, ct, coef, tab, kBlock);
     __syncthreads();
     double acc = 0.0;
-    for (u32 j = 0; j < (1u << (c - 8)); ++j) acc += cut_at<double>(ct, coef, tab, j) * norm2d<R>(psi[base + ((u64)j << 8) + t]);
+    // Four loop steps per iteration (c >= 12: at least 16 steps), loads first,
+    // so each thread keeps four reads in flight.
+    for (u32 j = 0; j < (1u << (c - 8)); j += 4) {
+        cx<R> a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = psi[base + ((u64)(j + u) << 8) + t];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += cut_at<double>(ct, coef, tab, j + u) * norm2d<R>(a[u]);
+    }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
     if ((t & 63) == 0) red[t >> 6] = acc;

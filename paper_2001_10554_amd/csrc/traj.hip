@@ -40,20 +40,24 @@ struct TGate {  // gate list on the device (kind, q0, q1, u)
 };
 
 // frames[t * count + g] = (a | b << 32) before gate g; final[t] after all gates;
-// nins[t] = number of insertions (0 for the noiseless run t = n_traj).
-// force_all: every noisy trajectory is simulated on its own (noise gates make
-// each trajectory's state differ even without insertions); nins_ws > 0 marks
-// a trajectory simulated on its own.
+// counts[t] = number of insertions.  first[t] = the first gate that sees a
+// non-identity frame (count if none): the trajectory equals the noiseless run
+// before that gate.  nins_ws[t] > 0 marks a trajectory simulated on its own:
+// one with a gate after its first insertion (insertions after the last gate
+// only change the frame the read-outs undo), or every noisy trajectory with
+// force_all (noise gates make each trajectory's state differ even without
+// insertions; first[t] = 0 then).
 __global__ void k_traj_frames(const TGate *__restrict__ gates, int count, int n_traj, u32 thr, u32 k0, u32 k1, uint64_t *__restrict__ frames,
-                              uint64_t *__restrict__ final_frame, int32_t *__restrict__ nins_ws, int32_t *__restrict__ counts,
-                              uint32_t *__restrict__ log, int log_cap, int force_all) {
+                              uint64_t *__restrict__ final_frame, int32_t *__restrict__ nins_ws, int32_t *__restrict__ first,
+                              int32_t *__restrict__ counts, uint32_t *__restrict__ log, int log_cap, int force_all) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t > n_traj) return;
     u32 a = 0, b = 0, slot = 0;
-    int nins = 0;
+    int nins = 0, g1 = count;
     const bool ideal = t == n_traj;  // the extra noiseless trajectory
     for (int g = 0; g < count; ++g) {
         frames[(u64)t * count + g] = (u64)a | ((u64)b << 32);
+        if ((a | b) && g1 == count) g1 = g;
         const TGate G = gates[g];
         if (G.kind == QS_G_SWAP) {
             const u32 x = 1u << G.q0, y = 1u << G.q1;
@@ -75,7 +79,9 @@ __global__ void k_traj_frames(const TGate *__restrict__ gates, int count, int n_
         }
     }
     final_frame[t] = (u64)a | ((u64)b << 32);
-    nins_ws[t] = nins + (force_all && !ideal ? 1 : 0);
+    const bool own = force_all ? !ideal : g1 < count;
+    nins_ws[t] = own ? nins + 1 : 0;
+    first[t] = force_all ? 0 : g1;
     if (counts && !ideal) counts[t] = nins;
 }
 
@@ -141,22 +147,33 @@ __global__ void k_traj_noise_mats(const DGate *__restrict__ gates, int count, in
 // One pass of every simulated trajectory: block = (trajectory, tile).  Gates
 // act on the stored state as F^dagger G F for the trajectory's frame F before
 // the gate; sweeps of gates run in registers (see DGate).
+// Noiseless run: reads ideal_in (the previous pass's output) and writes
+// ideal_out (two buffers used in turn, the last pass writing its own state
+// slot), so that a trajectory whose first non-identity frame falls in this
+// pass can start from ideal_in while the noiseless run updates its state.
+// Trajectories whose first such gate lies beyond this pass skip it (their
+// state still equals the noiseless one).  first_pass: the input is |basis>.
 template <typename R, int TBMAX>
 __global__ __launch_bounds__(kTileThreads) void k_traj_pass(cx<R> *__restrict__ states, u64 N, int tiles_log2, DPass P, const DGate *__restrict__ gates,
                                                       const uint64_t *__restrict__ frames, int count, int first_pass, u64 basis,
-                                                      const int32_t *__restrict__ nins, int n_traj, const double *__restrict__ nm, int nnoise) {
+                                                      const int32_t *__restrict__ nins, const int32_t *__restrict__ first, int n_traj,
+                                                      const double *__restrict__ nm, int nnoise, const cx<R> *ideal_in, cx<R> *ideal_out) {
     __shared__ cx<R> sh[1 << TBMAX];
     __shared__ SGate<R> sg[kStage];
     const u64 tile = blockIdx.x & ((1ull << tiles_log2) - 1);
     const u64 t = blockIdx.x >> tiles_log2;
     if (!traj_simulated(nins, t, n_traj)) return;  // whole block: shares the noiseless state
+    const bool ideal = t == (u64)n_traj;
+    const int g1 = ideal ? 0 : first[t];
+    if (!ideal && g1 >= P.gate_begin + P.gate_count) return;  // still the noiseless state after this pass
+    const bool from_ideal = ideal || g1 >= P.gate_begin;       // first pass that differs: start from the noiseless run
     constexpr int NT = kTileThreads, PER = (1 << TBMAX) / NT;
-    cx<R> *psi = states + t * N;
+    cx<R> *psi = ideal ? ideal_out : states + t * N;
+    const cx<R> *src = from_ideal ? ideal_in : psi;
     const u64 TS = 1ull << P.tb;
     const u64 base = pass_base(P, tile);
-    tile_load<R, NT, PER, true>(sh, psi, P, base, first_pass != 0, basis);
+    tile_load<R, NT, PER, true>(sh, src, P, base, from_ideal && first_pass != 0, basis);
     __syncthreads();
-    const bool ideal = t == (u64)n_traj;
     auto prep = [&](int gidx, const DGate &g, GateVals<R> &gv, int &cval, int &kind) -> bool {
         const u64 f = frames[t * count + gidx];
         const u32 a = (u32)f, b = (u32)(f >> 32);
@@ -359,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restri
 // ------------------------------------------------------------------ host side
 
 struct TrajLayout {
-    size_t states, frames, final_frame, nins, pzf, px, gates, dgates, nm, total;
+    size_t states, ideal2, frames, final_frame, nins, first, pzf, px, gates, dgates, nm, total;
     int chunk_log2, chunks_log2;
 };
 
@@ -379,11 +396,15 @@ static TrajLayout traj_layout(int n, int dtype, int count, int n_traj, int nnois
     size_t off = 0;
     L.states = off;
     off = align(off + (size_t)(n_traj + 1) * N * amp_bytes(dtype));
+    L.ideal2 = off;  // the noiseless run's second state buffer
+    off = align(off + (size_t)N * amp_bytes(dtype));
     L.frames = off;
     off = align(off + (size_t)(n_traj + 1) * count * sizeof(uint64_t));
     L.final_frame = off;
     off = align(off + (size_t)(n_traj + 1) * sizeof(uint64_t));
     L.nins = off;
+    off = align(off + (size_t)(n_traj + 1) * sizeof(int32_t));
+    L.first = off;
     off = align(off + (size_t)(n_traj + 1) * sizeof(int32_t));
     L.pzf = off;
     off = align(off + (size_t)(n_traj + 1) * ((size_t)1 << L.chunks_log2) * (n + 3) * sizeof(double));
@@ -416,12 +437,12 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     if (p >= 1.0) thr = 0xFFFFFFFFu;
     else if (p > 0.0) thr = (u32)floor(p * 4294967296.0);
     uint64_t *frames = (uint64_t *)(ws + L.frames), *final_frame = (uint64_t *)(ws + L.final_frame);
-    int32_t *nins = (int32_t *)(ws + L.nins);
+    int32_t *nins = (int32_t *)(ws + L.nins), *first_gate = (int32_t *)(ws + L.first);
     bool noisy_gates = false;
     for (int k = 0; k < count; ++k)
         if (gates[k].kind == QS_G_NOISE && gates[k].u[0] > 0.0 && (inv_T1 > 0.0 || inv_T2 > 0.0)) noisy_gates = true;
     hipLaunchKernelGGL(k_traj_frames, dim3((n_traj + 1 + 63) / 64), dim3(64), 0, st, (const TGate *)(ws + L.gates), count, n_traj, thr,
-                       (u32)seed, (u32)(seed >> 32), frames, final_frame, nins, out->counts, out->log, out->log ? out->log_cap : 0,
+                       (u32)seed, (u32)(seed >> 32), frames, final_frame, nins, first_gate, out->counts, out->log, out->log ? out->log_cap : 0,
                        noisy_gates ? 1 : 0);
     QS_LAUNCH_CHECK("traj_frames");
     double *nm = (double *)(ws + L.nm);
@@ -433,14 +454,20 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     }
     cx<R> *states = (cx<R> *)(ws + L.states);
     const int T1 = n_traj + 1;
-    bool first = true;
-    for (const DPass &P : passes) {
+    // The noiseless run alternates between its state slot and ideal2 so that
+    // its last pass writes the slot the read-outs use.
+    cx<R> *ibuf[2] = {states + (u64)n_traj * N, (cx<R> *)(ws + L.ideal2)};
+    const int np = (int)passes.size();
+    for (int k = 0; k < np; ++k) {
+        const DPass &P = passes[k];
         const int tiles_log2 = P.nrest;
         const u64 blocks = (u64)T1 << tiles_log2;
+        const cx<R> *in = k == 0 ? nullptr : ibuf[(np - k) & 1];
+        cx<R> *outb = ibuf[(np - 1 - k) & 1];
         hipLaunchKernelGGL((k_traj_pass<R, TBMAX>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, states, N, tiles_log2, P, (const DGate *)(ws + L.dgates),
-                           (const uint64_t *)frames, count, first ? 1 : 0, basis, (const int32_t *)nins, n_traj, (const double *)nm, nnoise);
+                           (const uint64_t *)frames, count, k == 0 ? 1 : 0, basis, (const int32_t *)nins, (const int32_t *)first_gate, n_traj,
+                           (const double *)nm, nnoise, in, outb);
         QS_LAUNCH_CHECK("traj_pass");
-        first = false;
     }
     double *pzf = (double *)(ws + L.pzf), *px = (double *)(ws + L.px);
     const int chunks = 1 << L.chunks_log2;

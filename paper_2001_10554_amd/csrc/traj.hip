@@ -359,15 +359,67 @@ __global__ void k_traj_final(const double *__restrict__ pzf, const double *__res
 
 // p_mean(k) = (1/T) sum_t |psi_t(k xor a_t)|^2, trajectories summed in order
 // (a noiseless trajectory reads the noiseless run's state).
+// Trajectories whose probabilities are not those of the noiseless run (their
+// own state, or the noiseless state under a frame with X bits): list[0..m),
+// in index order; cnt[0] = m, cnt[1] = number of the others.  One block.
+__global__ __launch_bounds__(1024) void k_traj_pm_list(int n_traj, const uint64_t *__restrict__ final_frame, const int32_t *__restrict__ nins,
+                                                       int32_t *__restrict__ list, int32_t *__restrict__ cnt) {
+    __shared__ int32_t wsum[16];
+    __shared__ int32_t base;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    for (int t0 = 0; t0 < n_traj; t0 += 1024) {
+        const int t = t0 + (int)threadIdx.x;
+        const int in = t < n_traj && (traj_rep(nins, (u64)t, n_traj) != (u64)n_traj || (u32)final_frame[t] != 0u) ? 1 : 0;
+        // exclusive prefix sum over the block: within the wave, then over waves
+        const u64 ball = __ballot(in);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int before = __popcll(ball & ((1ull << lane) - 1));
+        if (lane == 0) wsum[wv] = __popcll(ball);
+        __syncthreads();
+        int off = base;
+        for (int k = 0; k < wv; ++k) off += wsum[k];
+        if (in) list[off + before] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int k = 0; k < 16; ++k) tot += wsum[k];
+            base += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cnt[0] = base;
+        cnt[1] = n_traj - base;
+    }
+}
+
+// Mean over trajectories of p_t(k) = |psi_rep(t)(k xor a_t)|^2: the
+// trajectories that share the noiseless probabilities enter as one weighted
+// term, the listed ones one by one (four loads in flight per thread).
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restrict__ states, u64 N, int n_traj, const uint64_t *__restrict__ final_frame,
-                                                           const int32_t *__restrict__ nins, double *__restrict__ out) {
+                                                           const int32_t *__restrict__ nins, const int32_t *__restrict__ list,
+                                                           const int32_t *__restrict__ cnt, double *__restrict__ out) {
     const u64 k = (u64)blockIdx.x * kBlock + threadIdx.x;
     if (k >= N) return;
-    double s = 0.0;
-    for (int t = 0; t < n_traj; ++t) {
-        const u32 a = (u32)final_frame[t];
-        const cx<R> v = states[traj_rep(nins, t, n_traj) * N + (k ^ a)];
+    const int m = cnt[0];
+    const cx<R> v0 = states[(u64)n_traj * N + k];
+    double s = (double)cnt[1] * ((double)v0.x * v0.x + (double)v0.y * v0.y);
+    int i = 0;
+    for (; i + 4 <= m; i += 4) {
+        cx<R> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = list[i + u];
+            v[u] = states[traj_rep(nins, (u64)t, n_traj) * N + (k ^ (u32)final_frame[t])];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += (double)v[u].x * v[u].x + (double)v[u].y * v[u].y;
+    }
+    for (; i < m; ++i) {
+        const int t = list[i];
+        const cx<R> v = states[traj_rep(nins, (u64)t, n_traj) * N + (k ^ (u32)final_frame[t])];
         s += (double)v.x * v.x + (double)v.y * v.y;
     }
     out[k] = s / (double)n_traj;
@@ -376,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restri
 // ------------------------------------------------------------------ host side
 
 struct TrajLayout {
-    size_t states, ideal2, frames, final_frame, nins, first, pzf, px, gates, dgates, nm, total;
+    size_t states, ideal2, frames, final_frame, nins, first, pmlist, pzf, px, gates, dgates, nm, total;
     int chunk_log2, chunks_log2;
 };
 
@@ -406,6 +458,8 @@ static TrajLayout traj_layout(int n, int dtype, int count, int n_traj, int nnois
     off = align(off + (size_t)(n_traj + 1) * sizeof(int32_t));
     L.first = off;
     off = align(off + (size_t)(n_traj + 1) * sizeof(int32_t));
+    L.pmlist = off;  // probability-mean list (n_traj entries) and its two counts
+    off = align(off + (size_t)(n_traj + 2) * sizeof(int32_t));
     L.pzf = off;
     off = align(off + (size_t)(n_traj + 1) * ((size_t)1 << L.chunks_log2) * (n + 3) * sizeof(double));
     L.px = off;
@@ -491,8 +545,11 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
         QS_LAUNCH_CHECK("traj_final");
     }
     if (out->prob_mean) {
+        int32_t *pml = (int32_t *)(ws + L.pmlist), *pmc = pml + n_traj;
+        hipLaunchKernelGGL(k_traj_pm_list, dim3(1), dim3(1024), 0, st, n_traj, (const uint64_t *)final_frame, (const int32_t *)nins, pml, pmc);
+        QS_LAUNCH_CHECK("traj_prob_mean");
         hipLaunchKernelGGL(k_traj_prob_mean<R>, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, (const cx<R> *)states, N, n_traj,
-                           (const uint64_t *)final_frame, (const int32_t *)nins, out->prob_mean);
+                           (const uint64_t *)final_frame, (const int32_t *)nins, (const int32_t *)pml, (const int32_t *)pmc, out->prob_mean);
         QS_LAUNCH_CHECK("traj_prob_mean");
     }
     return QS_OK;

@@ -339,8 +339,9 @@ typedef struct qs_traj_out {
     double *diag_val;   /* device [n_traj]: per-trajectory sum_k d_k |a_k|^2 (needs diag), or NULL */
 } qs_traj_out;
 
-/* Device workspace for qs_traj_run: n_traj + 1 states (the extra one is the
- * noiseless reference for the fidelity) plus per-gate Pauli frames. */
+/* Device workspace for qs_traj_run: n_traj + 2 states (the noiseless reference
+ * for the fidelity keeps two, so that trajectories can start from its state
+ * after the pass before their first insertion) plus per-gate Pauli frames. */
 int qs_traj_workspace_bytes(int n, int dtype, int count, int n_traj, size_t *bytes);
 
 /* gates: host list (1Q, C1Q, DIAG2, SWAP), 1 <= count <= 4096; 1 <= n <= 20;

@@ -38,6 +38,8 @@ struct TGate {  // gate list on the device (kind, q0, q1, u)
     int32_t kind, q0, q1, pad;
     double u[8];
 };
+static_assert(sizeof(TGate) == sizeof(qs_gate), "TGate mirrors qs_gate");
+static_assert(kTrajMaxGates % 8 == 0, "the frames kernel reads gate records in groups of eight");
 
 // frames[t * count + g] = (a | b << 32) before gate g; final[t] after all gates;
 // counts[t] = number of insertions.  first[t] = the first gate that sees a
@@ -47,34 +49,77 @@ struct TGate {  // gate list on the device (kind, q0, q1, u)
 // only change the frame the read-outs undo), or every noisy trajectory with
 // force_all (noise gates make each trajectory's state differ even without
 // insertions; first[t] = 0 then).
-__global__ void k_traj_frames(const TGate *__restrict__ gates, int count, int n_traj, u32 thr, u32 k0, u32 k1, uint64_t *__restrict__ frames,
-                              uint64_t *__restrict__ final_frame, int32_t *__restrict__ nins_ws, int32_t *__restrict__ first,
-                              int32_t *__restrict__ counts, uint32_t *__restrict__ log, int log_cap, int force_all) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t > n_traj) return;
-    u32 a = 0, b = 0, slot = 0;
-    int nins = 0, g1 = count;
-    const bool ideal = t == n_traj;  // the extra noiseless trajectory
-    for (int g = 0; g < count; ++g) {
-        frames[(u64)t * count + g] = (u64)a | ((u64)b << 32);
-        if ((a | b) && g1 == count) g1 = g;
-        const TGate G = gates[g];
-        if (G.kind == QS_G_SWAP) {
-            const u32 x = 1u << G.q0, y = 1u << G.q1;
-            if (((a & x) != 0) != ((a & y) != 0)) a ^= x | y;
-            if (((b & x) != 0) != ((b & y) != 0)) b ^= x | y;
+//
+// One wavefront per trajectory (t = n_traj is the extra noiseless one): its
+// lanes make the draws of all gates at once and keep one decision byte per
+// gate in LDS (bits 0-1: the Pauli drawn for q0, 2-3: for q1, 0 = none;
+// gates[g].pad holds the gate's first slot); lane 0 then replays the gates in
+// order, eight records at a time, which fixes the frames, the insertion log
+// and the first affected gate.
+constexpr int kFrameWaves = 4;
+__global__ __launch_bounds__(64 * kFrameWaves) void k_traj_frames(const TGate *__restrict__ gates, int count, int n_traj, u32 thr, u32 k0,
+                                                                   u32 k1, uint64_t *__restrict__ frames, uint64_t *__restrict__ final_frame,
+                                                                   int32_t *__restrict__ nins_ws, int32_t *__restrict__ first,
+                                                                   int32_t *__restrict__ counts, uint32_t *__restrict__ log, int log_cap,
+                                                                   int force_all) {
+    __shared__ uint32_t hdr[kTrajMaxGates];  // kind | q0 << 8 | q1 << 16
+    __shared__ uint8_t dec[kFrameWaves][kTrajMaxGates];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int t = blockIdx.x * kFrameWaves + w;
+    const bool ideal = t == n_traj;
+    for (int g = threadIdx.x; g < count; g += blockDim.x)
+        hdr[g] = ((u32)gates[g].kind & 0xffu) | ((u32)gates[g].q0 & 0xffu) << 8 | ((u32)gates[g].q1 & 0xffu) << 16;
+    if (t <= n_traj)
+        for (int g = lane; g < count; g += 64) {
+            const int kind = gates[g].kind;
+            const int nt = kind == QS_G_NOISE ? 0 : kind == QS_G_1Q ? 1 : 2;
+            const u32 s0 = (u32)gates[g].pad;
+            u32 d = 0;
+            for (int k = 0; k < nt && !ideal; ++k) {
+                const Philox4 r = philox4x32_10((u32)t, s0 + (u32)k, kTagTraj, 0u, k0, k1);
+                if (r.v[0] < thr) d |= (1u + (u32)(((u64)r.v[1] * 3u) >> 32)) << (2 * k);
+            }
+            dec[w][g] = (uint8_t)d;
         }
-        const int nt = G.kind == QS_G_NOISE ? 0 : G.kind == QS_G_1Q ? 1 : 2;
-        for (int k = 0; k < nt; ++k, ++slot) {
-            if (ideal) continue;
-            const Philox4 r = philox4x32_10((u32)t, slot, kTagTraj, 0u, k0, k1);
-            if (r.v[0] < thr) {
-                const int pauli = 1 + (int)(((u64)r.v[1] * 3u) >> 32);
-                const u32 m = 1u << (k == 0 ? G.q0 : G.q1);
-                if (pauli == 1 || pauli == 2) a ^= m;
-                if (pauli == 2 || pauli == 3) b ^= m;
-                if (log && nins < log_cap) log[(u64)t * log_cap + nins] = (slot << 2) | (u32)pauli;
-                ++nins;
+    __syncthreads();
+    if (t > n_traj || lane != 0) return;
+    const uint8_t *D = dec[w];
+    uint64_t *fr = frames + (u64)t * count;
+    u32 a = 0, b = 0;
+    int nins = 0, g1 = count;
+    constexpr int kU = 8;  // kTrajMaxGates is a multiple: the records read past count stay inside the arrays
+    for (int g0 = 0; g0 < count; g0 += kU) {
+        u32 H[kU], Dg[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            H[j] = hdr[g0 + j];
+            Dg[j] = D[g0 + j];
+        }
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            const int g = g0 + j;
+            if (g >= count) break;
+            fr[g] = (u64)a | ((u64)b << 32);
+            if ((a | b) && g1 == count) g1 = g;
+            const u32 q0 = (H[j] >> 8) & 0xffu, q1 = H[j] >> 16;
+            const u32 x = 1u << q0, y = 1u << (q1 & 31u);
+            if ((H[j] & 0xffu) == (u32)QS_G_SWAP) {
+                if (((a & x) != 0) != ((a & y) != 0)) a ^= x | y;
+                if (((b & x) != 0) != ((b & y) != 0)) b ^= x | y;
+            }
+            const u32 d0 = Dg[j] & 3u, d1 = Dg[j] >> 2;
+            a ^= (d0 == 1u || d0 == 2u ? x : 0u) ^ (d1 == 1u || d1 == 2u ? y : 0u);
+            b ^= (d0 == 2u || d0 == 3u ? x : 0u) ^ (d1 == 2u || d1 == 3u ? y : 0u);
+            if (Dg[j]) {  // rare: log in slot order
+                const u32 s0 = (u32)gates[g].pad;
+                if (d0) {
+                    if (log && nins < log_cap) log[(u64)t * log_cap + nins] = (s0 << 2) | d0;
+                    ++nins;
+                }
+                if (d1) {
+                    if (log && nins < log_cap) log[(u64)t * log_cap + nins] = ((s0 + 1u) << 2) | d1;
+                    ++nins;
+                }
             }
         }
     }
@@ -484,7 +529,13 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     std::vector<DGate> dg;
     make_plan(n, dtype, gates, count, passes, dg);
     // The planner keeps the list order, so dg[i] is gate i with tile positions per pass.
-    QS_HIP(hipMemcpyAsync(ws + L.gates, gates, (size_t)count * sizeof(TGate), hipMemcpyHostToDevice, st));
+    // The device copy carries each gate's first draw slot in its pad field.
+    std::vector<qs_gate> gl(gates, gates + count);
+    for (int k = 0, slot = 0; k < count; ++k) {
+        gl[k].pad = slot;
+        slot += gates[k].kind == QS_G_NOISE ? 0 : gates[k].kind == QS_G_1Q ? 1 : 2;
+    }
+    QS_HIP(hipMemcpyAsync(ws + L.gates, gl.data(), (size_t)count * sizeof(TGate), hipMemcpyHostToDevice, st));
     QS_HIP(hipMemcpyAsync(ws + L.dgates, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice, st));
     QS_HIP(hipStreamSynchronize(st));  // host arrays are released when this call returns
     u32 thr = 0;
@@ -495,7 +546,8 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     bool noisy_gates = false;
     for (int k = 0; k < count; ++k)
         if (gates[k].kind == QS_G_NOISE && gates[k].u[0] > 0.0 && (inv_T1 > 0.0 || inv_T2 > 0.0)) noisy_gates = true;
-    hipLaunchKernelGGL(k_traj_frames, dim3((n_traj + 1 + 63) / 64), dim3(64), 0, st, (const TGate *)(ws + L.gates), count, n_traj, thr,
+    hipLaunchKernelGGL(k_traj_frames, dim3((n_traj + kFrameWaves) / kFrameWaves), dim3(64 * kFrameWaves), 0, st, (const TGate *)(ws + L.gates),
+                       count, n_traj, thr,
                        (u32)seed, (u32)(seed >> 32), frames, final_frame, nins, first_gate, out->counts, out->log, out->log ? out->log_cap : 0,
                        noisy_gates ? 1 : 0);
     QS_LAUNCH_CHECK("traj_frames");

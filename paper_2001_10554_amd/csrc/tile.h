@@ -48,10 +48,10 @@ inline int tile_bits_max(int dtype) { return dtype == QS_C128 ? 12 : 13; }
 
 // Greedy split of a gate list into passes: a pass takes the longest prefix of
 // the remaining gates whose targets (1Q target, C1Q target, both SWAP qubits)
-// fit in a tile of tile_bits_max(dtype) qubits that also holds the lowest
-// qubits; diagonal gates and controls outside the tile ride along.  Each
-// pass of at least 3 tile bits is then cut into sweeps (see DGate).
-void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg);
+// fit in a tile of tile_bits qubits (at most tile_bits_max(dtype)) that also
+// holds the lowest qubits; diagonal gates and controls outside the tile ride
+// along.  Each pass of at least 3 tile bits is then cut into sweeps (see DGate).
+void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg);
 
 // LDS tiles are stored swizzled: amplitude m of a tile sits at slot swz(m),
 // the low 3 bits (the 16-byte slot within a 128-byte row) XORed with bits

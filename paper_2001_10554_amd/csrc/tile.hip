@@ -102,8 +102,8 @@ static void make_sweeps(int tb, DGate *d, int cnt) {
 
 // Split the list into passes (see the file comment) and encode each gate's
 // qubits as tile-bit positions of its pass.
-void make_plan(int n, int dtype, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg) {
-    const int tbmax = std::min(tile_bits_max(dtype), n);
+void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg) {
+    const int tbmax = std::min(std::min(tile_bits, tile_bits_max(dtype)), n);
     const int r = std::min(dtype == QS_C128 ? 3 : 4, tbmax);  // contiguous low qubits: 128-byte rows
     int k = 0, nnoise = 0;
     while (k < count) {
@@ -176,7 +176,7 @@ int run_block(qs_state *s, const qs_gate *gates, int count) {
         if (it == cache->plans.end()) {
             Plan p;
             std::vector<DGate> dg;
-            make_plan(s->n, s->dtype, gates, count, p.passes, dg);
+            make_plan(s->n, s->dtype, tile_bits_max(s->dtype), gates, count, p.passes, dg);
             QS_HIP(hipMalloc(&p.dev_gates, dg.size() * sizeof(DGate)));
             QS_HIP(hipMemcpy(p.dev_gates, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice));
             it = cache->plans.emplace(std::move(key), std::move(p)).first;

@@ -527,7 +527,7 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     const u64 N = 1ull << n;
     std::vector<DPass> passes;
     std::vector<DGate> dg;
-    make_plan(n, dtype, gates, count, passes, dg);
+    make_plan(n, dtype, TBMAX, gates, count, passes, dg);
     // The planner keeps the list order, so dg[i] is gate i with tile positions per pass.
     // The device copy carries each gate's first draw slot in its pad field.
     std::vector<qs_gate> gl(gates, gates + count);
@@ -625,9 +625,12 @@ static int traj_run_any(int n, int dtype, const qs_gate *gates, int count, u64 b
         return fail(QS_ERR_SIZE, "trajectory workspace too small");
     const double inv_T1 = nz.T1 < INFINITY ? 1.0 / nz.T1 : 0.0, inv_T2 = nz.T2 < INFINITY ? 1.0 / nz.T2 : 0.0;
     hipStream_t st = (hipStream_t)stream;
+    // Tiles of 12 qubits for both types (64 KiB of LDS for c128, 32 KiB for
+    // c64): with many small states, c64 gains more from twice the resident
+    // workgroups per CU than from the wider tile a single state uses.
     return dtype == QS_C128
                ? traj_run_t<double, 12>(n, dtype, gates, count, basis_index, n_traj, nz.p_depol, inv_T1, inv_T2, seed, out, (char *)ws, st)
-               : traj_run_t<float, 13>(n, dtype, gates, count, basis_index, n_traj, nz.p_depol, inv_T1, inv_T2, seed, out, (char *)ws, st);
+               : traj_run_t<float, 12>(n, dtype, gates, count, basis_index, n_traj, nz.p_depol, inv_T1, inv_T2, seed, out, (char *)ws, st);
 }
 
 }  // namespace qs

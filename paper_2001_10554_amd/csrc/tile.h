@@ -29,10 +29,12 @@ struct DGate {
     int8_t pad0;
     int16_t run;    // first gate of a sweep: gates in the sweep; 0 for the others
     int16_t nidx;   // noise gates: index among the list's noise gates
+    int32_t gidx;   // index of the gate in the caller's list (passes may reorder commuting gates)
     double u[8];
 };
 
-// One pass: the tile qubit set and the slice of the gate list it applies.
+// One pass: the tile qubit set and its slice [gate_begin, gate_begin +
+// gate_count) of the plan's gates (execution order).
 struct DPass {
     int tb;
     int nrest;
@@ -46,11 +48,18 @@ inline int tile_bits_max(int dtype) { return dtype == QS_C128 ? 12 : 13; }
 
 
 
-// Greedy split of a gate list into passes: a pass takes the longest prefix of
-// the remaining gates whose targets (1Q target, C1Q target, both SWAP qubits)
-// fit in a tile of tile_bits qubits (at most tile_bits_max(dtype)) that also
-// holds the lowest qubits; diagonal gates and controls outside the tile ride
-// along.  Each pass of at least 3 tile bits is then cut into sweeps (see DGate).
+// Greedy split of a gate list into passes.  A pass scans the remaining gates
+// in list order and takes each one whose targets (1Q / noise target, C1Q
+// target, both SWAP qubits) fit in a tile of tile_bits qubits (at most
+// tile_bits_max(dtype)) that also holds the lowest qubits, provided it
+// commutes with every gate it would overtake: those left for later passes.
+// Gates on disjoint qubits commute, and so do two diagonal gates.  (Under a
+// Pauli frame a diagonal gate stays diagonal, so trajectories may reorder the
+// same way, each gate keeping the frame of its list position.)  This split is
+// used when it has fewer passes than the plain one (each pass the longest
+// fitting prefix of the list).  Diagonal gates and controls outside the tile
+// ride along.  Each pass of at least 3 tile bits is then cut into sweeps (see
+// DGate).
 void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg);
 
 // LDS tiles are stored swizzled: amplitude m of a tile sits at slot swz(m),
@@ -318,7 +327,8 @@ constexpr int kStage = 64;
 
 // Sweeps of one pass on the LDS tile `sh` (2^tb amplitudes, fixed bits
 // `base`), block size NT, at most GMAX groups of 8 per thread.
-// prep(gidx, gate, vals, cval, kind) fills a gate's values and may skip it
+// prep(gidx, gate, vals, cval, kind) fills a gate's values (gidx: its list
+// index) and may skip it
 // (return false) or change its kind / control value.
 template <typename R, int NT, int GMAX, typename Prep>
 __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 base, const DGate *__restrict__ gates, int begin, int count,
@@ -332,7 +342,7 @@ __device__ __forceinline__ void run_sweeps(cx<R> *sh, SGate<R> *sg, int tb, u64 
             const DGate &x = gates[begin + at + threadIdx.x];
             GateVals<R> gv;
             int cval = 1, kind = x.kind;
-            if (!prep(begin + at + (int)threadIdx.x, x, gv, cval, kind)) kind = 0;
+            if (!prep(x.gidx, x, gv, cval, kind)) kind = 0;
             SGate<R> o;
             auto byte = [](int v) { return (uint32_t)(uint8_t)(int8_t)v; };
             o.h.x = byte(kind) | byte(x.p0) << 8 | byte(x.p1) << 16 | byte(x.q0) << 24;

@@ -105,19 +105,58 @@ static void make_sweeps(int tb, DGate *d, int cnt) {
 void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg) {
     const int tbmax = std::min(std::min(tile_bits, tile_bits_max(dtype)), n);
     const int r = std::min(dtype == QS_C128 ? 3 : 4, tbmax);  // contiguous low qubits: 128-byte rows
-    int k = 0, nnoise = 0;
-    while (k < count) {
-        u64 T = (1ull << r) - 1;
-        int begin = k;
-        for (; k < count; ++k) {
-            u64 need = 0;
-            const qs_gate &x = g[k];
-            if (x.kind == QS_G_1Q || x.kind == QS_G_NOISE) need = 1ull << x.q0;
-            else if (x.kind == QS_G_C1Q) need = 1ull << x.q1;
-            else if (x.kind == QS_G_SWAP) need = (1ull << x.q0) | (1ull << x.q1);
-            if (__builtin_popcountll(T | need) > tbmax) break;
-            T |= need;
+    std::vector<int16_t> nidx(count);
+    for (int j = 0, c = 0; j < count; ++j) {
+        nidx[j] = (int16_t)c;
+        c += g[j].kind == QS_G_NOISE;
+    }
+    // Gate lists and tile masks of the passes; with commute = false a pass is
+    // the longest prefix of the remaining list that fits.
+    auto split = [&](bool commute, std::vector<std::vector<int>> &lists, std::vector<u64> &tiles) {
+        std::vector<int> rem(count), take, later;
+        for (int j = 0; j < count; ++j) rem[j] = j;
+        while (!rem.empty()) {
+            u64 T = (1ull << r) - 1;
+            u64 left_any = 0, left_nondiag = 0;  // qubits of the gates left for later passes
+            take.clear();
+            later.clear();
+            for (int j : rem) {
+                const qs_gate &x = g[j];
+                const bool one = x.kind == QS_G_1Q || x.kind == QS_G_NOISE, diag = x.kind == QS_G_DIAG2;
+                const u64 touch = (1ull << x.q0) | (one ? 0ull : 1ull << x.q1);
+                u64 need = 0;
+                if (one) need = 1ull << x.q0;
+                else if (x.kind == QS_G_C1Q) need = 1ull << x.q1;
+                else if (x.kind == QS_G_SWAP) need = touch;
+                const bool blocked = commute ? (touch & (diag ? left_nondiag : left_any)) != 0 : !later.empty();
+                if (!blocked && __builtin_popcountll(T | need) <= tbmax) {
+                    T |= need;
+                    take.push_back(j);
+                } else {
+                    later.push_back(j);
+                    left_any |= touch;
+                    if (!diag) left_nondiag |= touch;
+                }
+            }
+            lists.push_back(take);
+            tiles.push_back(T);
+            rem.swap(later);
         }
+    };
+    // Reordering pays only where it saves passes: with as many passes, the
+    // list-order split keeps the early passes short, which trajectories
+    // starting from the noiseless run's state prefer.
+    std::vector<std::vector<int>> lists, lists_c;
+    std::vector<u64> tiles, tiles_c;
+    split(false, lists, tiles);
+    split(true, lists_c, tiles_c);
+    if (lists_c.size() < lists.size()) {
+        lists.swap(lists_c);
+        tiles.swap(tiles_c);
+    }
+    for (size_t pi = 0; pi < lists.size(); ++pi) {
+        const std::vector<int> &take = lists[pi];
+        u64 T = tiles[pi];
         // Fill the tile up to tbmax with the lowest unused qubits.
         for (int q = 0; q < n && __builtin_popcountll(T) < tbmax; ++q) T |= 1ull << q;
         DPass P{};
@@ -140,8 +179,8 @@ void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std
             P.hi[k] = o;
         }
         P.gate_begin = (int)dg.size();
-        P.gate_count = k - begin;
-        for (int j = begin; j < k; ++j) {
+        P.gate_count = (int)take.size();
+        for (int j : take) {
             DGate d{};
             d.kind = g[j].kind;
             d.q0 = (int8_t)g[j].q0;
@@ -151,8 +190,8 @@ void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std
             d.p1 = (int8_t)(one ? -1 : pos[g[j].q1]);
             memcpy(d.u, g[j].u, sizeof(d.u));
             d.s0 = d.s1 = -1;
-            d.nidx = (int16_t)nnoise;
-            if (g[j].kind == QS_G_NOISE) ++nnoise;
+            d.nidx = nidx[j];
+            d.gidx = j;
             dg.push_back(d);
         }
         if (P.tb >= 3) make_sweeps(P.tb, dg.data() + P.gate_begin, P.gate_count);

@@ -40,11 +40,13 @@ struct TGate {  // gate list on the device (kind, q0, q1, u)
 };
 static_assert(sizeof(TGate) == sizeof(qs_gate), "TGate mirrors qs_gate");
 static_assert(kTrajMaxGates % 8 == 0, "the frames kernel reads gate records in groups of eight");
+static_assert(2 * kTrajMaxGates <= 0xffff, "draw slots and execution positions share a 32-bit field");
 
 // frames[t * count + g] = (a | b << 32) before gate g; final[t] after all gates;
-// counts[t] = number of insertions.  first[t] = the first gate that sees a
+// counts[t] = number of insertions.  first[t] = the earliest execution
+// position (index into the plan's gate order) of a gate that sees a
 // non-identity frame (count if none): the trajectory equals the noiseless run
-// before that gate.  nins_ws[t] > 0 marks a trajectory simulated on its own:
+// before that position.  nins_ws[t] > 0 marks a trajectory simulated on its own:
 // one with a gate after its first insertion (insertions after the last gate
 // only change the frame the read-outs undo), or every noisy trajectory with
 // force_all (noise gates make each trajectory's state differ even without
@@ -53,7 +55,8 @@ static_assert(kTrajMaxGates % 8 == 0, "the frames kernel reads gate records in g
 // One wavefront per trajectory (t = n_traj is the extra noiseless one): its
 // lanes make the draws of all gates at once and keep one decision byte per
 // gate in LDS (bits 0-1: the Pauli drawn for q0, 2-3: for q1, 0 = none;
-// gates[g].pad holds the gate's first slot); lane 0 then replays the gates in
+// gates[g].pad holds the gate's first slot in its low 16 bits and its
+// execution position in the high 16); lane 0 then replays the gates in
 // order, eight records at a time, which fixes the frames, the insertion log
 // and the first affected gate.
 constexpr int kFrameWaves = 4;
@@ -63,17 +66,20 @@ __global__ __launch_bounds__(64 * kFrameWaves) void k_traj_frames(const TGate *_
                                                                    int32_t *__restrict__ counts, uint32_t *__restrict__ log, int log_cap,
                                                                    int force_all) {
     __shared__ uint32_t hdr[kTrajMaxGates];  // kind | q0 << 8 | q1 << 16
+    __shared__ uint16_t epos[kTrajMaxGates];
     __shared__ uint8_t dec[kFrameWaves][kTrajMaxGates];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int t = blockIdx.x * kFrameWaves + w;
     const bool ideal = t == n_traj;
-    for (int g = threadIdx.x; g < count; g += blockDim.x)
+    for (int g = threadIdx.x; g < count; g += blockDim.x) {
         hdr[g] = ((u32)gates[g].kind & 0xffu) | ((u32)gates[g].q0 & 0xffu) << 8 | ((u32)gates[g].q1 & 0xffu) << 16;
+        epos[g] = (uint16_t)((u32)gates[g].pad >> 16);
+    }
     if (t <= n_traj)
         for (int g = lane; g < count; g += 64) {
             const int kind = gates[g].kind;
             const int nt = kind == QS_G_NOISE ? 0 : kind == QS_G_1Q ? 1 : 2;
-            const u32 s0 = (u32)gates[g].pad;
+            const u32 s0 = (u32)gates[g].pad & 0xffffu;
             u32 d = 0;
             for (int k = 0; k < nt && !ideal; ++k) {
                 const Philox4 r = philox4x32_10((u32)t, s0 + (u32)k, kTagTraj, 0u, k0, k1);
@@ -86,21 +92,22 @@ __global__ __launch_bounds__(64 * kFrameWaves) void k_traj_frames(const TGate *_
     const uint8_t *D = dec[w];
     uint64_t *fr = frames + (u64)t * count;
     u32 a = 0, b = 0;
-    int nins = 0, g1 = count;
+    int nins = 0, e1 = count;
     constexpr int kU = 8;  // kTrajMaxGates is a multiple: the records read past count stay inside the arrays
     for (int g0 = 0; g0 < count; g0 += kU) {
-        u32 H[kU], Dg[kU];
+        u32 H[kU], Dg[kU], Ep[kU];
 #pragma unroll
         for (int j = 0; j < kU; ++j) {
             H[j] = hdr[g0 + j];
             Dg[j] = D[g0 + j];
+            Ep[j] = epos[g0 + j];
         }
 #pragma unroll
         for (int j = 0; j < kU; ++j) {
             const int g = g0 + j;
             if (g >= count) break;
             fr[g] = (u64)a | ((u64)b << 32);
-            if ((a | b) && g1 == count) g1 = g;
+            if ((a | b) && (int)Ep[j] < e1) e1 = (int)Ep[j];
             const u32 q0 = (H[j] >> 8) & 0xffu, q1 = H[j] >> 16;
             const u32 x = 1u << q0, y = 1u << (q1 & 31u);
             if ((H[j] & 0xffu) == (u32)QS_G_SWAP) {
@@ -111,7 +118,7 @@ __global__ __launch_bounds__(64 * kFrameWaves) void k_traj_frames(const TGate *_
             a ^= (d0 == 1u || d0 == 2u ? x : 0u) ^ (d1 == 1u || d1 == 2u ? y : 0u);
             b ^= (d0 == 2u || d0 == 3u ? x : 0u) ^ (d1 == 2u || d1 == 3u ? y : 0u);
             if (Dg[j]) {  // rare: log in slot order
-                const u32 s0 = (u32)gates[g].pad;
+                const u32 s0 = (u32)gates[g].pad & 0xffffu;
                 if (d0) {
                     if (log && nins < log_cap) log[(u64)t * log_cap + nins] = (s0 << 2) | d0;
                     ++nins;
@@ -124,9 +131,9 @@ __global__ __launch_bounds__(64 * kFrameWaves) void k_traj_frames(const TGate *_
         }
     }
     final_frame[t] = (u64)a | ((u64)b << 32);
-    const bool own = force_all ? !ideal : g1 < count;
+    const bool own = force_all ? !ideal : e1 < count;
     nins_ws[t] = own ? nins + 1 : 0;
-    first[t] = force_all ? 0 : g1;
+    first[t] = force_all ? 0 : e1;
     if (counts && !ideal) counts[t] = nins;
 }
 
@@ -179,11 +186,11 @@ __global__ void k_traj_noise_mats(const DGate *__restrict__ gates, int count, in
                                   double inv_T2, double *__restrict__ nm) {
     const u64 id = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= (u64)n_traj * count) return;
-    const u32 t = (u32)(id / count), gidx = (u32)(id % count);
-    const DGate &g = gates[gidx];
+    const u32 t = (u32)(id / count);
+    const DGate &g = gates[id % count];
     if (g.kind != QS_G_NOISE) return;
     double u[8];
-    noise_matrix(u, g.u[0], inv_T1, inv_T2, t, gidx, k0, k1);
+    noise_matrix(u, g.u[0], inv_T1, inv_T2, t, (u32)g.gidx, k0, k1);
     double *o = nm + ((u64)t * nnoise + g.nidx) * 8;
 #pragma unroll
     for (int k = 0; k < 8; ++k) o[k] = u[k];
@@ -257,11 +264,10 @@ __global__ __launch_bounds__(kTileThreads) void k_traj_pass(cx<R> *__restrict__ 
         run_sweeps<R, NT, ((1 << (TBMAX - 3)) + NT - 1) / NT>(sh, sg, P.tb, base, gates, P.gate_begin, P.gate_count, prep);
     } else {
         for (int gi = 0; gi < P.gate_count; ++gi) {
-            const int gidx = P.gate_begin + gi;
-            const DGate &g = gates[gidx];
+            const DGate &g = gates[P.gate_begin + gi];
             GateVals<R> gv;
             int cval = 1, kind = g.kind;
-            if (!prep(gidx, g, gv, cval, kind)) continue;
+            if (!prep(g.gidx, g, gv, cval, kind)) continue;
             double u[8];
             if (kind == QS_G_DIAG2) {
 #pragma unroll
@@ -528,11 +534,14 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     std::vector<DPass> passes;
     std::vector<DGate> dg;
     make_plan(n, dtype, TBMAX, gates, count, passes, dg);
-    // The planner keeps the list order, so dg[i] is gate i with tile positions per pass.
-    // The device copy carries each gate's first draw slot in its pad field.
+    // dg holds every gate once, in execution order (dg[i].gidx: its list
+    // index); each pass applies a slice of it.
+    // The device copy carries each gate's first draw slot and its execution
+    // position in the plan in its pad field (16 bits each).
     std::vector<qs_gate> gl(gates, gates + count);
+    for (int i = 0; i < count; ++i) gl[dg[i].gidx].pad = i << 16;
     for (int k = 0, slot = 0; k < count; ++k) {
-        gl[k].pad = slot;
+        gl[k].pad |= slot;
         slot += gates[k].kind == QS_G_NOISE ? 0 : gates[k].kind == QS_G_1Q ? 1 : 2;
     }
     QS_HIP(hipMemcpyAsync(ws + L.gates, gl.data(), (size_t)count * sizeof(TGate), hipMemcpyHostToDevice, st));

@@ -246,6 +246,21 @@ def with_noise_gates(gates: np.ndarray, duration: float = 1.0) -> np.ndarray:
     return gates_array(recs)
 
 
+def dressed_qaoa_circuit(n: int, edges, p: int, seed: int) -> np.ndarray:
+    """The QAOA circuit (seeded angles) with a seeded Haar one-qubit gate on
+    both qubits after every two-qubit diagonal: the shape of a noisy QAOA
+    schedule with fixed gates in place of the noise, whose passes shrink
+    when gates that commute are moved ahead of those that do not fit."""
+    g = rng(seed)
+    recs = []
+    for x in qaoa_circuit(n, edges, p, qaoa_angles(p, seed=seed)):
+        recs.append(x)
+        if int(x["kind"]) == G_DIAG2:
+            for q in (int(x["q0"]), int(x["q1"])):
+                recs.append(gate(G_1Q, q, -1, haar_2x2(g)))
+    return gates_array(recs)
+
+
 def qaoa_circuit(n: int, edges, p: int, theta) -> np.ndarray:
     """QAOA Max-Cut circuit as a gate list: H on every qubit, then per layer l
     a two-qubit diagonal diag(1, e^{-i g}, e^{-i g}, 1) per edge (g = gamma_l)

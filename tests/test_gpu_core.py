@@ -103,6 +103,19 @@ def test_block_matches_sequential(n, count, seed, dt):
     assert max_err(to_host(s), ref) < TOL[dt] * 8
 
 
+@pytest.mark.parametrize("dt", DTS)
+def test_block_reordered_passes(dt):
+    """16 qubits, a circuit whose passes move commuting gates ahead of those
+    that do not fit the tile (diagonals past one-qubit gates on other qubits)."""
+    n = 16
+    gates = W.dressed_qaoa_circuit(n, W.random_regular_graph(n, 3, seed=3), 2, seed=5)
+    s = _state(n, dt).init_random(9)
+    ref = oracle.init_random(n, 9)
+    s.apply_block(gates)
+    oracle.apply_gates(ref, gates)
+    assert max_err(to_host(s), ref) < TOL[dt] * 4
+
+
 def test_brick_circuit_12q():
     """12-qubit complex128 brick circuit from |0>: 20 layers of Haar 1q gates and
     CZ bricks; all amplitudes and <Z_i>."""

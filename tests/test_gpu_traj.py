@@ -56,6 +56,19 @@ def test_mixed_gate_kinds_frames(dt):
     _compare(n, gates, 5, 48, 0.2, seed=4, dt=dt)
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_reordered_passes_frames(dt):
+    """A circuit whose passes move commuting gates ahead (14 qubits, tiles of
+    12: a one-qubit gate after every two-qubit diagonal on both of its
+    qubits).  Each gate keeps the frame of its list position, and a
+    trajectory leaves the noiseless run at the first executed gate that sees
+    a non-identity frame."""
+    n = 14
+    gates = W.dressed_qaoa_circuit(n, W.random_regular_graph(n, 3, seed=3), 2, seed=5)
+    res, ens = _compare(n, gates, 77, 32, 0.01, seed=6, dt=dt)
+    assert 0 < ens["counts"].sum() and (ens["counts"] == 0).sum() > 0
+
+
 def test_noiseless_and_certain_insertion():
     n = 6
     gates = W.random_block(n, 30, seed=8)

@@ -69,6 +69,15 @@ def test_reordered_passes_frames(dt):
     assert 0 < ens["counts"].sum() and (ens["counts"] == 0).sum() > 0
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_reordered_passes_all_gate_kinds(dt):
+    """14 qubits, random 1Q / C1Q / DIAG2 / SWAP circuit whose plan moves
+    commuting gates ahead (5 passes instead of 8): controls flipped by the
+    frame, permuted diagonals and frame-relabelling swaps under reordering."""
+    n = 14
+    _compare(n, W.random_block(n, 120, seed=12), 321, 24, 0.008, seed=7, dt=dt)
+
+
 def test_noiseless_and_certain_insertion():
     n = 6
     gates = W.random_block(n, 30, seed=8)

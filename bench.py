@@ -275,6 +275,42 @@ def brick_bench():
             "us_per_circuit": round(t * 1e6, 1), "gates_per_s": round(len(gates) / t, 1)}
 
 
+def fused_bench(n=30):
+    """The sweep's gate list (Haar 1q on q = 0..n-1, then CNOT(q, q+1)) on a
+    30-qubit complex128 register (16 GiB) as one fused block, against the same
+    gates launched one by one.  pass_GB_per_s: the passes' real read+write
+    traffic; gate_GB_per_s: what the gates would move one at a time (1q: the
+    whole register, CNOT: the control-1 half, or all of it when the control
+    lies inside a 128-byte line), which fusion lets exceed the HBM peak."""
+    import torch
+
+    from paper_2001_10554_amd import workloads as W
+    from paper_2001_10554_amd.qsim import State, block_passes
+    mats, cnots = W.sweep_circuit(n, seed=2)
+    gates = W.gates_array([W.gate(W.G_1Q, q, -1, m) for q, m in enumerate(mats)]
+                          + [W.gate(W.G_C1Q, c, t, W.PAULI_X) for c, t in cnots])
+    passes = block_passes(n, gates)
+    s = State(n, torch.complex128).init_random(2)
+    t_fused = _time_cuda(lambda: s.apply_block(gates), 3)
+
+    def one_by_one():
+        for q, m in enumerate(mats):
+            s.apply_1q(q, m)
+        for c, t in cnots:
+            s.apply_c1q(c, t, W.PAULI_X)
+    t_single = _time_cuda(one_by_one, 2)
+    amp = 16
+    full = 2 * (1 << n) * amp
+    gate_bytes = n * full + sum(full if c < 3 else full // 2 for c, _ in cnots)
+    del s
+    torch.cuda.empty_cache()
+    return {"workload": f"{n}-qubit complex128 sweep (Haar 1q on every qubit, CNOT chain) as one fused block",
+            "gates": int(len(gates)), "passes": passes, "ms": round(t_fused * 1e3, 3),
+            "pass_GB_per_s": round(passes * full / t_fused / 1e9, 1),
+            "gate_GB_per_s": round(gate_bytes / t_fused / 1e9, 1),
+            "one_by_one_ms": round(t_single * 1e3, 3), "speedup": round(t_single / t_fused, 2)}
+
+
 def pso_bench(G=300, R=16, rounds=32):
     """Particle swarm over the pool, the paper's study shape: random 3-regular
     graphs on 18 vertices, p = 4 (8 coordinates), one swarm of R particles per
@@ -550,6 +586,8 @@ def main():
         out["traj"] = traj_bench()
         log("brick circuit")
         out["brick12"] = brick_bench()
+        log("fused block at 30 qubits")
+        out["fused30"] = fused_bench()
         log("particle swarm")
         out["pso"] = pso_bench()
         log("single-state rows at 30 qubits")

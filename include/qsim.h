@@ -155,14 +155,22 @@ int qs_collapse(qs_state *s, int q, int outcome, double *prob_dev);
 int qs_measure(qs_state *s, int q, uint64_t seed, int32_t *outcome_dev, double *prob_dev);
 
 /* Fused block: the same result as applying gates[0..count) one after the
- * other.  The library groups consecutive gates into passes whose targets fit
- * one on-chip tile and runs each pass as one read+write of the state.  Plans
+ * other (up to rounding).  The library groups the gates into passes whose
+ * targets fit one on-chip tile, moving a gate ahead of earlier ones when it
+ * commutes with them (disjoint qubits, or both diagonal) and that saves
+ * passes, and runs each pass as one read+write of the state.  Plans
  * are cached per gate list (content-keyed) in the handle; the first call with
  * a new list builds and uploads the plan synchronously, later calls with the
  * same list only launch kernels (so they may be captured in a hipGraph).
  * QS_ERR_ARG on an unknown kind (QS_G_NOISE included: noise gates belong to
  * trajectories) or a bad qubit. */
 int qs_apply_block(qs_state *s, const qs_gate *gates, int count);
+
+/* Number of read+write passes of the state that qs_apply_block takes for this
+ * gate list on an n-qubit register of this dtype (host-only planning; no
+ * device is touched).  *passes = 0 for count = 0.  QS_ERR_ARG / QS_ERR_DTYPE /
+ * QS_ERR_SIZE as for qs_state_create and qs_apply_block. */
+int qs_block_passes(int n, int dtype, const qs_gate *gates, int count, int *passes);
 
 /* QAOA cost layer: amplitude k *= exp(-i gamma C(k)),
  * C(k) = sum over edges (u,v) of w_uv [k_u != k_v]  (w NULL = unit weights).

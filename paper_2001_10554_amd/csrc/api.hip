@@ -4,6 +4,7 @@
 #include <new>
 
 #include "launch.h"
+#include "tile.h"
 
 #define QS_API extern "C" __attribute__((visibility("default")))
 
@@ -217,6 +218,21 @@ QS_API int qs_apply_block(qs_state *s, const qs_gate *gates, int count) {
     if (int rc = check_state(s)) return rc;
     if (int rc = validate_gates(s->n, gates, count, false)) return rc;
     return run_block(s, gates, count);
+    QS_GUARD_END
+}
+
+QS_API int qs_block_passes(int n, int dtype, const qs_gate *gates, int count, int *passes) {
+    QS_GUARD_BEGIN
+    if (!passes) return fail(QS_ERR_ARG, "null output pointer");
+    if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_ERR_DTYPE, "dtype must be QS_C64 or QS_C128");
+    if (n < 1) return fail(QS_ERR_ARG, "n must be >= 1");
+    if (n > (dtype == QS_C128 ? QS_MAX_QUBITS_C128 : QS_MAX_QUBITS_C64)) return fail(QS_ERR_SIZE, "n above the per-device limit");
+    if (int rc = validate_gates(n, gates, count, false)) return rc;
+    std::vector<DPass> plan;
+    std::vector<DGate> dg;
+    make_plan(n, dtype, tile_bits_max(dtype), gates, count, plan, dg);
+    *passes = (int)plan.size();
+    return QS_OK;
     QS_GUARD_END
 }
 

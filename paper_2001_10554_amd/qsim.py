@@ -90,6 +90,7 @@ def lib():
             "qs_collapse": [vp, i, i, vp],
             "qs_measure": [vp, i, u64, vp, vp],
             "qs_apply_block": [vp, vp, i],
+            "qs_block_passes": [i, i, vp, i, vp],
             "qs_apply_cut_phase": [vp, vp, vp, i, d],
             "qs_prob_one": [vp, i, vp],
             "qs_expect_z_all": [vp, vp],
@@ -394,6 +395,15 @@ class Pool:
                                 ctypes.c_void_p(self.G.data_ptr()) if self.G is not None else None,
                                 ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.c_void_p(_stream_ptr(stream))))
         return self.E, self.G
+
+
+def block_passes(n: int, gates: np.ndarray, dtype=torch.complex128) -> int:
+    """Read+write passes of the state that State.apply_block takes for this
+    gate list (host-side planning only)."""
+    g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
+    out = ctypes.c_int(-1)
+    check(lib().qs_block_passes(n, QS_C128 if dtype == torch.complex128 else QS_C64, _ptr(g), len(g), ctypes.byref(out)))
+    return out.value
 
 
 def cut_max(graphs, n_qubits, w=None, device="cuda", stream=None):

@@ -50,9 +50,13 @@ def test_only_qs_symbols_exported():
 
 
 def test_last_error_initially_empty(built_lib):
-    f = built_lib.qs_last_error
-    f.restype = ctypes.c_char_p
-    assert f() == b""
+    # a fresh process: the message is per thread and earlier tests may have set it
+    import subprocess
+    import sys
+    code = ("import ctypes, torch; L = ctypes.CDLL(%r); f = L.qs_last_error; "
+            "f.restype = ctypes.c_char_p; print(repr(f()))" % LIB)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True).stdout
+    assert out.strip() == "b''"
 
 
 def test_binding_names_match_header():

@@ -116,6 +116,24 @@ def test_block_reordered_passes(dt):
     assert max_err(to_host(s), ref) < TOL[dt] * 4
 
 
+@pytest.mark.parametrize("dt", DTS)
+def test_fused_sweep_26q(dt):
+    """The sweep's gate list (Haar 1q on every qubit, then the CNOT chain) as
+    one fused block on 26 qubits: 3 passes whose tiles cover different qubit
+    sets, full-state parity with the gates applied one by one by the oracle."""
+    from paper_2001_10554_amd.qsim import block_passes
+    n = 26
+    mats, cnots = W.sweep_circuit(n, seed=2)
+    gates = W.gates_array([W.gate(W.G_1Q, q, -1, m) for q, m in enumerate(mats)]
+                          + [W.gate(W.G_C1Q, c, t, W.PAULI_X) for c, t in cnots])
+    assert block_passes(n, gates, torch_dtype(dt)) == 3
+    s = _state(n, dt).init_random(4)
+    ref = oracle.init_random(n, 4)
+    s.apply_block(gates)
+    oracle.apply_gates(ref, gates)
+    assert max_err(to_host(s), ref) < TOL[dt] * 4
+
+
 def test_brick_circuit_12q():
     """12-qubit complex128 brick circuit from |0>: 20 layers of Haar 1q gates and
     CZ bricks; all amplitudes and <Z_i>."""

@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the QAOA, pool and trajectory measurements")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_1q_32q_c128.json"))
+    ap.add_argument("--section", choices=sorted(SECTIONS), help="run only this extra section and print its JSON")
     return ap.parse_args()
 
 
@@ -522,6 +523,9 @@ def cpu_baseline(seconds):
     return out
 
 
+SECTIONS = {}  # name -> function, filled below the section definitions
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -531,6 +535,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.section:
+        print(json.dumps({"section": args.section, **SECTIONS[args.section]()}), flush=True)
+        return
     n = args.n
     wall, per_1q, per_cx, norm, copy_gbs = sweep_bench(n, args.steps, args.warmup)
     bytes_1q = 2 * (1 << n) * 16
@@ -601,6 +608,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
+
+SECTIONS.update({"qaoa": qaoa_bench, "pool": pool_bench, "traj": traj_bench, "brick12": brick_bench, "fused30": fused_bench,
+                 "pso": pso_bench, "rows30": readout_bench, "kq": kq_bench, "noise": noise_bench})
 
 if __name__ == "__main__":
     main()

@@ -316,17 +316,30 @@ __global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ st
 #pragma unroll
     for (int q = 0; q < kTrajMaxQubits; ++q) z[q] = 0.0;
     const u64 lo = c << chunk_log2, hi = lo + (1ull << chunk_log2);
-    for (u64 i = lo + threadIdx.x; i < hi; i += kBlock) {
-        const cx<R> v = psi[i];
+    auto step = [&](u64 i, cx<R> v, cx<R> id, double dg) {
         const double p = (double)v.x * v.x + (double)v.y * v.y;
 #pragma unroll
         for (int q = 0; q < kTrajMaxQubits; ++q) z[q] += ((i >> q) & 1) ? -p : p;
-        const cx<R> id = ideal[i ^ fa];
         const double sgn = (__popcll(i & fb) & 1) ? -1.0 : 1.0;
         fre += sgn * ((double)id.x * v.x + (double)id.y * v.y);
         fim += sgn * ((double)id.x * v.y - (double)id.y * v.x);
-        if (diag) dsum += p * diag[i ^ fa];
+        dsum += p * dg;
+    };
+    u64 i = lo + threadIdx.x;
+    for (; i + 3 * kBlock < hi; i += 4 * kBlock) {  // four steps, loads first; same summation order
+        cx<R> v[4], id[4];
+        double dg[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const u64 k = i + (u64)s * kBlock;
+            v[s] = psi[k];
+            id[s] = ideal[k ^ fa];
+            dg[s] = diag ? diag[k ^ fa] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) step(i + (u64)s * kBlock, v[s], id[s], dg[s]);
     }
+    for (; i < hi; i += kBlock) step(i, psi[i], ideal[i ^ fa], diag ? diag[i ^ fa] : 0.0);
     const int nv = n + 3;
     double *out = partial + (u64)blockIdx.x * nv;
 #pragma unroll
@@ -359,7 +372,20 @@ __global__ __launch_bounds__(kBlock) void k_traj_x(const cx<R> *__restrict__ sta
     const cx<R> *psi = states + t * N;
     const u64 npairs = N >> 1, per = npairs >> chunks_log2;
     double acc = 0.0;
-    for (u64 k = c * per + threadIdx.x; k < (c + 1) * per; k += kBlock) {
+    const u64 k1 = (c + 1) * per;
+    u64 k = c * per + threadIdx.x;
+    for (; k + 3 * kBlock < k1; k += 4 * kBlock) {  // four steps, loads first; same summation order
+        cx<R> a[4], b[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const u64 i = insert0(k + (u64)s * kBlock, q);
+            a[s] = psi[i];
+            b[s] = psi[i | (1ull << q)];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc += 2.0 * ((double)a[s].x * b[s].x + (double)a[s].y * b[s].y);
+    }
+    for (; k < k1; k += kBlock) {
         const u64 i = insert0(k, q);
         const cx<R> a = psi[i], b = psi[i | (1ull << q)];
         acc += 2.0 * ((double)a.x * b.x + (double)a.y * b.y);

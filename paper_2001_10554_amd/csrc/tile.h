@@ -60,7 +60,12 @@ inline int tile_bits_max(int dtype) { return dtype == QS_C128 ? 12 : 13; }
 // fitting prefix of the list).  Diagonal gates and controls outside the tile
 // ride along.  Each pass of at least 3 tile bits is then cut into sweeps (see
 // DGate).
-void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg);
+//
+// cap > 0: passes that start among the first cap_region gates of the list
+// hold at most cap gates (trajectories: shorter early passes let more noisy
+// trajectories start late from the noiseless run's state).
+void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg,
+               int cap = 0, int cap_region = 0);
 
 // LDS tiles are stored swizzled: amplitude m of a tile sits at slot swz(m),
 // the low 3 bits (the 16-byte slot within a 128-byte row) XORed with bits

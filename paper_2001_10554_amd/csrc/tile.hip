@@ -102,7 +102,8 @@ static void make_sweeps(int tb, DGate *d, int cnt) {
 
 // Split the list into passes (see the file comment) and encode each gate's
 // qubits as tile-bit positions of its pass.
-void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg) {
+void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg, int cap,
+               int cap_region) {
     const int tbmax = std::min(std::min(tile_bits, tile_bits_max(dtype)), n);
     const int r = std::min(dtype == QS_C128 ? 3 : 4, tbmax);  // contiguous low qubits: 128-byte rows
     std::vector<int16_t> nidx(count);
@@ -118,6 +119,8 @@ void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std
         while (!rem.empty()) {
             u64 T = (1ull << r) - 1;
             u64 left_any = 0, left_nondiag = 0;  // qubits of the gates left for later passes
+            const int placed = count - (int)rem.size();
+            const size_t limit = cap > 0 && placed < cap_region ? (size_t)cap : (size_t)count;
             take.clear();
             later.clear();
             for (int j : rem) {
@@ -128,7 +131,7 @@ void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std
                 if (one) need = 1ull << x.q0;
                 else if (x.kind == QS_G_C1Q) need = 1ull << x.q1;
                 else if (x.kind == QS_G_SWAP) need = touch;
-                const bool blocked = commute ? (touch & (diag ? left_nondiag : left_any)) != 0 : !later.empty();
+                const bool blocked = take.size() >= limit || (commute ? (touch & (diag ? left_nondiag : left_any)) != 0 : !later.empty());
                 if (!blocked && __builtin_popcountll(T | need) <= tbmax) {
                     T |= need;
                     take.push_back(j);

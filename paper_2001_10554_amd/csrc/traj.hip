@@ -21,6 +21,8 @@
 // insert iff x0 < floor(p 2^32); Pauli = 1 + floor(3 x1 / 2^32).  The frames
 // kernel replays these integer decisions once per trajectory and stores the
 // frame seen by every gate, so the decisions are bit-exact by construction.
+#include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "launch.h"
@@ -551,6 +553,31 @@ static TrajLayout traj_layout(int n, int dtype, int count, int n_traj, int nnois
     return L;
 }
 
+// Expected pass work of a plan for trajectories with insertion probability p
+// per slot (gate applications plus a per-pass floor for the state traffic;
+// the noiseless run does every pass), used to choose how finely to cut the
+// early passes: a trajectory runs every pass from the one holding the first
+// gate executed after its first insertion.
+static double traj_plan_cost(const std::vector<DPass> &passes, const std::vector<DGate> &dg, const qs_gate *gates, int count, double p,
+                             int n_traj) {
+    constexpr double kFloor = 14.5;  // one pass's read+write of a state, in gate applications (measured, 16 qubits)
+    const int np = (int)passes.size();
+    std::vector<int> after(count + 1, np);  // after[g]: earliest pass holding a gate of the list beyond g - 1
+    for (int k = 0; k < np; ++k)
+        for (int i = passes[k].gate_begin; i < passes[k].gate_begin + passes[k].gate_count; ++i) after[dg[i].gidx] = k;
+    for (int g = count - 1; g >= 0; --g) after[g] = std::min(after[g], after[g + 1]);
+    std::vector<double> tail(np + 1, 0.0);
+    for (int k = np - 1; k >= 0; --k) tail[k] = tail[k + 1] + passes[k].gate_count + kFloor;
+    double surv = 1.0, e = 0.0;
+    for (int g = 0; g < count; ++g) {
+        const int slots = gates[g].kind == QS_G_NOISE ? 0 : gates[g].kind == QS_G_1Q ? 1 : 2;
+        const double pins = 1.0 - std::pow(1.0 - p, slots);
+        e += surv * pins * tail[after[g + 1]];
+        surv *= 1.0 - pins;
+    }
+    return n_traj * e + tail[0];
+}
+
 template <typename R, int TBMAX>
 static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 basis, int n_traj, double p, double inv_T1, double inv_T2, u64 seed,
                       const qs_traj_out *out, char *ws, hipStream_t st) {
@@ -560,6 +587,27 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     std::vector<DPass> passes;
     std::vector<DGate> dg;
     make_plan(n, dtype, TBMAX, gates, count, passes, dg);
+    bool noisy_gates = false;
+    for (int k = 0; k < count; ++k)
+        if (gates[k].kind == QS_G_NOISE && gates[k].u[0] > 0.0 && (inv_T1 > 0.0 || inv_T2 > 0.0)) noisy_gates = true;
+    // Sparse insertions: cut the first pass's stretch of the list into up to
+    // four shorter passes when the expected work drops (noise gates make every
+    // trajectory run every pass, so they keep the plan).
+    if (!noisy_gates && p > 0.0 && p < 1.0 && !passes.empty()) {
+        const int L = passes[0].gate_count;
+        double best = traj_plan_cost(passes, dg, gates, count, p, n_traj);
+        for (int parts = 2; parts <= 4 && L >= 2 * parts; ++parts) {
+            std::vector<DPass> p2;
+            std::vector<DGate> d2;
+            make_plan(n, dtype, TBMAX, gates, count, p2, d2, (L + parts - 1) / parts, L);
+            const double c = traj_plan_cost(p2, d2, gates, count, p, n_traj);
+            if (c < best) {
+                best = c;
+                passes.swap(p2);
+                dg.swap(d2);
+            }
+        }
+    }
     // dg holds every gate once, in execution order (dg[i].gidx: its list
     // index); each pass applies a slice of it.
     // The device copy carries each gate's first draw slot and its execution
@@ -578,9 +626,6 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     else if (p > 0.0) thr = (u32)floor(p * 4294967296.0);
     uint64_t *frames = (uint64_t *)(ws + L.frames), *final_frame = (uint64_t *)(ws + L.final_frame);
     int32_t *nins = (int32_t *)(ws + L.nins), *first_gate = (int32_t *)(ws + L.first);
-    bool noisy_gates = false;
-    for (int k = 0; k < count; ++k)
-        if (gates[k].kind == QS_G_NOISE && gates[k].u[0] > 0.0 && (inv_T1 > 0.0 || inv_T2 > 0.0)) noisy_gates = true;
     hipLaunchKernelGGL(k_traj_frames, dim3((n_traj + kFrameWaves) / kFrameWaves), dim3(64 * kFrameWaves), 0, st, (const TGate *)(ws + L.gates),
                        count, n_traj, thr,
                        (u32)seed, (u32)(seed >> 32), frames, final_frame, nins, first_gate, out->counts, out->log, out->log ? out->log_cap : 0,

@@ -59,12 +59,12 @@ extern "C" {
 
 typedef struct qs_state qs_state;
 
-/* Gate record for qs_apply_block and qs_traj_run (48 bytes, 8-byte aligned). */
+/* Gate record for qs_apply_block and qs_traj_run (80 bytes, 8-byte aligned). */
 typedef struct qs_gate {
     int32_t kind; /* QS_G_* */
     int32_t q0;   /* 1Q: target; C1Q: control; DIAG2 / SWAP: first qubit */
     int32_t q1;   /* C1Q: target; DIAG2 / SWAP: second qubit; unused for 1Q */
-    int32_t pad;
+    int32_t pad;  /* ignored */
     double u[8];  /* 1Q / C1Q: the 2x2 matrix; DIAG2: d00, d01, d10, d11 (re, im) with
                      entry index 2*bit(q1) + bit(q0); SWAP: unused */
 } qs_gate;

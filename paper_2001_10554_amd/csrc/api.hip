@@ -1,6 +1,7 @@
 // C-ABI entry points of libqsim_hip.so: argument validation, handle
 // management and dispatch to the launchers.  No C++ exception leaves this file.
 #include <cmath>
+#include <cstddef>
 #include <new>
 
 #include "launch.h"
@@ -9,6 +10,8 @@
 #define QS_API extern "C" __attribute__((visibility("default")))
 
 namespace qs {
+
+static_assert(sizeof(qs_gate) == 80 && offsetof(qs_gate, u) == 16, "qs_gate layout is part of the ABI");
 
 static thread_local std::string t_last_error;
 

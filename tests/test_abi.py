@@ -64,3 +64,12 @@ def test_binding_names_match_header():
     src = open(qsim.__file__).read()
     for n in declared_functions():
         assert f'"{n}"' in src or n == "qs_last_error", n
+
+
+def test_gate_record_layout_matches_header():
+    # qs_gate: int32 kind, q0, q1, pad, then double u[8] (80 bytes)
+    from paper_2001_10554_amd import workloads as W
+    dt = W.GATE_DTYPE
+    assert dt.itemsize == 80
+    assert [dt.fields[k][1] for k in ("kind", "q0", "q1", "pad", "u")] == [0, 4, 8, 12, 16]
+    assert "80 bytes" in open(HEADER).read()

@@ -44,6 +44,28 @@ static_assert(sizeof(TGate) == sizeof(qs_gate), "TGate mirrors qs_gate");
 static_assert(kTrajMaxGates % 8 == 0, "the frames kernel reads gate records in groups of eight");
 static_assert(2 * kTrajMaxGates <= 0xffff, "draw slots and execution positions share a 32-bit field");
 
+// SWAP gates at the end of the list only relabel qubits, so they are not
+// simulated: the read-outs see them instead.  With S their product, the true
+// state is S psi', psi' the simulated one: bit p of a true index is bit src[p]
+// of the simulated index, and the final frame F is carried back as
+// S^dagger F S (X_p -> X_src[p]).  active = 0: no trailing SWAPs.
+struct QPerm {
+    uint8_t src[kTrajMaxQubits];
+    int active;
+};
+// Simulated index -> true index.
+__device__ __forceinline__ u64 perm_index(const QPerm &P, int n, u64 k) {
+    u64 r = 0;
+    for (int p = 0; p < n; ++p) r |= ((k >> P.src[p]) & 1ull) << p;
+    return r;
+}
+// A frame mask in true qubit labels -> simulated labels.
+__device__ __forceinline__ u32 perm_mask(const QPerm &P, int n, u32 m) {
+    u32 r = 0;
+    for (int p = 0; p < n; ++p) r |= ((m >> p) & 1u) << P.src[p];
+    return r;
+}
+
 // frames[t * count + g] = (a | b << 32) before gate g; final[t] after all gates;
 // counts[t] = number of insertions.  first[t] = the earliest execution
 // position (index into the plan's gate order) of a gate that sees a
@@ -66,7 +88,7 @@ __global__ __launch_bounds__(64 * kFrameWaves) void k_traj_frames(const TGate *_
                                                                    u32 k1, uint64_t *__restrict__ frames, uint64_t *__restrict__ final_frame,
                                                                    int32_t *__restrict__ nins_ws, int32_t *__restrict__ first,
                                                                    int32_t *__restrict__ counts, uint32_t *__restrict__ log, int log_cap,
-                                                                   int force_all) {
+                                                                   int force_all, QPerm perm, int n) {
     __shared__ uint32_t hdr[kTrajMaxGates];  // kind | q0 << 8 | q1 << 16
     __shared__ uint16_t epos[kTrajMaxGates];
     __shared__ uint8_t dec[kFrameWaves][kTrajMaxGates];
@@ -131,6 +153,10 @@ __global__ __launch_bounds__(64 * kFrameWaves) void k_traj_frames(const TGate *_
                 }
             }
         }
+    }
+    if (perm.active) {
+        a = perm_mask(perm, n, a);
+        b = perm_mask(perm, n, b);
     }
     final_frame[t] = (u64)a | ((u64)b << 32);
     const bool own = force_all ? !ideal : e1 < count;
@@ -304,13 +330,17 @@ __device__ __forceinline__ double tblock_sum(double v, double *red) {
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ states, int n, int chunk_log2, int chunks_log2,
                                                     const uint64_t *__restrict__ final_frame, const int32_t *__restrict__ nins, int n_traj,
-                                                    const double *__restrict__ diag, double *__restrict__ partial) {
+                                                    const double *__restrict__ diag, double *__restrict__ partial, QPerm perm) {
     __shared__ double red[kBlock / 64];
     const u64 N = 1ull << n;
     const u64 c = blockIdx.x & ((1ull << chunks_log2) - 1);
     const u64 t = blockIdx.x >> chunks_log2;
-    if (!traj_simulated(nins, t, n_traj)) return;
-    const cx<R> *psi = states + t * N;
+    // A trajectory not simulated on its own but with a non-identity final
+    // frame (all its insertions after the last simulated gate) reads the
+    // noiseless state; its fidelity and diagonal observable still depend on
+    // its frame, so it gets partials of its own.
+    if (!traj_simulated(nins, t, n_traj) && final_frame[t] == 0) return;
+    const cx<R> *psi = states + traj_rep(nins, t, n_traj) * N;
     const cx<R> *ideal = states + (u64)n_traj * N;
     const u64 f = final_frame[t];
     const u32 fa = (u32)f, fb = (u32)(f >> 32);
@@ -336,12 +366,12 @@ __global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ st
             const u64 k = i + (u64)s * kBlock;
             v[s] = psi[k];
             id[s] = ideal[k ^ fa];
-            dg[s] = diag ? diag[k ^ fa] : 0.0;
+            dg[s] = diag ? diag[perm.active ? perm_index(perm, n, k ^ fa) : k ^ fa] : 0.0;
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) step(i + (u64)s * kBlock, v[s], id[s], dg[s]);
     }
-    for (; i < hi; i += kBlock) step(i, psi[i], ideal[i ^ fa], diag ? diag[i ^ fa] : 0.0);
+    for (; i < hi; i += kBlock) step(i, psi[i], ideal[i ^ fa], diag ? diag[perm.active ? perm_index(perm, n, i ^ fa) : i ^ fa] : 0.0);
     const int nv = n + 3;
     double *out = partial + (u64)blockIdx.x * nv;
 #pragma unroll
@@ -400,7 +430,7 @@ __global__ __launch_bounds__(kBlock) void k_traj_x(const cx<R> *__restrict__ sta
 // trajectory's representative in order, then undo the trajectory's frame.
 __global__ void k_traj_final(const double *__restrict__ pzf, const double *__restrict__ px, int n, int chunks, int n_traj,
                              const uint64_t *__restrict__ final_frame, const int32_t *__restrict__ nins, double *__restrict__ z,
-                             double *__restrict__ x, double *__restrict__ fid, double *__restrict__ dval) {
+                             double *__restrict__ x, double *__restrict__ fid, double *__restrict__ dval, QPerm perm) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     const int per = n + n + 2;  // z values, x values, fidelity, diagonal observable
     if (id >= n_traj * per) return;
@@ -409,19 +439,21 @@ __global__ void k_traj_final(const double *__restrict__ pzf, const double *__res
     const u64 f = final_frame[t];
     const u32 a = (u32)f, b = (u32)(f >> 32);
     const int nv = n + 3;
+    const u64 zsrc = traj_simulated(nins, t, n_traj) || f != 0 ? (u64)t : rep;  // whose Z / fidelity partials (see k_traj_zf)
     if (v < n) {
-        const double *p = pzf + rep * chunks * nv;
+        const int qs = perm.active ? perm.src[v] : v;  // the simulated qubit that ends on qubit v
+        const double *p = pzf + zsrc * chunks * nv;
         double s = 0.0;
-        for (int c = 0; c < chunks; ++c) s += p[(u64)c * nv + v];
-        if (z) z[(u64)t * n + v] = ((a >> v) & 1) ? -s : s;
+        for (int c = 0; c < chunks; ++c) s += p[(u64)c * nv + qs];
+        if (z) z[(u64)t * n + v] = ((a >> qs) & 1) ? -s : s;
     } else if (v < 2 * n) {
-        const int q = v - n;
-        const double *p = px + (rep * n + q) * chunks;
+        const int q = v - n, qs = perm.active ? perm.src[q] : q;
+        const double *p = px + (rep * n + qs) * chunks;
         double s = 0.0;
         for (int c = 0; c < chunks; ++c) s += p[c];
-        if (x) x[(u64)t * n + q] = ((b >> q) & 1) ? -s : s;
+        if (x) x[(u64)t * n + q] = ((b >> qs) & 1) ? -s : s;
     } else if (v == 2 * n) {
-        const double *p = pzf + rep * chunks * nv;
+        const double *p = pzf + zsrc * chunks * nv;
         double re = 0.0, im = 0.0;
         for (int c = 0; c < chunks; ++c) {
             re += p[(u64)c * nv + n];
@@ -429,7 +461,7 @@ __global__ void k_traj_final(const double *__restrict__ pzf, const double *__res
         }
         if (fid) fid[t] = re * re + im * im;
     } else {
-        const double *p = pzf + rep * chunks * nv;
+        const double *p = pzf + zsrc * chunks * nv;
         double s = 0.0;
         for (int c = 0; c < chunks; ++c) s += p[(u64)c * nv + n + 2];
         if (dval) dval[t] = s;
@@ -479,7 +511,7 @@ __global__ __launch_bounds__(1024) void k_traj_pm_list(int n_traj, const uint64_
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restrict__ states, u64 N, int n_traj, const uint64_t *__restrict__ final_frame,
                                                            const int32_t *__restrict__ nins, const int32_t *__restrict__ list,
-                                                           const int32_t *__restrict__ cnt, double *__restrict__ out) {
+                                                           const int32_t *__restrict__ cnt, double *__restrict__ out, QPerm perm, int n) {
     const u64 k = (u64)blockIdx.x * kBlock + threadIdx.x;
     if (k >= N) return;
     const int m = cnt[0];
@@ -501,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restri
         const cx<R> v = states[traj_rep(nins, (u64)t, n_traj) * N + (k ^ (u32)final_frame[t])];
         s += (double)v.x * v.x + (double)v.y * v.y;
     }
-    out[k] = s / (double)n_traj;
+    out[perm.active ? perm_index(perm, n, k) : k] = s / (double)n_traj;
 }
 
 // ------------------------------------------------------------------ host side
@@ -584,9 +616,21 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     const int nnoise = count_noise(gates, count);
     const TrajLayout L = traj_layout(n, dtype, count, n_traj, nnoise);
     const u64 N = 1ull << n;
+    // SWAP gates at the end of a list without noise gates are not simulated:
+    // they become the read-outs' qubit relabelling (QPerm).
+    QPerm perm{};
+    int count_exec = count;
+    if (nnoise == 0) {
+        while (count_exec > 1 && gates[count_exec - 1].kind == QS_G_SWAP) --count_exec;
+        if (count_exec < count) {
+            perm.active = 1;
+            for (int q = 0; q < kTrajMaxQubits; ++q) perm.src[q] = (uint8_t)q;
+            for (int k = count_exec; k < count; ++k) std::swap(perm.src[gates[k].q0], perm.src[gates[k].q1]);
+        }
+    }
     std::vector<DPass> passes;
     std::vector<DGate> dg;
-    make_plan(n, dtype, TBMAX, gates, count, passes, dg);
+    make_plan(n, dtype, TBMAX, gates, count_exec, passes, dg);
     bool noisy_gates = false;
     for (int k = 0; k < count; ++k)
         if (gates[k].kind == QS_G_NOISE && gates[k].u[0] > 0.0 && (inv_T1 > 0.0 || inv_T2 > 0.0)) noisy_gates = true;
@@ -599,7 +643,7 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
         for (int parts = 2; parts <= 4 && L >= 2 * parts; ++parts) {
             std::vector<DPass> p2;
             std::vector<DGate> d2;
-            make_plan(n, dtype, TBMAX, gates, count, p2, d2, (L + parts - 1) / parts, L);
+            make_plan(n, dtype, TBMAX, gates, count_exec, p2, d2, (L + parts - 1) / parts, L);
             const double c = traj_plan_cost(p2, d2, gates, count, p, n_traj);
             if (c < best) {
                 best = c;
@@ -608,12 +652,14 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
             }
         }
     }
-    // dg holds every gate once, in execution order (dg[i].gidx: its list
-    // index); each pass applies a slice of it.
+    // dg holds every simulated gate once, in execution order (dg[i].gidx: its
+    // list index); each pass applies a slice of it.
     // The device copy carries each gate's first draw slot and its execution
-    // position in the plan in its pad field (16 bits each).
+    // position in the plan in its pad field (16 bits each; count for the
+    // trailing SWAPs, which are never executed).
     std::vector<qs_gate> gl(gates, gates + count);
-    for (int i = 0; i < count; ++i) gl[dg[i].gidx].pad = i << 16;
+    for (int k = 0; k < count; ++k) gl[k].pad = count << 16;
+    for (size_t i = 0; i < dg.size(); ++i) gl[dg[i].gidx].pad = (int)i << 16;
     for (int k = 0, slot = 0; k < count; ++k) {
         gl[k].pad |= slot;
         slot += gates[k].kind == QS_G_NOISE ? 0 : gates[k].kind == QS_G_1Q ? 1 : 2;
@@ -629,7 +675,7 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     hipLaunchKernelGGL(k_traj_frames, dim3((n_traj + kFrameWaves) / kFrameWaves), dim3(64 * kFrameWaves), 0, st, (const TGate *)(ws + L.gates),
                        count, n_traj, thr,
                        (u32)seed, (u32)(seed >> 32), frames, final_frame, nins, first_gate, out->counts, out->log, out->log ? out->log_cap : 0,
-                       noisy_gates ? 1 : 0);
+                       noisy_gates ? 1 : 0, perm, n);
     QS_LAUNCH_CHECK("traj_frames");
     double *nm = (double *)(ws + L.nm);
     if (nnoise) {
@@ -661,7 +707,7 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     if (out->z || out->fid || diag) {
         const u64 blocks = (u64)T1 << L.chunks_log2;
         hipLaunchKernelGGL(k_traj_zf<R>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<R> *)states, n, L.chunk_log2, L.chunks_log2,
-                           (const uint64_t *)final_frame, (const int32_t *)nins, n_traj, diag, pzf);
+                           (const uint64_t *)final_frame, (const int32_t *)nins, n_traj, diag, pzf, perm);
         QS_LAUNCH_CHECK("traj_zf");
     }
     if (out->x) {
@@ -673,7 +719,8 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     if (out->z || out->x || out->fid || diag) {
         const int work = n_traj * (2 * n + 2);
         hipLaunchKernelGGL(k_traj_final, dim3((work + 255) / 256), dim3(256), 0, st, (const double *)pzf, (const double *)px, n, chunks, n_traj,
-                           (const uint64_t *)final_frame, (const int32_t *)nins, out->z, out->x, out->fid, diag ? out->diag_val : nullptr);
+                           (const uint64_t *)final_frame, (const int32_t *)nins, out->z, out->x, out->fid, diag ? out->diag_val : nullptr,
+                           perm);
         QS_LAUNCH_CHECK("traj_final");
     }
     if (out->prob_mean) {
@@ -681,7 +728,8 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
         hipLaunchKernelGGL(k_traj_pm_list, dim3(1), dim3(1024), 0, st, n_traj, (const uint64_t *)final_frame, (const int32_t *)nins, pml, pmc);
         QS_LAUNCH_CHECK("traj_prob_mean");
         hipLaunchKernelGGL(k_traj_prob_mean<R>, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, (const cx<R> *)states, N, n_traj,
-                           (const uint64_t *)final_frame, (const int32_t *)nins, (const int32_t *)pml, (const int32_t *)pmc, out->prob_mean);
+                           (const uint64_t *)final_frame, (const int32_t *)nins, (const int32_t *)pml, (const int32_t *)pmc, out->prob_mean,
+                           perm, n);
         QS_LAUNCH_CHECK("traj_prob_mean");
     }
     return QS_OK;

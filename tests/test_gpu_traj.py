@@ -78,6 +78,33 @@ def test_reordered_passes_all_gate_kinds(dt):
     _compare(n, W.random_block(n, 120, seed=12), 321, 24, 0.008, seed=7, dt=dt)
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_insertions_after_the_last_simulated_gate(dt):
+    """Trajectories whose insertions all follow the last simulated gate are not
+    simulated: they read the noiseless state through their own Pauli frame.
+    One gate (every insertion comes after it), and a circuit ending in SWAPs
+    (the trailing SWAPs are folded into the read-outs): fidelity, <Z>, <X>,
+    the probability mean and a diagonal observable against the oracle."""
+    import torch
+    from paper_2001_10554_amd.qsim import traj_run
+    g = np.random.default_rng(4)
+    n = 4
+    one = W.gates_array([W.gate(W.G_1Q, 1, -1, W.haar_2x2(g))])
+    tail = np.concatenate([W.random_block(n, 12, seed=9),
+                           W.gates_array([W.gate(W.G_SWAP, 0, 3), W.gate(W.G_SWAP, 1, 2), W.gate(W.G_SWAP, 0, 1)])])
+    d = g.standard_normal(1 << n)
+    tol = TOL[dt] * 8
+    for gates, p in ((one, 0.5), (tail, 0.1)):
+        res = traj_run(n, gates, 6, 48, p, seed=3, dtype=torch_dtype(dt), log_cap=16,
+                       diag=torch.tensor(d, device="cuda"))
+        ens = oracle.traj_ensemble(n, gates, 6, 48, p, 3, log_cap=16, diag=d)
+        assert np.array_equal(res["counts"].cpu().numpy(), ens["counts"])
+        for key in ("z", "x", "fid", "prob_mean", "diag"):
+            err = np.max(np.abs(res[key].cpu().numpy() - ens[key]))
+            assert err < tol * (4 if key == "diag" else 1), (key, err)
+        assert np.min(ens["fid"]) < 0.9  # some frames move the state away from the noiseless one
+
+
 def test_noiseless_and_certain_insertion():
     n = 6
     gates = W.random_block(n, 30, seed=8)

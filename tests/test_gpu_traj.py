@@ -105,6 +105,15 @@ def test_insertions_after_the_last_simulated_gate(dt):
         assert np.min(ens["fid"]) < 0.9  # some frames move the state away from the noiseless one
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_qft20_largest_register(dt):
+    """20 qubits, the largest trajectory register: several tile passes, 256
+    read-out chunks per state and the QFT's ten final SWAPs folded into the
+    read-outs."""
+    n = 20
+    _compare(n, W.qft_circuit(n), W.random_basis_index(n, 21), 6, 0.004, seed=13, dt=dt, log_cap=16)
+
+
 def test_noiseless_and_certain_insertion():
     n = 6
     gates = W.random_block(n, 30, seed=8)

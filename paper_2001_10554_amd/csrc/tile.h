@@ -26,7 +26,7 @@ struct DGate {
     int8_t q0, q1;
     int8_t s0, s1;  // group slot (0..2) of p0 / p1 in the gate's sweep, -1 if not a group bit
     int8_t g[3];    // first gate of a sweep: the group bits (ascending); unused otherwise
-    int8_t pad0;
+    int8_t pad0;    // trajectory plans: 1 = also applies the next gate (a noise gate on its qubit), 2 = that noise gate
     int16_t run;    // first gate of a sweep: gates in the sweep; 0 for the others
     int16_t nidx;   // noise gates: index among the list's noise gates
     int32_t gidx;   // index of the gate in the caller's list (passes may reorder commuting gates)

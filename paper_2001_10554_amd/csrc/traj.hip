@@ -171,6 +171,28 @@ __global__ __launch_bounds__(64 * kFrameWaves) void k_traj_frames(const TGate *_
 __device__ __forceinline__ bool traj_simulated(const int32_t *nins, u64 t, int n_traj) { return t == (u64)n_traj || nins[t] > 0; }
 __device__ __forceinline__ u64 traj_rep(const int32_t *nins, u64 t, int n_traj) { return nins[t] > 0 ? t : (u64)n_traj; }
 
+// u <- w u (2x2 complex, row-major interleaved).
+__device__ __forceinline__ void mat2_mul(const double *w, double *u) {
+    double r[8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            double re = 0.0, im = 0.0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const double wr = w[(2 * i + k) * 2], wi = w[(2 * i + k) * 2 + 1];
+                const double ur = u[(2 * k + j) * 2], ui = u[(2 * k + j) * 2 + 1];
+                re += wr * ur - wi * ui;
+                im += wr * ui + wi * ur;
+            }
+            r[(2 * i + j) * 2] = re;
+            r[(2 * i + j) * 2 + 1] = im;
+        }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k] = r[k];
+}
+
 // U' = P^dagger U P for P = X^xa Z^zb (row-major interleaved u[8]).
 __device__ __forceinline__ void conj_pauli(double *u, int xa, int zb) {
     if (xa) {  // X U X: swap rows and columns
@@ -259,7 +281,7 @@ __global__ __launch_bounds__(kTileThreads) void k_traj_pass(cx<R> *__restrict__ 
         const u32 a = (u32)f, b = (u32)(f >> 32);
         double u[8];
         if (kind == QS_G_NOISE) {
-            if (ideal) return false;  // the noiseless reference run
+            if (ideal || g.pad0 == 2) return false;  // the noiseless reference run / folded into the gate before
             const double *src = nm + ((u64)t * nnoise + g.nidx) * 8;
 #pragma unroll
             for (int k = 0; k < 8; ++k) u[k] = src[k];
@@ -270,6 +292,18 @@ __global__ __launch_bounds__(kTileThreads) void k_traj_pass(cx<R> *__restrict__ 
             for (int k = 0; k < 8; ++k) u[k] = g.u[k];
             if (kind == QS_G_1Q) {
                 conj_pauli(u, (a >> g.q0) & 1, (b >> g.q0) & 1);
+                if (g.pad0 == 1 && !ideal) {
+                    // The next gate (execution order) is a noise gate on the same
+                    // qubit: apply both as one matrix, each conjugated by its own frame.
+                    const DGate &nx = (&g)[1];
+                    const u64 f2 = frames[t * count + nx.gidx];
+                    const double *src = nm + ((u64)t * nnoise + nx.nidx) * 8;
+                    double w[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) w[k] = src[k];
+                    conj_pauli(w, ((u32)f2 >> g.q0) & 1, ((u32)(f2 >> 32) >> g.q0) & 1);
+                    mat2_mul(w, u);
+                }
             } else if (kind == QS_G_C1Q) {
                 cval = 1 ^ (int)((a >> g.q0) & 1);
                 conj_pauli(u, (a >> g.q1) & 1, (b >> g.q1) & 1);
@@ -652,6 +686,15 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
             }
         }
     }
+    // A one-qubit gate followed (execution order) by a noise gate on its qubit
+    // takes the noise matrix into its own (pad0 = 1); the noise gate is then
+    // skipped (pad0 = 2).
+    for (size_t i = 0; nnoise && i + 1 < dg.size(); ++i)
+        if (dg[i].kind == QS_G_1Q && dg[i + 1].kind == QS_G_NOISE && dg[i + 1].q0 == dg[i].q0) {
+            dg[i].pad0 = 1;
+            dg[i + 1].pad0 = 2;
+            ++i;
+        }
     // dg holds every simulated gate once, in execution order (dg[i].gidx: its
     // list index); each pass applies a slice of it.
     // The device copy carries each gate's first draw slot and its execution

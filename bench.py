@@ -11,9 +11,11 @@ per-launch durations.
 
 Printed: one JSON line.  value = algorithmic bytes of the one-qubit gates
 (2 * 2^32 * 16 B each: every amplitude read and written once) divided by their
-summed kernel time.  roofline = the same for the dominant kernel (the
-one-qubit gate) against MI355X's 8 TB/s.  cpu_baseline = the CPU oracle on a
-bounded sample of the same sweep.
+summed kernel time.  roofline = the same for the dominant kernels (the
+one-qubit gate: k_apply_1q, and k_apply_1q_lane for targets below 6) against
+MI355X's 8 TB/s.  cpu_baseline = the CPU oracle on a bounded sample of the
+same sweep.  The line ends with both halves of the metric: the QAOA
+adjoint/finite-difference ratio and the per-target minima.
 """
 from __future__ import annotations
 
@@ -44,7 +46,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_1q_32q_c128.json"))
     ap.add_argument("--section", choices=sorted(SECTIONS), help="run only this extra section and print its JSON")
+    ap.add_argument("--curves", default=None,
+                    help="also compute the convergence / approximation-ratio curves of the study workloads and write them "
+                         "to this JSON file (they are not part of the printed line)")
     return ap.parse_args()
+
+
+CURVES = {}  # filled by the sections when --curves is given
 
 
 def log(msg):
@@ -243,15 +251,16 @@ def traj_bench():
                      "max_abs_Z": float(r["z"].abs().max().item()),
                      "max_abs_p_minus_2^-16": float((r["prob_mean"] - 2.0 ** -n).abs().max().item()),
                      "insertions": int(r["counts"].sum().item())}
-    # Convergence of the trajectory means with T, over 8 independent seeds (c128).
-    curves_f, curves_x = [], []
-    for seed in range(5, 13):
-        r = traj_run(n, gates, x0, T, p, seed=seed, dtype=torch.complex128, prob_mean=False)
-        fid = r["fid"].cpu().numpy()
-        xm = r["x"].cpu().numpy().mean(axis=1)  # mean over qubits of <X_q>, per trajectory
-        curves_f.append([round(float(fid[:k].mean()), 6) for k in Ts])
-        curves_x.append([round(float(xm[:k].mean()), 6) for k in Ts])
-    out["convergence"] = {"T": Ts, "seeds": list(range(5, 13)), "mean_fidelity": curves_f, "mean_X": curves_x}
+    if CURVES.get("enabled"):
+        # Convergence of the trajectory means with T, over 8 independent seeds (c128).
+        curves_f, curves_x = [], []
+        for seed in range(5, 13):
+            r = traj_run(n, gates, x0, T, p, seed=seed, dtype=torch.complex128, prob_mean=False)
+            fid = r["fid"].cpu().numpy()
+            xm = r["x"].cpu().numpy().mean(axis=1)  # mean over qubits of <X_q>, per trajectory
+            curves_f.append([round(float(fid[:k].mean()), 6) for k in Ts])
+            curves_x.append([round(float(xm[:k].mean()), 6) for k in Ts])
+        CURVES["traj_convergence"] = {"T": Ts, "seeds": list(range(5, 13)), "mean_fidelity": curves_f, "mean_X": curves_x}
     return out
 
 
@@ -344,9 +353,10 @@ def pso_bench(G=300, R=16, rounds=32):
                        f"(512 evaluations per graph), complex128",
            "evaluations_per_s": round(evals / t, 1), "ms_per_round": round(t / rounds * 1e3, 3), "seconds_per_run": round(t, 4),
            "first_run_s": round(t_setup, 2), "cut_max_ms_all_graphs": round(t_cut * 1e3, 2),
-           "mean_ratio_by_round": [round(float(x), 5) for x in ratio.mean(axis=1)],
            "mean_ratio_at_512_evals": round(float(ratio[-1].mean()), 5), "std_ratio_at_512_evals": round(float(ratio[-1].std()), 5),
-           "max_ratio": float(ratio.max())}
+           "max_ratio": round(float(ratio.max()), 5)}
+    if CURVES.get("enabled"):
+        CURVES["pso_mean_ratio_by_round"] = [round(float(x), 5) for x in ratio.mean(axis=1)]
     del pool, sw
     torch.cuda.empty_cache()
     return out
@@ -382,16 +392,18 @@ def noise_bench(T=1024):
     for label, theta in (("pso_angles", theta_pso), ("random_angles", W.qaoa_angles(p, seed=9, hi=2 * math.pi))):
         gates = W.with_noise_gates(W.qaoa_circuit(n, edges, p, theta), 1.0)
         t = _time_cuda(lambda: traj_run(n, gates, 0, T, 0.0, 1, T1=500.0, T2=250.0, diag=diag, prob_mean=False), 2)
-        curves = []
-        for seed in range(1, 9):
-            r = traj_run(n, gates, 0, T, 0.0, seed, T1=500.0, T2=250.0, diag=diag, prob_mean=False)
-            c = r["diag"].cpu().numpy()
-            curves.append([round(float(c[:m].mean()), 5) for m in Ts])
+        r = traj_run(n, gates, 0, T, 0.0, 1, T1=500.0, T2=250.0, diag=diag, prob_mean=False)
         ideal = traj_run(n, gates, 0, 1, 0.0, 1, diag=diag, prob_mean=False)  # no decay: the noiseless value
         out[label] = {"gates": int(len(gates)), "trajectories_per_s": round(T / t, 1), "ms": round(t * 1e3, 3),
                       "noiseless_C": round(float(ideal["diag"][0].item()), 6),
-                      "noisy_C_mean_8x1024": round(float(np.mean([cv[-1] for cv in curves])), 5),
-                      "convergence": {"T": Ts, "mean_C": curves}}
+                      "noisy_C_mean": round(float(r["diag"].mean().item()), 5)}
+        if CURVES.get("enabled"):
+            curves = []
+            for seed in range(1, 9):
+                r = traj_run(n, gates, 0, T, 0.0, seed, T1=500.0, T2=250.0, diag=diag, prob_mean=False)
+                c = r["diag"].cpu().numpy()
+                curves.append([round(float(c[:m].mean()), 5) for m in Ts])
+            CURVES[f"noise_{label}_convergence"] = {"T": Ts, "mean_C": curves}
     out["pso_angles"]["swarm_best_C"] = round(e_pso, 6)
     del pool, sw
     torch.cuda.empty_cache()
@@ -468,39 +480,56 @@ def kq_bench(n=30):
 
 
 def cpu_baseline(seconds):
-    """Oracle (plain C, OpenMP element loops) applying the sweep's Haar gates to a
-    smaller register until `seconds` of gate time have been spent."""
+    """The oracle (plain C; OpenMP on its element loops) on bounded samples of
+    the workloads: one-qubit gates per target on a 28-qubit register (4 GiB;
+    the 32-qubit register does not fit the host budget of this run), with all
+    host threads and single-threaded; the QAOA adjoint gradient at 22 qubits,
+    p = 8 (one evaluation); the brick circuit, pool circuits and trajectories
+    on small samples.  `seconds` caps the single-threaded gate timing."""
     import numpy as np
 
     import oracle
     from paper_2001_10554_amd import workloads as W
 
-    n = 26
+    nthreads = oracle.threads()
+    n = 28
     mats, _ = W.sweep_circuit(n, seed=2)
     psi = oracle.init_random(n, 2)
-    spent, gates = 0.0, 0
-    q = 0
-    while spent < seconds:
+    gate_bytes = 2 * (1 << n) * 16
+    per_q = {}
+    for q in range(n):
         t = time.perf_counter()
         oracle.apply_1q(psi, q, mats[q])
-        spent += time.perf_counter() - t
-        gates += 1
-        q = (q + 1) % n
-    bytes_moved = gates * 2 * (1 << n) * 16
-    out = {"value": round(bytes_moved / spent / 1e9, 3), "unit": "GB/s", "cores": oracle.threads(), "kind": "oracle",
-           "sample": f"{gates} one-qubit gates (targets cycling 0..{n-1}) on a {n}-qubit c128 register, "
-                     f"{spent:.1f} s of gate time"}
-    # Oracle QAOA gradient evaluations/s on a smaller instance of the same family.
+        per_q[q] = time.perf_counter() - t
+    omp_gbs = n * gate_bytes / sum(per_q.values()) / 1e9
+    oracle.set_threads(1)
+    single, spent = {}, 0.0
+    try:
+        for q in (0, 7, 14, 21, n - 1):
+            if spent > seconds:
+                break
+            t = time.perf_counter()
+            oracle.apply_1q(psi, q, mats[q])
+            single[q] = time.perf_counter() - t
+            spent += single[q]
+    finally:
+        oracle.set_threads(nthreads)
+    out = {"value": round(omp_gbs, 3), "unit": "GB/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"one Haar one-qubit gate on each target q = 0..{n-1} of a {n}-qubit c128 register, "
+                     f"{nthreads} OpenMP threads",
+           "per_qubit_gbs": {str(q): round(gate_bytes / t / 1e9, 2) for q, t in per_q.items()},
+           "single_thread": {"GB_per_s": round(len(single) * gate_bytes / sum(single.values()) / 1e9, 3),
+                             "targets": sorted(single)}}
     del psi
-    nq, p = 20, 8
+    nq, p = 22, 8
     edges = W.random_regular_graph(nq, 3, seed=3)
     theta = W.qaoa_angles(p, seed=3)
     t0 = time.perf_counter()
     oracle.qaoa_grad(nq, edges, p, theta)
     t_adj = time.perf_counter() - t0
-    out["qaoa"] = {"adjoint_grads_per_s": round(1.0 / t_adj, 3),
-                   "sample": f"oracle adjoint gradient, {nq}-qubit random 3-regular graph, p={p}, one evaluation"}
-    # The other workloads, each on a small sample.
+    out["qaoa"] = {"adjoint_grads_per_s": round(1.0 / t_adj, 4),
+                   "sample": f"oracle adjoint gradient, {nq}-qubit random 3-regular graph, p={p}, one evaluation, "
+                             f"{nthreads} threads (24 qubits takes ~4x longer)"}
     gates = W.brick_circuit(12, 20, seed=1)
     t0 = time.perf_counter()
     for _ in range(20):
@@ -547,9 +576,13 @@ def main():
     gbs = bytes_1q * launches_1q / t1q / 1e9
     # Per target: the median launch time of the timed steps.
     per_q = {q: round(bytes_1q / statistics.median(v) / 1e9, 1) for q, v in per_1q.items()}
-    # CNOT: only the control-1 half is read and written (2^(n-1) amplitudes, R+W).
-    bytes_cx = 2 * (1 << (n - 1)) * 16
-    per_c = {q: round(bytes_cx / statistics.median(v) / 1e9, 1) for q, v in per_cx.items()}
+    # CNOT: the control-1 half is read and written (2^(n-1) amplitudes, R+W);
+    # a control inside a 128-byte line (c < 3 for c128) touches every line, so
+    # its algorithmic bytes are the whole register (line granularity).
+    per_c = {}
+    for q, v in per_cx.items():
+        bytes_cx = 2 * (1 << n) * 16 if q < 3 else 2 * (1 << (n - 1)) * 16
+        per_c[q] = round(bytes_cx / statistics.median(v) / 1e9, 1)
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
@@ -574,38 +607,36 @@ def main():
         "config": {"workload": f"{n}-qubit complex128 sweep: Haar 1q gate on q=0..{n-1}, then CNOT(q,q+1) for q=0..{n-2}; "
                                "seeded random normalised state in HBM",
                    "n_qubits": n, "state_bytes": (1 << n) * 16, "gates_per_step": 2 * n - 1},
-        "roofline": {"bound": "hbm", "achieved": round(bytes_1q / avg_1q / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(bytes_1q / avg_1q / 1e9 / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": "k_apply_1q", "bytes_per_launch": bytes_1q, "avg_launch_ms": round(avg_1q * 1e3, 4)},
         "per_qubit_1q_gbs": per_q,
         "per_qubit_cnot_gbs": per_c,
-        "min_1q_frac": round(min(per_q.values()) / PEAK_HBM_GBS, 4),
         "device_copy_gbs": round(copy_gbs, 1),
         "value_over_device_copy": round(gbs / copy_gbs, 3),
         "norm_after": norm,
     }
+    if args.curves:
+        CURVES["enabled"] = True
     if not args.no_extra:
-        log("QAOA adjoint vs finite differences")
-        out["qaoa"] = qaoa_bench()
-        log("pool")
-        out["pool"] = pool_bench()
-        log("trajectories")
-        out["traj"] = traj_bench()
-        log("brick circuit")
-        out["brick12"] = brick_bench()
-        log("fused block at 30 qubits")
-        out["fused30"] = fused_bench()
-        log("particle swarm")
-        out["pso"] = pso_bench()
-        log("single-state rows at 30 qubits")
-        out["rows30"] = readout_bench()
-        log("k-qubit gates and measurement")
-        out["kq"] = kq_bench()
-        log("noisy QAOA trajectories")
-        out["noise"] = noise_bench()
+        for name in ("qaoa", "pool", "traj", "brick12", "fused30", "pso", "rows30", "kq", "noise"):
+            log(name)
+            out[name] = SECTIONS[name]()
+    out["roofline"] = {"bound": "hbm", "achieved": round(bytes_1q / avg_1q / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": round(bytes_1q / avg_1q / 1e9 / PEAK_HBM_GBS, 4), "traffic": traffic,
+                       "kernel": "k_apply_1q (targets 6..n-1) + k_apply_1q_lane (targets 0..5)",
+                       "bytes_per_launch": bytes_1q, "avg_launch_ms": round(avg_1q * 1e3, 4)}
     if not args.no_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    if "qaoa" in out:
+        q = out["qaoa"]
+        out["qaoa_adjoint_grads_per_s"] = q["adjoint_grads_per_s"]
+        out["qaoa_fd_grads_per_s"] = q["fd_grads_per_s"]
+        out["qaoa_adjoint_over_fd"] = q["ratio"]
+    out["min_1q_frac"] = round(min(per_q.values()) / PEAK_HBM_GBS, 4)
+    out["min_cnot_frac"] = round(min(per_c.values()) / PEAK_HBM_GBS, 4)
+    if args.curves:
+        CURVES.pop("enabled")
+        with open(args.curves, "w") as f:
+            json.dump(CURVES, f)
     print(json.dumps(out), flush=True)
 
 

@@ -104,7 +104,9 @@ const char *qs_last_error(void);
 /* |index>.  Paper: Initialize("base", index).  QS_ERR_ARG if index >= 2^n. */
 int qs_init_basis(qs_state *s, uint64_t index);
 
-/* Balanced superposition H^{(x)n}|0> (all amplitudes 2^{-n/2}). */
+/* Balanced superposition H^{(x)n}|0> (all amplitudes 2^{-n/2}).  Paper:
+ * Software description, "Scope and basic use" (initialisation as the balanced
+ * superposition of all computational basis states). */
 int qs_init_uniform(qs_state *s);
 
 /* Seeded random normalised state: amplitude i = (2u-1) + i(2v-1), u and v the
@@ -155,7 +157,9 @@ int qs_collapse(qs_state *s, int q, int outcome, double *prob_dev);
 int qs_measure(qs_state *s, int q, uint64_t seed, int32_t *outcome_dev, double *prob_dev);
 
 /* Fused block: the same result as applying gates[0..count) one after the
- * other (up to rounding).  The library groups the gates into passes whose
+ * other (up to rounding).  Paper: Software description, "Scope and basic
+ * use" (custom multi-qubit operations built from the register's internals;
+ * here a list of one- and two-qubit gates applied as one operation).  The library groups the gates into passes whose
  * targets fit one on-chip tile, moving a gate ahead of earlier ones when it
  * commutes with them (disjoint qubits, or both diagonal) and that saves
  * passes, and runs each pass as one read+write of the state.  Plans
@@ -175,8 +179,9 @@ int qs_block_passes(int n, int dtype, const qs_gate *gates, int count, int *pass
 /* QAOA cost layer: amplitude k *= exp(-i gamma C(k)),
  * C(k) = sum over edges (u,v) of w_uv [k_u != k_v]  (w NULL = unit weights).
  * edges: host int32 [2*num_edges], 0 <= u, v < n, u != v; num_edges <= 256.
- * Paper: the Max-Cut Hamiltonian of the QAOA study and the "single global
- * operation per step" of the QAOA-specialised methods. */
+ * Paper: the Max-Cut Hamiltonian of the Particle Swarm / QAOA section, and
+ * the footnote of "Scope and basic use" on the QAOA-specialised methods (one
+ * diagonal operation on the whole register per layer). */
 int qs_apply_cut_phase(qs_state *s, const int32_t *edges, const double *w, int num_edges, double gamma);
 
 /* ---------------------------------------------------------------- read-outs (device outputs) */
@@ -185,28 +190,37 @@ int qs_apply_cut_phase(qs_state *s, const int32_t *edges, const double *w, int n
 int qs_prob_one(qs_state *s, int q, double *out_dev);
 
 /* <Z_q> = sum_i (-1)^{i_q} |a_i|^2 for q = 0..n-1 into out_dev[0..n)
- * (= 1 - 2 P(q = 1) for a normalised state), in one pass over the state. */
+ * (= 1 - 2 P(q = 1) for a normalised state), in one pass over the state.
+ * Paper: "Scope and basic use" (<Z> from the probability of qubit q in |1>). */
 int qs_expect_z_all(qs_state *s, double *out_dev);
 
 /* sum_i |a_i|^2 into out_dev[0]. */
 int qs_norm2(qs_state *s, double *out_dev);
 
-/* <C> = sum_k C(k) |a_k|^2 for the cut counter of qs_apply_cut_phase. */
+/* <C> = sum_k C(k) |a_k|^2 for the cut counter of qs_apply_cut_phase.
+ * Paper: Particle Swarm / QAOA section (the objective is the expectation of
+ * the Max-Cut Hamiltonian after the circuit). */
 int qs_expect_cut(qs_state *s, const int32_t *edges, const double *w, int num_edges, double *out_dev);
 
-/* sum_k d_k |a_k|^2 for a real diagonal observable d_dev (device, 2^n doubles). */
+/* sum_k d_k |a_k|^2 for a real diagonal observable d_dev (device, 2^n doubles).
+ * Paper: "Scope and basic use" (expectation values of multi-qubit
+ * observables; a diagonal one weights each basis state's probability). */
 int qs_expect_diag(qs_state *s, const double *d_dev, double *out_dev);
 
 /* <psi|P|psi> for the Pauli product with X on bits only in xmask, Z on bits
  * only in zmask and Y on bits in both; out_dev[0] = re, out_dev[1] = im
- * (zero up to rounding, as P is Hermitian).  Masks must be < 2^n. */
+ * (zero up to rounding, as P is Hermitian).  Masks must be < 2^n.
+ * Paper: "Scope and basic use" (expectation values of products of Pauli
+ * matrices). */
 int qs_expect_pauli(qs_state *s, uint64_t xmask, uint64_t zmask, double *out_dev);
 
 /* <a|b> = sum_i conj(a_i) b_i into out_dev[0..2) (re, im).  Same n and dtype;
  * the work is ordered on a's stream. */
 int qs_inner(qs_state *a, qs_state *b, double *out_dev);
 
-/* Computational-basis sampling: shot s draws u_s = 53-bit uniform of
+/* Computational-basis sampling (paper: "Scope and basic use", measurement
+ * outcomes drawn from the state-dependent distribution): shot s draws
+ * u_s = 53-bit uniform of
  * Philox4x32-10 (key = seed, counter = (s_lo, s_hi, 2, 0), words 0 and 1) and
  * returns the smallest index i with CDF(i) > u_s, the CDF summed in FP64;
  * u_s at or above the total returns the last index of nonzero probability.
@@ -243,8 +257,10 @@ int qs_qaoa_run(const qs_qaoa_desc *d, const double *angles_dev, int B, double *
 
 /* ---------------------------------------------------------------- pool of QAOA circuits */
 
-/* Many QAOA instances of uneven size in one persistent launch (paper: pool of
- * states, each circuit with its own parameters).  Circuit c = (graph g,
+/* Many QAOA instances of uneven size (paper: "Pool of multiple states", each
+ * circuit with its own parameters).  The first call captures the launch
+ * sequence (per size class, one launch per pass over a batch of circuits)
+ * into a hipGraph; later calls replay it with the angles read on the device.  Circuit c = (graph g,
  * angle set a) for g < num_graphs, a < sets_per_graph, c = g*sets_per_graph + a. */
 typedef struct qs_pool_desc {
     int num_graphs;

@@ -67,6 +67,7 @@ def lib():
             "ref_init_basis": (None, [_c_cplx_p, c_int, c_u64]),
             "ref_init_uniform": (None, [_c_cplx_p, c_int]),
             "ref_init_random": (None, [_c_cplx_p, c_int, c_u64]),
+            "ref_random_raw": (None, [c_u64, c_u64, c_u64, _c_cplx_p]),
             "ref_cut_value": (c_double, [c_u64, c_int, _c_i32_p, vp]),
             "ref_cut_max": (c_double, [c_int, c_int, _c_i32_p, vp, _c_u64_p]),
             "ref_apply_kq": (c_int, [_c_cplx_p, c_int, _c_i32_p, c_int, _c_f64_p]),
@@ -86,8 +87,9 @@ def lib():
             "ref_qaoa_grad": (c_double, [c_int, c_int, _c_i32_p, vp, c_int, _c_f64_p, _c_f64_p]),
             "ref_qaoa_grad_fd": (None, [c_int, c_int, _c_i32_p, vp, c_int, _c_f64_p, c_double, _c_f64_p]),
             "ref_depol_threshold": (c_u32, [c_double]),
-            "ref_traj_run_one": (c_int, [_c_cplx_p, c_int, vp, c_int, c_double, c_u64, c_u32, vp, c_int, c_double, c_double]),
+            "ref_traj_run_one": (c_int, [vp, c_int, vp, c_int, c_double, c_u64, c_u32, vp, c_int, c_double, c_double]),
             "ref_threads": (c_int, []),
+            "ref_set_threads": (None, [c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -129,6 +131,11 @@ def threads() -> int:
     return int(lib().ref_threads())
 
 
+def set_threads(t: int) -> None:
+    """Threads for the oracle's element-wise loops (results do not depend on it)."""
+    lib().ref_set_threads(int(t))
+
+
 # ---------------------------------------------------------------- RNG
 def philox4x32_10(ctr, key) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
@@ -157,6 +164,14 @@ def init_random(n: int, seed: int) -> np.ndarray:
     psi = np.empty(1 << n, dtype=np.complex128)
     lib().ref_init_random(psi, n, seed)
     return psi
+
+
+def random_raw(seed: int, first: int, count: int) -> np.ndarray:
+    """Amplitudes first .. first+count-1 of init_random's definition before
+    the division by the norm (indices may exceed any register held here)."""
+    out = np.empty(count, dtype=np.complex128)
+    lib().ref_random_raw(seed, first, count, out)
+    return out
 
 
 # ---------------------------------------------------------------- gates (in place)
@@ -308,11 +323,20 @@ def _inv(T):
 
 
 def traj_run_one(psi, gates, p, seed, t, log_cap=64, T1=None, T2=None):
+    """Trajectory t in place on psi; psi = None makes the draws only."""
     g = np.ascontiguousarray(gates)
     log = np.zeros(max(log_cap, 1), dtype=np.uint32)
-    nins = lib().ref_traj_run_one(psi, _nq(psi), g.ctypes.data_as(ctypes.c_void_p), len(g), p, seed, t,
+    n = 0 if psi is None else _nq(psi)
+    nins = lib().ref_traj_run_one(None if psi is None else psi.ctypes.data_as(ctypes.c_void_p), n,
+                                  g.ctypes.data_as(ctypes.c_void_p), len(g), p, seed, t,
                                   log.ctypes.data_as(ctypes.c_void_p), log_cap, _inv(T1), _inv(T2))
     return nins, log[:min(nins, log_cap)].copy()
+
+
+def traj_draws(gates, p, seed, t, log_cap=64):
+    """Insertion count and log of trajectory t (the draws of traj_run_one
+    without the state)."""
+    return traj_run_one(None, gates, p, seed, t, log_cap)
 
 
 def expect_x_all(psi) -> np.ndarray:

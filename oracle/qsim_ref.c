@@ -227,15 +227,26 @@ EXPORT void ref_init_uniform(cplx *psi, int n)
 /* Seeded random state: amplitude i = (2u-1) + i(2v-1) with u, v the 53-bit
  * uniforms of Philox(key = seed, counter = (i_lo, i_hi, TAG_INIT_RANDOM, 0))
  * words (0,1) and (2,3); then divided by the 2-norm. */
+static cplx random_amp(uint64_t seed, uint64_t i)
+{
+    uint32_t x[4];
+    philox_draw(seed, (uint32_t)i, (uint32_t)(i >> 32), TAG_INIT_RANDOM, x);
+    return (2.0 * u53(x[0], x[1]) - 1.0) + I * (2.0 * u53(x[2], x[3]) - 1.0);
+}
+
+/* The amplitudes of indices first .. first + count - 1 before the division by
+ * the norm (any index below 2^64, so registers too large to hold here can be
+ * checked at chosen indices). */
+EXPORT void ref_random_raw(uint64_t seed, uint64_t first, uint64_t count, cplx *out)
+{
+    for (uint64_t k = 0; k < count; ++k) out[k] = random_amp(seed, first + k);
+}
+
 EXPORT void ref_init_random(cplx *psi, int n, uint64_t seed)
 {
     const uint64_t N = 1ull << n;
 #pragma omp parallel for schedule(static)
-    for (uint64_t i = 0; i < N; ++i) {
-        uint32_t x[4];
-        philox_draw(seed, (uint32_t)i, (uint32_t)(i >> 32), TAG_INIT_RANDOM, x);
-        psi[i] = (2.0 * u53(x[0], x[1]) - 1.0) + I * (2.0 * u53(x[2], x[3]) - 1.0);
-    }
+    for (uint64_t i = 0; i < N; ++i) psi[i] = random_amp(seed, i);
     ldbl s = 0;
     for (uint64_t i = 0; i < N; ++i) s += (ldbl)creal(psi[i]) * creal(psi[i]) + (ldbl)cimag(psi[i]) * cimag(psi[i]);
     const double inv = (double)(1.0L / sqrtl(s));
@@ -321,8 +332,6 @@ EXPORT double ref_prob_one(const cplx *psi, int n, int q)
     return (double)s;
 }
 
-/* <Z_q> = P(0) - P(1) = 1 - 2 P(1) for a normalised state; written as the
- * plain sum of (-1)^{i_q} |a_i|^2 so it holds for any norm. */
 /* Projective measurement of qubit q with a given outcome: P = sum of |a_i|^2
  * over i with bit q = outcome; amplitudes with the other bit value become 0,
  * the rest are divided by sqrt(P) (all become 0 if P = 0).  Returns P. */
@@ -357,6 +366,8 @@ EXPORT int ref_measure(cplx *psi, int n, int q, uint64_t seed, double *prob)
     return outcome;
 }
 
+/* <Z_q> = P(0) - P(1) = 1 - 2 P(1) for a normalised state; written as the
+ * plain sum of (-1)^{i_q} |a_i|^2 so it holds for any norm. */
 EXPORT void ref_expect_z_all(const cplx *psi, int n, double *out)
 {
     const uint64_t N = 1ull << n;
@@ -672,7 +683,8 @@ static void noise_gate(cplx *psi, int n, int q, double d, double inv_T1, double 
 /* Runs trajectory `t` in place on psi (already initialised).  Writes up to
  * log_cap insertion records (slot << 2 | pauli) and returns the number of
  * insertions.  Noise gates (kind 5, qubit q0, duration u[0]) draw no
- * insertion slots. */
+ * insertion slots.  With psi == NULL only the draws are made (the insertion
+ * decisions do not depend on the state). */
 EXPORT int ref_traj_run_one(cplx *psi, int n, const ref_gate *g, int count, double p, uint64_t seed, uint32_t t,
                             uint32_t *log, int log_cap, double inv_T1, double inv_T2)
 {
@@ -684,10 +696,10 @@ EXPORT int ref_traj_run_one(cplx *psi, int n, const ref_gate *g, int count, doub
     int nins = 0;
     for (int k = 0; k < count; ++k) {
         if (g[k].kind == RG_NOISE) {
-            noise_gate(psi, n, g[k].q0, g[k].u[0], inv_T1, inv_T2, seed, t, (uint32_t)k);
+            if (psi) noise_gate(psi, n, g[k].q0, g[k].u[0], inv_T1, inv_T2, seed, t, (uint32_t)k);
             continue;
         }
-        apply_gate(psi, n, &g[k]);
+        if (psi) apply_gate(psi, n, &g[k]);
         const int touched[2] = {g[k].q0, g[k].q1};
         const int nt = (g[k].kind == RG_1Q) ? 1 : 2;
         for (int a = 0; a < nt; ++a, ++slot) {
@@ -695,7 +707,7 @@ EXPORT int ref_traj_run_one(cplx *psi, int n, const ref_gate *g, int count, doub
             philox_draw(seed, t, slot, TAG_TRAJ, x);
             if (x[0] < thr) {
                 const int pauli = 1 + (int)(((uint64_t)x[1] * 3u) >> 32);
-                ref_apply_1q(psi, n, touched[a], pauli == 1 ? X : (pauli == 2 ? Y : Z));
+                if (psi) ref_apply_1q(psi, n, touched[a], pauli == 1 ? X : (pauli == 2 ? Y : Z));
                 if (log && nins < log_cap) log[nins] = (slot << 2) | (uint32_t)pauli;
                 ++nins;
             }
@@ -708,6 +720,8 @@ EXPORT int ref_traj_run_one(cplx *psi, int n, const ref_gate *g, int count, doub
 #ifdef _OPENMP
 #include <omp.h>
 EXPORT int ref_threads(void) { return omp_get_max_threads(); }
+EXPORT void ref_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
 #else
 EXPORT int ref_threads(void) { return 1; }
+EXPORT void ref_set_threads(int t) { (void)t; }
 #endif

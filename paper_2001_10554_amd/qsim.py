@@ -136,6 +136,29 @@ def _stream_ptr(stream=None) -> int:
     return s.cuda_stream
 
 
+def _begin(stream=None):
+    """The stream a call runs on.  A stream other than the current one first
+    waits for the current stream's queued work (the call's inputs may be
+    produced there); allocate the call's buffers under it."""
+    cur = torch.cuda.current_stream()
+    if stream is None or stream == cur:
+        return cur
+    stream.wait_stream(cur)
+    return stream
+
+
+def _finish(s, outputs=()):
+    """After a call queued on stream s: the current stream waits for it, so its
+    readers see the outputs, and the outputs are marked as used there (the
+    caching allocator then keeps them until that stream's work is done)."""
+    cur = torch.cuda.current_stream()
+    if s != cur:
+        cur.wait_stream(s)
+        for t in outputs:
+            if t is not None:
+                t.record_stream(cur)
+
+
 def _u8(m) -> np.ndarray:
     m = np.asarray(m)
     if m.dtype == np.float64 and m.shape == (8,):
@@ -232,7 +255,7 @@ class State:
         """Project qubit q onto `outcome` and renormalise; returns P(outcome) (device)."""
         o = self._out(1)
         check(lib().qs_collapse(self._h, q, outcome, ctypes.c_void_p(o.data_ptr())))
-        return o
+        return self._done(o)
 
     def measure(self, q: int, seed: int):
         """Born-rule measurement of qubit q (decided on the device); returns
@@ -240,7 +263,7 @@ class State:
         out = self._out(1, torch.int32)
         pr = self._out(1)
         check(lib().qs_measure(self._h, q, seed, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(pr.data_ptr())))
-        return out, pr
+        return self._done(out, pr)
 
     # -- named gates (matrices from the gates module; every one runs the C-ABI gate kernels)
     def h(self, q): self.apply_1q(q, G.H); return self
@@ -278,50 +301,57 @@ class State:
 
     # -- read-outs (device tensors; reading them on the host synchronises)
     def _out(self, k, dtype=torch.float64):
-        return torch.empty(k, dtype=dtype, device=self.amps.device)
+        """Output buffer allocated on the state's stream; _done makes the
+        current stream wait for the call that fills it."""
+        with torch.cuda.stream(self._stream):
+            return torch.empty(k, dtype=dtype, device=self.amps.device)
+
+    def _done(self, *outs):
+        _finish(self._stream, outs)
+        return outs[0] if len(outs) == 1 else outs
 
     def prob_one(self, q: int) -> torch.Tensor:
         o = self._out(1)
         check(lib().qs_prob_one(self._h, q, ctypes.c_void_p(o.data_ptr())))
-        return o
+        return self._done(o)
 
     def expect_z_all(self) -> torch.Tensor:
         o = self._out(self.n)
         check(lib().qs_expect_z_all(self._h, ctypes.c_void_p(o.data_ptr())))
-        return o
+        return self._done(o)
 
     def norm2(self) -> torch.Tensor:
         o = self._out(1)
         check(lib().qs_norm2(self._h, ctypes.c_void_p(o.data_ptr())))
-        return o
+        return self._done(o)
 
     def expect_cut(self, edges, w=None) -> torch.Tensor:
         e = _edges(edges)
         wa = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
         o = self._out(1)
         check(lib().qs_expect_cut(self._h, _ptr(e), None if wa is None else _ptr(wa), len(e), ctypes.c_void_p(o.data_ptr())))
-        return o
+        return self._done(o)
 
     def expect_diag(self, d: torch.Tensor) -> torch.Tensor:
         assert d.dtype == torch.float64 and d.is_cuda and d.numel() == 1 << self.n
         o = self._out(1)
         check(lib().qs_expect_diag(self._h, ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(o.data_ptr())))
-        return o
+        return self._done(o)
 
     def expect_pauli(self, xmask: int, zmask: int) -> torch.Tensor:
         o = self._out(2)
         check(lib().qs_expect_pauli(self._h, xmask, zmask, ctypes.c_void_p(o.data_ptr())))
-        return o
+        return self._done(o)
 
     def inner(self, other: "State") -> torch.Tensor:
         o = self._out(2)
         check(lib().qs_inner(self._h, other._h, ctypes.c_void_p(o.data_ptr())))
-        return o
+        return self._done(o)
 
     def sample(self, shots: int, seed: int) -> torch.Tensor:
         o = self._out(max(shots, 1), torch.int64)
         check(lib().qs_sample(self._h, shots, seed, ctypes.c_void_p(o.data_ptr())))
-        return o[:shots]
+        return self._done(o)[:shots]
 
 
 # ---------------------------------------------------------------- QAOA Max-Cut
@@ -348,14 +378,19 @@ class Qaoa:
         """angles: float64 [B, 2p] or [2p] on the GPU.  Returns (E [B], grad [B, 2p] or None)."""
         a = angles.reshape(-1, 2 * self.p)
         assert a.dtype == torch.float64 and a.is_cuda
-        a = a.contiguous()
-        B = a.shape[0]
-        E = torch.empty(B, dtype=torch.float64, device=a.device)
-        G = torch.empty(B, 2 * self.p, dtype=torch.float64, device=a.device) if grad else None
+        s = _begin(stream)
+        with torch.cuda.stream(s):
+            a = a.contiguous()
+            B = a.shape[0]
+            E = torch.empty(B, dtype=torch.float64, device=a.device)
+            G = torch.empty(B, 2 * self.p, dtype=torch.float64, device=a.device) if grad else None
         ws = self.workspace(grad)
+        if s != torch.cuda.current_stream():
+            ws.record_stream(s)  # the cached workspace is also used on s
         check(lib().qs_qaoa_run(ctypes.byref(self._desc), ctypes.c_void_p(a.data_ptr()), B, ctypes.c_void_p(E.data_ptr()),
                                 ctypes.c_void_p(G.data_ptr()) if grad else None, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                                ctypes.c_void_p(_stream_ptr(stream))))
+                                ctypes.c_void_p(s.cuda_stream)))
+        _finish(s, (E, G))
         return E, G
 
 
@@ -389,11 +424,18 @@ class Pool:
     def run(self, angles: torch.Tensor | None = None, stream=None):
         """Copy `angles` [count, 2p] into the pool's device buffer (if given) and
         evaluate; returns (E, G) device tensors owned by the pool."""
+        s = _begin(stream)
+        if s != torch.cuda.current_stream():
+            for t in (self.angles, self.E, self.G, self.ws):
+                if t is not None:
+                    t.record_stream(s)
         if angles is not None:
-            self.angles.copy_(angles.reshape(self.count, 2 * self.p))
+            with torch.cuda.stream(s):
+                self.angles.copy_(angles.reshape(self.count, 2 * self.p))
         check(lib().qs_pool_run(ctypes.byref(self._desc), ctypes.c_void_p(self.angles.data_ptr()), ctypes.c_void_p(self.E.data_ptr()),
                                 ctypes.c_void_p(self.G.data_ptr()) if self.G is not None else None,
-                                ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.c_void_p(_stream_ptr(stream))))
+                                ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+        _finish(s)
         return self.E, self.G
 
 
@@ -471,30 +513,33 @@ def traj_run(n: int, gates: np.ndarray, basis_index: int, n_traj: int, p: float,
     code = QS_C128 if dtype == torch.complex128 else QS_C64
     nbytes = ctypes.c_size_t()
     check(lib().qs_traj_noise_workspace_bytes(n, code, _ptr(g), len(g), n_traj, ctypes.byref(nbytes)))
-    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
-    f64 = dict(dtype=torch.float64, device=device)
-    res = {"z": torch.empty(n_traj, n, **f64), "x": torch.empty(n_traj, n, **f64), "fid": torch.empty(n_traj, **f64),
-           "counts": torch.empty(n_traj, dtype=torch.int32, device=device)}
-    if prob_mean:
-        res["prob_mean"] = torch.empty(1 << n, **f64)
-    if log_cap:
-        res["log"] = torch.zeros(n_traj, log_cap, dtype=torch.int32, device=device)
-    if diag is not None:
-        assert diag.dtype == torch.float64 and diag.is_cuda and diag.numel() == 1 << n
-        res["diag"] = torch.empty(n_traj, **f64)
+    s = _begin(stream)
+    with torch.cuda.stream(s):  # workspace and outputs belong to the stream the kernels run on
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
+        f64 = dict(dtype=torch.float64, device=device)
+        res = {"z": torch.empty(n_traj, n, **f64), "x": torch.empty(n_traj, n, **f64), "fid": torch.empty(n_traj, **f64),
+               "counts": torch.empty(n_traj, dtype=torch.int32, device=device)}
+        if prob_mean:
+            res["prob_mean"] = torch.empty(1 << n, **f64)
+        if log_cap:
+            res["log"] = torch.zeros(n_traj, log_cap, dtype=torch.int32, device=device)
+        if diag is not None:
+            assert diag.dtype == torch.float64 and diag.is_cuda and diag.numel() == 1 << n
+            res["diag"] = torch.empty(n_traj, **f64)
     out = TrajOut(res["z"].data_ptr(), res["x"].data_ptr(), res["fid"].data_ptr(),
                   res["prob_mean"].data_ptr() if prob_mean else None, res["counts"].data_ptr(),
                   res["log"].data_ptr() if log_cap else None, log_cap,
                   diag.data_ptr() if diag is not None else None, res["diag"].data_ptr() if diag is not None else None)
     if math.isinf(T1) and math.isinf(T2) and not np.any(g["kind"] == W.G_NOISE):
         check(lib().qs_traj_run(n, code, _ptr(g), len(g), basis_index, n_traj, p, seed, ctypes.byref(out),
-                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream_ptr(stream))))
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(s.cuda_stream)))
     else:
         nz = Noise(p, T1, T2)
         check(lib().qs_traj_run_noise(n, code, _ptr(g), len(g), basis_index, n_traj, ctypes.byref(nz), seed, ctypes.byref(out),
-                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream_ptr(stream))))
-    # ws is released to torch's caching allocator in stream order: later work
-    # on this stream cannot overwrite it before the kernels above have run.
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+    # ws was allocated on s and goes back to the caching allocator in s's
+    # order, so later work cannot overwrite it before the kernels above ran.
+    _finish(s, tuple(res.values()))
     return res
 
 

@@ -18,3 +18,17 @@ def _oracle_built():
     import oracle
     oracle.build()
     yield
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Observed parity errors against their bounds, one line per check."""
+    try:
+        from gpu_util import RECORDS
+    except ImportError:
+        return
+    if not RECORDS:
+        return
+    tr = terminalreporter
+    tr.section("parity: observed error / bound")
+    for test, what, obs, bound in RECORDS:
+        tr.write_line(f"{obs:10.3e} / {bound:9.3e}  {test}  {what}")

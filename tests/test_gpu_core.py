@@ -4,7 +4,9 @@ sampling through the C-ABI, element by element against the CPU oracle.
 Sizes span one tile (n <= 12), several tiles with a ragged structure (odd n,
 n = 13..20) and the small degenerate registers (n = 1, 2).  Tolerances:
 complex128 amplitudes 1e-12 abs, complex64 2e-5 abs (against the complex128
-oracle), FP64 read-outs 1e-12 * max(1, |value|).
+oracle), FP64 read-outs 1e-12 * max(1, |value|); complex64 states also meet
+the normwise rounding bound of their gate count (the helpers in gpu_util state
+and print every bound).
 """
 import math
 
@@ -13,7 +15,7 @@ import pytest
 
 import oracle
 from paper_2001_10554_amd import workloads as W
-from gpu_util import TOL, max_err, require_gpu, to_host, torch_dtype
+from gpu_util import check_amps, check_val, max_err, record, require_gpu, to_host, torch_dtype
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +40,9 @@ def test_init_parity(n, dt):
     s.init_basis((1 << n) - 1)
     assert max_err(to_host(s), oracle.init_basis(n, (1 << n) - 1)) == 0
     s.init_uniform()
-    assert max_err(to_host(s), oracle.init_uniform(n)) < TOL[dt]
+    check_amps(to_host(s), oracle.init_uniform(n), dt, "uniform", gates=1)
     s.init_random(1234)
-    assert max_err(to_host(s), oracle.init_random(n, 1234)) < TOL[dt]
+    check_amps(to_host(s), oracle.init_random(n, 1234), dt, "random", gates=1)
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -52,7 +54,7 @@ def test_1q_every_target(n, dt):
     for q in range(n):
         s.apply_1q(q, mats[q])
         oracle.apply_1q(ref, q, mats[q])
-        assert max_err(to_host(s), ref) < TOL[dt], f"q={q}"
+        check_amps(to_host(s), ref, dt, f"after q={q}", gates=q + 2)
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -68,7 +70,7 @@ def test_c1q_pairs(n, dt):
         U = W.haar_2x2(g)
         s.apply_c1q(c, t, U)
         oracle.apply_c1q(ref, c, t, U)
-    assert max_err(to_host(s), ref) < TOL[dt] * 4
+    check_amps(to_host(s), ref, dt, f"{len(pairs)} controlled gates", gates=len(pairs) + 1)
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -85,7 +87,7 @@ def test_diag2_swap(dt):
         oracle.apply_diag2(ref, a, b, d)
         s.apply_swap(a, b)
         oracle.apply_swap(ref, a, b)
-    assert max_err(to_host(s), ref) < TOL[dt] * 4
+    check_amps(to_host(s), ref, dt, "20 diagonal + 20 swap gates", gates=41)
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -96,11 +98,11 @@ def test_block_matches_sequential(n, count, seed, dt):
     ref = oracle.init_random(n, seed)
     s.apply_block(gates)
     oracle.apply_gates(ref, gates)
-    assert max_err(to_host(s), ref) < TOL[dt] * 4
+    check_amps(to_host(s), ref, dt, "first call", gates=count + 1)
     # Second call hits the cached plan.
     s.apply_block(gates)
     oracle.apply_gates(ref, gates)
-    assert max_err(to_host(s), ref) < TOL[dt] * 8
+    check_amps(to_host(s), ref, dt, "cached plan", gates=2 * count + 1)
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -113,7 +115,7 @@ def test_block_reordered_passes(dt):
     ref = oracle.init_random(n, 9)
     s.apply_block(gates)
     oracle.apply_gates(ref, gates)
-    assert max_err(to_host(s), ref) < TOL[dt] * 4
+    check_amps(to_host(s), ref, dt, "reordered block", gates=len(gates) + 1)
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -131,7 +133,7 @@ def test_fused_sweep_26q(dt):
     ref = oracle.init_random(n, 4)
     s.apply_block(gates)
     oracle.apply_gates(ref, gates)
-    assert max_err(to_host(s), ref) < TOL[dt] * 4
+    check_amps(to_host(s), ref, dt, "fused 26q sweep", gates=len(gates) + 1)
 
 
 def test_brick_circuit_12q():
@@ -143,8 +145,8 @@ def test_brick_circuit_12q():
     s.apply_block(gates)
     ref = oracle.init_basis(n, 0)
     oracle.apply_gates(ref, gates)
-    assert max_err(to_host(s), ref) < 1e-12
-    assert max_err(s.expect_z_all().cpu().numpy(), oracle.expect_z_all(ref)) < 1e-12
+    check_amps(to_host(s), ref, "c128", "brick amplitudes")
+    check_val(s.expect_z_all().cpu().numpy(), oracle.expect_z_all(ref), "c128", "<Z_i>")
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -156,29 +158,29 @@ def test_readouts(n, dt):
     s.apply_1q(0, U)
     ref = oracle.init_random(n, 11)
     oracle.apply_1q(ref, 0, U)
-    tol = 1e-12 if dt == "c128" else 2e-5
     z = s.expect_z_all().cpu().numpy()
-    assert max_err(z, oracle.expect_z_all(ref)) < tol
-    assert abs(s.norm2().item() - oracle.norm2(ref)) < tol
+    check_val(z, oracle.expect_z_all(ref), dt, "<Z_q> all", gates=2)
+    check_val(s.norm2().item(), oracle.norm2(ref), dt, "norm2", gates=2)
     for q in {0, n // 2, n - 1}:
-        assert abs(s.prob_one(q).item() - oracle.prob_one(ref, q)) < tol
+        check_val(s.prob_one(q).item(), oracle.prob_one(ref, q), dt, f"P(q{q}=1)", gates=2)
     g = np.random.default_rng(n)
     for _ in range(4):
         x, z_ = int(g.integers(1 << n)), int(g.integers(1 << n))
         got = s.expect_pauli(x, z_).cpu().numpy()
         want = oracle.expect_pauli(ref, x, z_)
-        assert abs(got[0] - want.real) < tol and abs(got[1] - want.imag) < tol
+        check_val(got, [want.real, want.imag], dt, f"Pauli x={x:#x} z={z_:#x}", gates=2)
     d = torch.tensor(g.standard_normal(1 << n), device="cuda")
-    assert abs(s.expect_diag(d).item() - oracle.expect_diag(ref, d.cpu().numpy())) < tol * max(1, n)
+    dh = d.cpu().numpy()
+    check_val(s.expect_diag(d).item(), oracle.expect_diag(ref, dh), dt, "sum d|a|^2", opnorm=float(np.max(np.abs(dh))), gates=2)
     if n >= 4:
         e = W.random_regular_graph(n if n % 2 == 0 else n - 1, 3, seed=n)
-        assert abs(s.expect_cut(e).item() - oracle.expect_cut(ref, e)) < tol * len(e)
+        check_val(s.expect_cut(e).item(), oracle.expect_cut(ref, e), dt, "<C>", opnorm=len(e), gates=2)
         w = g.uniform(0.5, 2, len(e))
-        assert abs(s.expect_cut(e, w).item() - oracle.expect_cut(ref, e, w)) < tol * len(e) * 2
+        check_val(s.expect_cut(e, w).item(), oracle.expect_cut(ref, e, w), dt, "<C_w>", opnorm=float(w.sum()), gates=2)
     t = _state(n, dt).init_random(12)
     got = s.inner(t).cpu().numpy()
     want = oracle.inner(ref, oracle.init_random(n, 12))
-    assert abs(got[0] - want.real) < tol and abs(got[1] - want.imag) < tol
+    check_val(got, [want.real, want.imag], dt, "<a|b>", gates=2)
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -189,11 +191,25 @@ def test_cut_phase(n, dt):
     ref = oracle.init_random(n, 2)
     s.apply_cut_phase(e, 0.731)
     oracle.apply_cut_phase(ref, e, 0.731)
-    assert max_err(to_host(s), ref) < TOL[dt]
+    check_amps(to_host(s), ref, dt, "unit weights", gates=2)
     w = np.linspace(0.3, 1.7, len(e))
     s.apply_cut_phase(e, -1.2, w)
     oracle.apply_cut_phase(ref, e, -1.2, w)
-    assert max_err(to_host(s), ref) < TOL[dt] * 2
+    check_amps(to_host(s), ref, dt, "weighted", gates=3)
+
+
+def _sample_check(s, psi_host, shots, seed):
+    """Draws of qs_sample against the oracle's sampling of the same amplitudes
+    (both CDFs in FP64).  Exact equality, except that a draw within 1e-12 of a
+    bin edge of the oracle's sequential CDF may land on the neighbouring index
+    (the GPU sums chunks in a different order); their number is reported."""
+    got = s.sample(shots, seed=seed).cpu().numpy().astype(np.uint64)
+    want, margin = oracle.sample(psi_host, shots, seed=seed)
+    close = margin < 1e-12
+    far_mismatch = int(np.count_nonzero(got[~close] != want[~close]))
+    record(f"sample n={s.n} shots={shots}: mismatches away from bin edges ({int(close.sum())} draws near an edge)", far_mismatch, 0)
+    step = np.abs(got[close].astype(np.int64) - want[close].astype(np.int64))
+    record("sample: index distance of near-edge draws", int(step.max()) if step.size else 0, 1)
 
 
 @pytest.mark.parametrize("n", [1, 6, 12, 14, 19])
@@ -203,13 +219,31 @@ def test_sample_parity(n):
     s.apply_1q(n - 1, U)
     ref = oracle.init_random(n, 5)
     oracle.apply_1q(ref, n - 1, U)
-    shots = 5000
-    got = s.sample(shots, seed=77).cpu().numpy().astype(np.uint64)
-    want, margin = oracle.sample(ref, shots, seed=77)
-    close = margin < 1e-12
-    assert np.array_equal(got[~close], want[~close])
-    # Decisions within rounding of a bin edge may land on the neighbour.
-    assert np.all(np.abs(got[close].astype(np.int64) - want[close].astype(np.int64)) <= 1)
+    _sample_check(s, ref, 5000, 77)
+
+
+@pytest.mark.parametrize("n,dt", [(21, "c128"), (21, "c64"), (24, "c128"), (24, "c64"), (30, "c128"), (30, "c64"), (31, "c64")])
+def test_sample_parity_large(n, dt):
+    """Registers whose chunk scan gives each thread several chunks (n >= 21)
+    and whose chunks widen beyond 2^12 amplitudes (n >= 31).  The oracle
+    samples the same amplitudes the kernel sampled (complex64 values are exact
+    in complex128), with a gate on the top qubit so the distribution is not
+    the initial one."""
+    import torch
+    nbytes = (1 << n) * (16 if dt == "c128" else 8)
+    if n >= 30:
+        free, _ = torch.cuda.mem_get_info()
+        if free < nbytes + (4 << 30):
+            pytest.skip(f"needs {nbytes >> 30} GiB of free device memory")
+    U = W.haar_list(n, 1)[0]
+    s = _state(n, dt).init_random(n)
+    s.apply_1q(n - 1, U)
+    host = s.amps.cpu().numpy()
+    if dt == "c64":
+        host = host.astype(np.complex128)
+    _sample_check(s, host, 1 << 16, 1000 + n)
+    del s, host
+    torch.cuda.empty_cache()
 
 
 def test_sample_degenerate():

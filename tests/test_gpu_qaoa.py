@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2001_10554_amd import workloads as W
-from gpu_util import require_gpu
+from gpu_util import record, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -42,10 +42,10 @@ def test_energy_and_gradient_vs_oracle(n, p):
     prob = _problem(n, edges, p)
     E, G = prob.run(torch.tensor(theta, device="cuda"))
     e_ref, g_ref = oracle.qaoa_grad(n, edges, p, theta)
-    assert abs(E.item() - e_ref) < E_TOL
-    assert np.max(np.abs(G.cpu().numpy()[0] - g_ref)) < GRAD_TOL
+    record("E", abs(E.item() - e_ref), E_TOL)
+    record("gradient", float(np.max(np.abs(G.cpu().numpy()[0] - g_ref))), GRAD_TOL)
     E2, _ = prob.run(torch.tensor(theta, device="cuda"), grad=False)
-    assert abs(E2.item() - e_ref) < E_TOL
+    record("E", abs(E2.item() - e_ref), E_TOL)
 
 
 @pytest.mark.parametrize("n", [10, 16, 20])
@@ -59,8 +59,8 @@ def test_weighted_graph(n):
     theta = W.qaoa_angles(p, seed=6)
     E, G = _problem(n, edges, p, w).run(torch.tensor(theta, device="cuda"))
     e_ref, g_ref = oracle.qaoa_grad(n, edges, p, theta, w=w)
-    assert abs(E.item() - e_ref) < E_TOL
-    assert np.max(np.abs(G.cpu().numpy()[0] - g_ref)) < GRAD_TOL
+    record("E", abs(E.item() - e_ref), E_TOL)
+    record("gradient", float(np.max(np.abs(G.cpu().numpy()[0] - g_ref))), GRAD_TOL)
 
 
 def test_batch_of_angle_sets():
@@ -71,8 +71,8 @@ def test_batch_of_angle_sets():
     E, G = _problem(n, edges, p).run(torch.tensor(thetas, device="cuda"))
     for b in range(B):
         e_ref, g_ref = oracle.qaoa_grad(n, edges, p, thetas[b])
-        assert abs(E[b].item() - e_ref) < E_TOL
-        assert np.max(np.abs(G[b].cpu().numpy() - g_ref)) < GRAD_TOL
+        record("E", abs(E[b].item() - e_ref), E_TOL)
+        record("gradient", float(np.max(np.abs(G[b].cpu().numpy() - g_ref))), GRAD_TOL)
 
 
 @pytest.mark.parametrize("n", [6, 12, 15])
@@ -97,7 +97,7 @@ def test_autograd_function():
     E = QAOAEnergy.apply(th, prob)
     (3.0 * E).backward()
     _, g_ref = oracle.qaoa_grad(n, edges, p, th.detach().cpu().numpy())
-    assert np.max(np.abs(th.grad.cpu().numpy() - 3.0 * g_ref)) < 3 * GRAD_TOL
+    record("autograd gradient / 3", float(np.max(np.abs(th.grad.cpu().numpy() / 3.0 - g_ref))), GRAD_TOL)
 
 
 def test_config3_24q_p8_vs_oracle_and_fd():
@@ -112,8 +112,8 @@ def test_config3_24q_p8_vs_oracle_and_fd():
     E, G = prob.run(torch.tensor(theta, device="cuda"))
     g = G.cpu().numpy()[0]
     e_ref, g_ref = oracle.qaoa_grad(n, edges, p, theta)
-    assert abs(E.item() - e_ref) < E_TOL
-    assert np.max(np.abs(g - g_ref)) < GRAD_TOL
+    record("E", abs(E.item() - e_ref), E_TOL)
+    record("gradient", float(np.max(np.abs(g - g_ref))), GRAD_TOL)
     shifts = np.repeat(theta[None, :], 4 * p, axis=0)
     for k in range(2 * p):
         shifts[2 * k, k] += h
@@ -123,7 +123,7 @@ def test_config3_24q_p8_vs_oracle_and_fd():
     fd = (Es[0::2] - Es[1::2]) / (2 * h)
     # E ~ 36 in magnitude: rounding of each forward ~ 1e-13 relative -> eps_E/h ~ 4e-6 / ... bound:
     tau = 10 * (abs(E.item()) * 1e-14 / h + h * h * 1e3)
-    assert np.max(np.abs(fd - g)) < tau
+    record("|g_adjoint - g_FD| (h = 1e-6)", float(np.max(np.abs(fd - g))), tau)
 
 
 def test_fd_error_vs_step_has_truncation_and_rounding_branches():
@@ -195,5 +195,5 @@ def test_merge_policies_match_oracle(mode):
         edges = W.random_regular_graph(n, 3, seed=n + p)
         theta = W.qaoa_angles(p, seed=n)
         e_ref, g_ref = oracle.qaoa_grad(n, edges, p, theta)
-        assert abs(e - e_ref) < E_TOL, (mode, n, p)
-        assert np.max(np.abs(np.array(g) - g_ref)) < GRAD_TOL, (mode, n, p)
+        record(f"E ({mode}, n={n}, p={p})", abs(e - e_ref), E_TOL)
+        record(f"gradient ({mode}, n={n}, p={p})", float(np.max(np.abs(np.array(g) - g_ref))), GRAD_TOL)

@@ -157,6 +157,57 @@ def test_init_random_normalised_and_seeded():
     assert abs(scale.imag) < 1e-12 and scale.real > 0
 
 
+def _philox_np(c0, c1, c2, c3, k0, k1):
+    """Philox4x32-10 (Salmon et al., SC'11) on numpy uint64 arrays of 32-bit
+    words, written here independently of the oracle's C; pinned by the
+    published known-answer vectors below."""
+    m32 = np.uint64(0xFFFFFFFF)
+    c = [np.asarray(x, dtype=np.uint64) & m32 for x in (c0, c1, c2, c3)]
+    k = [np.uint64(k0), np.uint64(k1)]
+    for r in range(10):
+        if r:
+            k = [(k[0] + np.uint64(0x9E3779B9)) & m32, (k[1] + np.uint64(0xBB67AE85)) & m32]
+        p0 = np.uint64(0xD2511F53) * c[0]
+        p1 = np.uint64(0xCD9E8D57) * c[2]
+        c = [((p1 >> np.uint64(32)) ^ c[1] ^ k[0]) & m32, p1 & m32, ((p0 >> np.uint64(32)) ^ c[3] ^ k[1]) & m32, p0 & m32]
+    return c
+
+
+def test_numpy_philox_matches_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if l.strip() and not l.startswith("#")]
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = _philox_np(*[np.array([x]) for x in v[0:4]], v[4], v[5])
+        assert [int(o[0]) for o in out] == v[6:10]
+
+
+@pytest.mark.parametrize("first", [0, (1 << 32) - 8, 1 << 32, (1 << 33) + 12345, (1 << 34) - 16, (1 << 35) + 7])
+def test_init_random_counter_layout_at_any_index(first):
+    """init_random's definition at indices up to 2^35 (registers the CPU
+    cannot hold): amplitude i before normalisation is (2u - 1) + i(2v - 1)
+    with u, v the 53-bit uniforms of Philox(key = seed, counter = (i mod
+    2^32, i div 2^32, 1, 0)), words (0, 1) and (2, 3)."""
+    seed = 0x1234_5678_9ABC
+    idx = np.arange(first, first + 16, dtype=np.uint64)
+    x = _philox_np(idx & np.uint64(0xFFFFFFFF), idx >> np.uint64(32), np.full(16, 1), np.zeros(16),
+                   seed & 0xFFFFFFFF, seed >> 32)
+    u = ((x[1] << np.uint64(32)) | x[0]) >> np.uint64(11)
+    v = ((x[3] << np.uint64(32)) | x[2]) >> np.uint64(11)
+    want = (2 * (u.astype(np.float64) * 2.0 ** -53) - 1) + 1j * (2 * (v.astype(np.float64) * 2.0 ** -53) - 1)
+    got = oracle.random_raw(seed, first, 16)
+    assert np.array_equal(got, want)
+    # the high counter word matters: index i and i + 2^32 differ
+    if first >= 1 << 32:
+        assert not np.array_equal(got, oracle.random_raw(seed, first - (1 << 32), 16))
+
+
+def test_init_random_is_raw_over_norm():
+    n, seed = 10, 77
+    raw = oracle.random_raw(seed, 0, 1 << n)
+    psi = oracle.init_random(n, seed)
+    assert np.max(np.abs(psi - raw / np.linalg.norm(raw))) < 1e-16
+
+
 # ------------------------------------------------------------------ paper's worked examples
 def test_paper_basic_use_listing():
     rows = {}
@@ -428,3 +479,27 @@ def test_trajectory_means_converge_to_density_matrix():
     kinds = np.concatenate([l & 3 for l in ens["logs"] if len(l)])
     frac = np.bincount(kinds, minlength=4)[1:] / len(kinds)
     assert np.all(np.abs(frac - 1 / 3) < 0.03)
+
+
+def test_trajectory_draws_only_mode_and_decision_rule():
+    """The draws-only mode gives the full run's insertion counts and logs, and
+    both follow the decision rule computed here from an independent Philox:
+    slot s of trajectory t inserts iff x0 < floor(p 2^32), Pauli 1 + floor(3 x1 / 2^32)."""
+    n, p, seed = 5, 0.02, 0xABCDEF0123
+    gates = W.qft_circuit(n)
+    slots = sum(1 if int(gr["kind"]) == W.G_1Q else 2 for gr in gates)
+    thr = np.uint64(math.floor(p * 2 ** 32))
+    assert oracle.depol_threshold(p) == int(thr)
+    s = np.arange(slots, dtype=np.uint64)
+    total = 0
+    for t in range(300):
+        psi = oracle.init_basis(n, 3)
+        full = oracle.traj_run_one(psi, gates, p, seed, t, log_cap=32)
+        only = oracle.traj_draws(gates, p, seed, t, log_cap=32)
+        assert full[0] == only[0] and np.array_equal(full[1], only[1])
+        x = _philox_np(np.full(slots, t), s, np.full(slots, 3), np.zeros(slots), seed & 0xFFFFFFFF, seed >> 32)
+        hit = x[0] < thr
+        want = (s[hit] << np.uint64(2)) | (np.uint64(1) + ((x[1][hit] * np.uint64(3)) >> np.uint64(32)))
+        assert only[0] == int(hit.sum()) and np.array_equal(only[1], want.astype(np.uint32))
+        total += only[0]
+    assert total > 50

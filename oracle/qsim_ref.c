@@ -477,22 +477,24 @@ EXPORT void ref_inner(const cplx *a, const cplx *b, int n, double *out /*re,im*/
 
 /* Sampling: shot s draws u_s = 53-bit uniform of Philox(seed, (s_lo, s_hi,
  * TAG_SAMPLE, 0)) words 0,1 and returns the smallest i with CDF(i) > u_s,
- * CDF(i) = sum_{j<=i} |a_j|^2 accumulated in FP64 in index order.  When u_s
- * is not below CDF(N-1) the last index of nonzero probability is returned.
- * Also reports, per shot, the distance from u_s to the nearest CDF boundary
- * (so callers can tell which decisions sit within rounding of a boundary). */
+ * CDF(i) = sum_{j<=i} |a_j|^2 summed in index order in long double and
+ * rounded to FP64 (so the oracle's CDF is the exact prefix sum to well below
+ * 1e-15 also over 2^31 terms).  When u_s is not below CDF(N-1) the last index
+ * of nonzero probability is returned.  Also reports, per shot, the distance
+ * from u_s to the nearest CDF boundary (so callers can tell which decisions
+ * sit within rounding of a boundary). */
 EXPORT int ref_sample(const cplx *psi, int n, int64_t shots, uint64_t seed, uint64_t *out, double *margin)
 {
     const uint64_t N = 1ull << n;
     double *cdf = (double *)malloc(N * sizeof(double));
     if (!cdf) return -1;
-    double acc = 0.0;
+    ldbl acc = 0.0L;
     uint64_t last_nz = 0;
     for (uint64_t i = 0; i < N; ++i) {
-        const double p = creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]);
+        const ldbl p = (ldbl)creal(psi[i]) * creal(psi[i]) + (ldbl)cimag(psi[i]) * cimag(psi[i]);
         acc += p;
-        cdf[i] = acc;
-        if (p > 0.0) last_nz = i;
+        cdf[i] = (double)acc;
+        if (p > 0.0L) last_nz = i;
     }
     for (int64_t s = 0; s < shots; ++s) {
         uint32_t x[4];

@@ -199,10 +199,13 @@ def test_cut_phase(n, dt):
 
 
 def _sample_check(s, psi_host, shots, seed):
-    """Draws of qs_sample against the oracle's sampling of the same amplitudes
-    (both CDFs in FP64).  Exact equality, except that a draw within 1e-12 of a
-    bin edge of the oracle's sequential CDF may land on the neighbouring index
-    (the GPU sums chunks in a different order); their number is reported."""
+    """Draws of qs_sample against the oracle's sampling of the same amplitudes.
+    The oracle's CDF is the exact prefix sum rounded to FP64 (long-double
+    accumulation); the kernel's FP64 CDF (chunk sums, a two-level prefix over
+    at most 2^18 chunks, a wavefront scan inside the chunk) carries at most
+    about 1.5e3 roundings of 2^-53 on the way to any index, i.e. < 2e-13.  So
+    draws must agree exactly, except that one within 1e-12 of an exact bin edge
+    may land on the neighbouring index; their number is reported."""
     got = s.sample(shots, seed=seed).cpu().numpy().astype(np.uint64)
     want, margin = oracle.sample(psi_host, shots, seed=seed)
     close = margin < 1e-12

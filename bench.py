@@ -436,7 +436,8 @@ def readout_bench(n=30):
     rate("init_random", lambda: s.init_random(1), 4 * S)                # write, read for the norm, read + write to scale
     rate("cut_phase", lambda: s.apply_cut_phase(edges, 0.3), 2 * S)
     rate("diag2_cz", lambda: s.apply_diag2(3, 17, cz), 2 * S // 4)      # only the |11> quarter moves
-    rate("swap", lambda: s.apply_swap(2, 25), 2 * S // 2)               # the (1,0)/(0,1) halves
+    rate("swap", lambda: s.apply_swap(5, 25), 2 * S // 2)               # the (1,0)/(0,1) quarters, whole lines
+    rate("swap_in_line", lambda: s.apply_swap(2, 25), 2 * S)            # qubit 2 inside the 128-byte line: every line moves
     rate("expect_z_all", lambda: s.expect_z_all(), S)
     rate("norm2", lambda: s.norm2(), S)
     rate("prob_one", lambda: s.prob_one(7), S)

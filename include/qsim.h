@@ -282,9 +282,19 @@ int qs_pool_workspace_bytes(const qs_pool_desc *d, size_t *bytes);
 int qs_pool_circuit_bytes(const qs_pool_desc *d, int with_grad, size_t *bytes);
 
 /* angles_dev: device [circuits * 2p]; E_dev: device [circuits];
- * grad_dev: device [circuits * 2p] or NULL.  Complex128. */
+ * grad_dev: device [circuits * 2p] or NULL.  Complex128.  The library keeps
+ * the plan of each (descriptor, buffers) combination it has run: the captured
+ * graph and the device tables of the passes, at most 32 plans, the least
+ * recently used released first. */
 int qs_pool_run(const qs_pool_desc *d, const double *angles_dev, double *E_dev, double *grad_dev,
                 void *ws, size_t ws_bytes, void *stream);
+
+/* Release the plan qs_pool_run keeps for exactly these arguments (its
+ * captured graph and device tables; the caller's buffers are untouched).  Call
+ * it before freeing buffers a plan was captured with.  Synchronises the
+ * device.  QS_OK also when no such plan exists. */
+int qs_pool_release(const qs_pool_desc *d, const double *angles_dev, double *E_dev, double *grad_dev, void *ws,
+                    size_t ws_bytes);
 
 /* ---------------------------------------------------------------- Max-Cut optimum and particle swarm */
 

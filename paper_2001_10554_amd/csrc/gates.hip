@@ -215,8 +215,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ ps
 // pairs / amplitudes (pair / lane kernel); QSIM_1Q_LCHUNK the lane kernel's
 // block remap; QSIM_C1Q_SPREAD the controlled kernel's spread.
 struct Shape1q {
-    int ppt, nt, lane, dlog, ldlog, cdlog;
-    u32 chunk, lchunk;
+    int ppt, nt, lane, dlog, ldlog, cdlog, cppt;
+    u32 chunk, lchunk, cchunk, dchunk;
 };
 
 static Shape1q shape_1q() {
@@ -234,6 +234,9 @@ static Shape1q shape_1q() {
         v.ldlog = (int)env("QSIM_1Q_LSPREAD", 11);
         v.cdlog = (int)env("QSIM_C1Q_SPREAD", 8);  // controlled gates: no gain from spreading (measured)
         v.lchunk = (u32)env("QSIM_1Q_LCHUNK", 0);
+        v.cppt = (int)env("QSIM_C1Q_PPT", 2);
+        v.cchunk = (u32)env("QSIM_C1Q_CHUNK", 0x7fffffff);  // 0x7fffffff: per-control schedule
+        v.dchunk = (u32)env("QSIM_QUAD_CHUNK", 0x7fffffff);  // diagonal / SWAP block remap
         return v;
     }();
     return sh;
@@ -249,6 +252,13 @@ static u32 chunk_for_target(int q) {
     if (q <= 16) return 128;
     return 16u << ((q - 20) & 3);
 }
+
+// Controlled gates with the control outside the 128-byte line, diagonal and
+// SWAP gates (quads of two qubits): each XCD takes one contiguous eighth of
+// the grid.  Measured on a 32-qubit complex128 register against per-target
+// XCD runs of 16..256 blocks and hardware order: 6.3-6.6 TB/s for CNOT(c, c+1)
+// at every c >= 3 (runs: 5.1-6.2), CZ 6.5 (6.0), SWAP 6.4 (5.6).
+static u32 chunk_for_control(int, int) { return ~0u; }
 
 template <typename R> static int launch_1q_t(qs_state *s, int q, const double *u) {
     const u64 N = 1ull << s->n, npairs = N >> 1;
@@ -344,9 +354,14 @@ template <typename R> static int launch_c1q_t(qs_state *s, int c, int t, const d
     } else {
         const Shape1q v = shape_1q();
         int dlog = v.cdlog >= 8 && v.cdlog < 40 ? v.cdlog : 8;
-        if (nquads % (2ull << dlog)) dlog = 8;
-        for_pieces(grid_for(nquads, kBlock * 2), [&](unsigned g, u64 b0) {
-            hipLaunchKernelGGL((k_apply_c1q<R, 2>), dim3(g), dim3(kBlock), 0, st, psi, nquads, c, t, m, chunk_for_target(t), dlog, b0);
+        const int ppt = v.cppt == 4 ? 4 : 2;
+        if (nquads % ((u64)ppt << dlog)) dlog = 8;
+        const u32 chunk = v.cchunk == 0x7fffffffu ? chunk_for_control(c, t) : v.cchunk;
+        for_pieces(grid_for(nquads, kBlock * ppt), [&](unsigned g, u64 b0) {
+            if (ppt == 4)
+                hipLaunchKernelGGL((k_apply_c1q<R, 4>), dim3(g), dim3(kBlock), 0, st, psi, nquads, c, t, m, chunk, dlog, b0);
+            else
+                hipLaunchKernelGGL((k_apply_c1q<R, 2>), dim3(g), dim3(kBlock), 0, st, psi, nquads, c, t, m, chunk, dlog, b0);
         });
     }
     QS_LAUNCH_CHECK("apply_c1q");
@@ -366,32 +381,62 @@ template <typename R> struct Diag4 {
     R d[8];
 };
 
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_apply_diag2(cx<R> *__restrict__ psi, u64 nquads, int q0, int q1, Diag4<R> d, int touch, u64 blk0) {
+// Two quads per thread, loads before stores; blocks remapped to XCD runs as
+// for the controlled gate.
+template <typename R, int PPT>
+__global__ __launch_bounds__(kBlock) void k_apply_diag2(cx<R> *__restrict__ psi, u64 nquads, int q0, int q1, Diag4<R> d, int touch, u32 chunk,
+                                                        u64 blk0) {
     const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
-    const u64 k = (blk0 + blockIdx.x) * kBlock + threadIdx.x;
-    if (k >= nquads) return;
-    const u64 base = insert0(insert0(k, lo), hi);
+    const u64 lb = logical_block(chunk, blk0);
+    const u64 first = lb * (kBlock * PPT) + threadIdx.x;
+    cx<R> v[PPT][4];
+    u64 base[PPT];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        if (!((touch >> e) & 1)) continue;
-        const u64 i = base | ((u64)(e & 1) << q0) | ((u64)(e >> 1) << q1);
-        cx<R> f;
-        f.x = d.d[2 * e];
-        f.y = d.d[2 * e + 1];
-        psi[i] = cmul<R>(psi[i], f);
+    for (int j = 0; j < PPT; ++j) {
+        const u64 k = first + (u64)j * kBlock;
+        base[j] = insert0(insert0(k, lo), hi);
+        if (k < nquads) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if ((touch >> e) & 1) v[j][e] = ld<true>(psi + (base[j] | ((u64)(e & 1) << q0) | ((u64)(e >> 1) << q1)));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (first + (u64)j * kBlock >= nquads) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (!((touch >> e) & 1)) continue;
+            cx<R> f;
+            f.x = d.d[2 * e];
+            f.y = d.d[2 * e + 1];
+            st<true>(psi + (base[j] | ((u64)(e & 1) << q0) | ((u64)(e >> 1) << q1)), cmul<R>(v[j][e], f));
+        }
     }
 }
 
-template <typename R> __global__ __launch_bounds__(kBlock) void k_apply_swap(cx<R> *__restrict__ psi, u64 nquads, int a, int b, u64 blk0) {
+template <typename R, int PPT>
+__global__ __launch_bounds__(kBlock) void k_apply_swap(cx<R> *__restrict__ psi, u64 nquads, int a, int b, u32 chunk, u64 blk0) {
     const int lo = a < b ? a : b, hi = a < b ? b : a;
-    const u64 k = (blk0 + blockIdx.x) * kBlock + threadIdx.x;
-    if (k >= nquads) return;
-    const u64 base = insert0(insert0(k, lo), hi);
-    const u64 i = base | (1ull << a), j = base | (1ull << b);
-    const cx<R> x = psi[i], y = psi[j];
-    psi[i] = y;
-    psi[j] = x;
+    const u64 lb = logical_block(chunk, blk0);
+    const u64 first = lb * (kBlock * PPT) + threadIdx.x;
+    cx<R> x[PPT], y[PPT];
+    u64 i[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const u64 k = first + (u64)j * kBlock;
+        i[j] = insert0(insert0(k, lo), hi);
+        if (k < nquads) {
+            x[j] = ld<true>(psi + (i[j] | (1ull << a)));
+            y[j] = ld<true>(psi + (i[j] | (1ull << b)));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        if (first + (u64)j * kBlock >= nquads) continue;
+        st<true>(psi + (i[j] | (1ull << a)), y[j]);
+        st<true>(psi + (i[j] | (1ull << b)), x[j]);
+    }
 }
 
 template <typename R> static int launch_diag2_t(qs_state *s, int q0, int q1, const double *d) {
@@ -404,8 +449,10 @@ template <typename R> static int launch_diag2_t(qs_state *s, int q0, int q1, con
         if (!(d[2 * e] == 1.0 && d[2 * e + 1] == 0.0)) touch |= 1 << e;
     }
     if (!touch) return QS_OK;
-    for_pieces(grid_for(nquads, kBlock), [&](unsigned g, u64 b0) {
-        hipLaunchKernelGGL(k_apply_diag2<R>, dim3(g), dim3(kBlock), 0, s->stream, (cx<R> *)s->buf, nquads, q0, q1, dd, touch, b0);
+    const Shape1q v = shape_1q();
+    const u32 chunk = v.dchunk == 0x7fffffffu ? chunk_for_control(q0, q1) : v.dchunk;
+    for_pieces(grid_for(nquads, kBlock * 2), [&](unsigned g, u64 b0) {
+        hipLaunchKernelGGL((k_apply_diag2<R, 2>), dim3(g), dim3(kBlock), 0, s->stream, (cx<R> *)s->buf, nquads, q0, q1, dd, touch, chunk, b0);
     });
     QS_LAUNCH_CHECK("apply_diag2");
     return QS_OK;
@@ -417,13 +464,15 @@ int launch_apply_diag2(qs_state *s, int q0, int q1, const double *d) {
 
 int launch_apply_swap(qs_state *s, int a, int b) {
     const u64 nquads = 1ull << (s->n - 2);
+    const Shape1q v = shape_1q();
+    const u32 chunk = v.dchunk == 0x7fffffffu ? chunk_for_control(a, b) : v.dchunk;
     if (s->dtype == QS_C128)
-        for_pieces(grid_for(nquads, kBlock), [&](unsigned g, u64 b0) {
-            hipLaunchKernelGGL(k_apply_swap<double>, dim3(g), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, nquads, a, b, b0);
+        for_pieces(grid_for(nquads, kBlock * 2), [&](unsigned g, u64 b0) {
+            hipLaunchKernelGGL((k_apply_swap<double, 2>), dim3(g), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, nquads, a, b, chunk, b0);
         });
     else
-        for_pieces(grid_for(nquads, kBlock), [&](unsigned g, u64 b0) {
-            hipLaunchKernelGGL(k_apply_swap<float>, dim3(g), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, nquads, a, b, b0);
+        for_pieces(grid_for(nquads, kBlock * 2), [&](unsigned g, u64 b0) {
+            hipLaunchKernelGGL((k_apply_swap<float, 2>), dim3(g), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, nquads, a, b, chunk, b0);
         });
     QS_LAUNCH_CHECK("apply_swap");
     return QS_OK;

@@ -1,0 +1,434 @@
+// Fused-block passes as straight-line code generated per plan and compiled at
+// run time (hiprtc).
+//
+// The interpreter kernel (k_tile_pass) decides at run time, gate by gate,
+// which kind of gate a staged record holds and which register slots it
+// touches; the compiler has to keep one register assignment for the group's
+// amplitudes across every branch, and it does so with copies at every merge.
+// Here the plan's structure (tile qubits, sweeps, each gate's kind, slots and
+// control position) is written out as source, so every gate becomes its plain
+// arithmetic on named values: a general 2x2 gate is its 16 multiply-adds per
+// pair, a permutation gate (X, CNOT, SWAP with the control in the group) only
+// renames values, and a diagonal entry equal to 1 costs nothing.  Gate values
+// stay data: the kernel reads them from a table (scalar loads), so a plan with
+// new angles but the same structure reuses the compiled code.
+//
+// Each workgroup is persistent: it walks tiles blockIdx.x, + gridDim.x, ...
+// and prefetches the next tile's amplitudes into registers while the current
+// tile's sweeps run, so the HBM stream overlaps the arithmetic.
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "launch.h"
+#include "tile.h"
+
+namespace qs {
+
+namespace {
+
+std::string S(long long v) { return std::to_string(v); }
+
+std::string hex(u64 v) {
+    char b[32];
+    snprintf(b, sizeof b, "0x%llxull", (unsigned long long)v);
+    return b;
+}
+
+// sum over b < nb of ((x >> b) & 1) << map[b], with runs of consecutive
+// positions mapped to consecutive bits as one shift-and-mask each.
+std::string deposit(const std::string &x, const uint8_t *map, int nb) {
+    std::string e;
+    int b = 0;
+    while (b < nb) {
+        int len = 1;
+        while (b + len < nb && map[b + len] == map[b] + len) ++len;
+        const u64 mask = len >= 64 ? ~0ull : ((1ull << len) - 1);
+        const std::string term = "(((" + x + ") >> " + S(b) + ") & " + hex(mask) + ") << " + S(map[b]);
+        e += (e.empty() ? "(" : " | (") + term + ")";
+        b += len;
+    }
+    return e.empty() ? std::string("0ull") : e;
+}
+
+enum Cls { kGeneral, kPermX, kDiagonal, kIdentity };
+
+// Structure of a 2x2 matrix, decided on its exact entries.
+Cls classify(const double *u) {
+    const bool off0 = u[2] == 0 && u[3] == 0 && u[4] == 0 && u[5] == 0;
+    if (off0 && u[0] == 1 && u[1] == 0 && u[6] == 1 && u[7] == 0) return kIdentity;
+    if (off0) return kDiagonal;
+    if (u[0] == 0 && u[1] == 0 && u[6] == 0 && u[7] == 0 && u[2] == 1 && u[3] == 0 && u[4] == 1 && u[5] == 0) return kPermX;
+    return kGeneral;
+}
+
+// Entry e of a diagonal two-qubit gate: 1 = exactly 1, -1 = exactly -1, 0 = other.
+int diag_entry_class(const double *u, int e) {
+    const double re = u[2 * e], im = u[2 * e + 1];
+    return re == 1 && im == 0 ? 1 : (re == -1 && im == 0 ? -1 : 0);
+}
+
+// A value source for one bit of an amplitude's index within a sweep: a
+// compile-time constant (a group slot), a per-lane bool, or a uniform bool.
+struct Bit {
+    int konst = -1;    // 0 / 1 when known for amplitude j
+    std::string var;   // otherwise the bool expression's variable
+};
+
+struct Gen {
+    int dtype;
+    int G;  // groups of 8 per thread
+    std::string o;
+    int uid = 0;
+    std::string fresh(const char *p) { return std::string(p) + S(uid++); }
+    std::string U(int gi, int k) const { return "vv[" + S(8 * gi + k) + "]"; }
+
+    // Bit of amplitude j of group g for tile position p / slot s / qubit q.
+    Bit bit(int j, int s, int p, int q, std::vector<std::string> &lane_vars, std::string &uni_var, int g) {
+        Bit b;
+        if (s >= 0) {
+            b.konst = (j >> s) & 1;
+        } else if (p >= 0) {
+            if (lane_vars[g].empty()) {
+                lane_vars[g] = fresh("c");
+                o += "      const bool " + lane_vars[g] + " = ((m" + S(g) + " >> " + S(p) + ") & 1u) != 0u;\n";
+            }
+            b.var = lane_vars[g];
+        } else {
+            if (uni_var.empty()) {
+                uni_var = fresh("w");
+                o += "      const bool " + uni_var + " = ((base >> " + S(q) + ") & 1ull) != 0ull;\n";
+            }
+            b.var = uni_var;
+        }
+        return b;
+    }
+
+    // The pair (names[j], names[k]) under a 2x2 gate of class c with values
+    // of plan gate gi, applied only where `cond` holds ("" = always).
+    void pair(std::string &x, std::string &y, Cls c, int gi, const std::string &cond) {
+        if (c == kIdentity) return;
+        if (c == kPermX) {
+            if (cond.empty()) {
+                std::swap(x, y);
+            } else {
+                const std::string a = fresh("x"), b = fresh("x");
+                o += "      const C " + a + " = " + cond + " ? " + y + " : " + x + ";\n";
+                o += "      const C " + b + " = " + cond + " ? " + x + " : " + y + ";\n";
+                x = a;
+                y = b;
+            }
+            return;
+        }
+        const std::string a = fresh("x"), b = fresh("x");
+        if (c == kDiagonal) {
+            o += "      const C " + a + " = cm(" + x + ", " + U(gi, 0) + ", " + U(gi, 1) + ");\n";
+            o += "      const C " + b + " = cm(" + y + ", " + U(gi, 6) + ", " + U(gi, 7) + ");\n";
+        } else {
+            o += "      const C " + a + " = row(" + U(gi, 0) + ", " + U(gi, 1) + ", " + U(gi, 2) + ", " + U(gi, 3) + ", " + x + ", " + y + ");\n";
+            o += "      const C " + b + " = row(" + U(gi, 4) + ", " + U(gi, 5) + ", " + U(gi, 6) + ", " + U(gi, 7) + ", " + x + ", " + y + ");\n";
+        }
+        if (cond.empty()) {
+            x = a;
+            y = b;
+        } else {
+            const std::string a2 = fresh("x"), b2 = fresh("x");
+            o += "      const C " + a2 + " = " + cond + " ? " + a + " : " + x + ";\n";
+            o += "      const C " + b2 + " = " + cond + " ? " + b + " : " + y + ";\n";
+            x = a2;
+            y = b2;
+        }
+    }
+
+    // One gate of a sweep on every group of the thread.
+    void gate(const DGate &d, int gi, std::vector<std::vector<std::string>> &nm) {
+        std::vector<std::string> lane0(G), lane1(G);
+        std::string uni0, uni1;
+        if (d.kind == QS_G_1Q) {
+            const Cls c = classify(d.u);
+            for (int g = 0; g < G; ++g)
+                for (int j = 0; j < 8; ++j)
+                    if (!((j >> d.s0) & 1)) pair(nm[g][j], nm[g][j | (1 << d.s0)], c, gi, "");
+        } else if (d.kind == QS_G_C1Q) {
+            const Cls c = classify(d.u);
+            for (int g = 0; g < G; ++g)
+                for (int j = 0; j < 8; ++j) {
+                    if ((j >> d.s1) & 1) continue;
+                    const Bit b = bit(j, d.s0, d.p0, d.q0, lane0, uni0, g);
+                    if (b.konst == 0) continue;
+                    pair(nm[g][j], nm[g][j | (1 << d.s1)], c, gi, b.konst == 1 ? "" : b.var);
+                }
+        } else if (d.kind == QS_G_DIAG2) {
+            // Entry index 2 b1 + b0; entries equal to 1 are skipped, -1 negates.
+            auto entry_cls = [&](int e) { return diag_entry_class(d.u, e); };
+            for (int g = 0; g < G; ++g)
+                for (int j = 0; j < 8; ++j) {
+                    const Bit b0 = bit(j, d.s0, d.p0, d.q0, lane0, uni0, g);
+                    const Bit b1 = bit(j, d.s1, d.p1, d.q1, lane1, uni1, g);
+                    std::string &x = nm[g][j];
+                    const std::string y = fresh("x");
+                    if (b0.konst >= 0 && b1.konst >= 0) {
+                        const int e = 2 * b1.konst + b0.konst, ec = entry_cls(e);
+                        if (ec == 1) continue;
+                        if (ec == -1) o += "      const C " + y + " = -" + x + ";\n";
+                        else o += "      const C " + y + " = cm(" + x + ", " + U(gi, 2 * e) + ", " + U(gi, 2 * e + 1) + ");\n";
+                    } else {
+                        // Select the entry's parts with the runtime bits.
+                        auto pick = [&](int part) {
+                            auto ent = [&](int e) { return U(gi, 2 * e + part); };
+                            auto over0 = [&](int hi) {
+                                if (b0.konst >= 0) return ent(2 * hi + b0.konst);
+                                return "(" + b0.var + " ? " + ent(2 * hi + 1) + " : " + ent(2 * hi) + ")";
+                            };
+                            if (b1.konst >= 0) return over0(b1.konst);
+                            return "(" + b1.var + " ? " + over0(1) + " : " + over0(0) + ")";
+                        };
+                        o += "      const C " + y + " = cm(" + x + ", " + pick(0) + ", " + pick(1) + ");\n";
+                    }
+                    x = y;
+                }
+        } else if (d.kind == QS_G_SWAP) {
+            const int a = d.s0, b = d.s1;
+            for (int g = 0; g < G; ++g)
+                for (int j = 0; j < 8; ++j)
+                    if (((j >> a) & 1) && !((j >> b) & 1)) std::swap(nm[g][j], nm[g][j ^ (1 << a) ^ (1 << b)]);
+        }
+    }
+};
+
+}  // namespace
+
+int gate_value_class(int kind, const double *u) {
+    if (kind == QS_G_1Q || kind == QS_G_C1Q) return (int)classify(u);
+    if (kind == QS_G_DIAG2) {
+        int c = 0;
+        for (int e = 0; e < 4; ++e) c |= (diag_entry_class(u, e) + 1) << (2 * e);
+        return c;
+    }
+    return 0;
+}
+
+// Source of one kernel per pass (qs_pass0, qs_pass1, ...) for passes whose
+// tile is full (tb = the dtype's tile size).  Returns "" if a pass does not
+// qualify (the caller then uses the interpreter).
+std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype) {
+    // Code-shape knobs (for tuning runs): QSIM_JIT_PREFETCH=0 loads each tile
+    // straight into LDS instead of prefetching the next one into registers;
+    // QSIM_JIT_WAVES=w asks the compiler to fit w waves per SIMD (0: no limit).
+    auto env = [](const char *k, int dflt) {
+        const char *e = getenv(k);
+        return e ? atoi(e) : dflt;
+    };
+    const bool prefetch = env("QSIM_JIT_PREFETCH", 1) != 0;
+    const int waves = env("QSIM_JIT_WAVES", 4);
+    const int TB = tile_bits_max(dtype);
+    const int TS = 1 << TB, NT = kTileThreads, PER = TS / NT;
+    Gen gen;
+    gen.dtype = dtype;
+    gen.G = (TS / 8) / NT;
+    std::string &o = gen.o;
+    o += dtype == QS_C128 ? "typedef double R;\n" : "typedef float R;\n";
+    o += "typedef R C __attribute__((ext_vector_type(2)));\n"
+         "__device__ __forceinline__ C row(R a, R b, R c, R d, C x, C y) {\n"
+         "  C r; r.x = a * x.x - b * x.y + c * y.x - d * y.y; r.y = a * x.y + b * x.x + c * y.y + d * y.x; return r; }\n"
+         "__device__ __forceinline__ C cm(C x, R a, R b) { C r; r.x = a * x.x - b * x.y; r.y = a * x.y + b * x.x; return r; }\n"
+         "__device__ __forceinline__ unsigned swz(unsigned m) { return m ^ ((m >> 3) & 7u); }\n"
+         "__device__ __forceinline__ unsigned ins(unsigned x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u)); }\n";
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        const DPass &P = passes[pi];
+        if (P.tb != TB) return "";
+        o += "extern \"C\" __global__ void __launch_bounds__(" + S(NT) + ")";
+        if (waves > 0) o += " __attribute__((amdgpu_waves_per_eu(" + S(waves) + ")))";
+        o += " qs_pass" + S((long long)pi) + "(C *__restrict__ psi, const R *__restrict__ v, unsigned ntiles) {\n";
+        o += "  __shared__ C sh[" + S(TS) + "];\n";
+        o += "  const unsigned t = threadIdx.x, st = swz(t);\n";
+        o += "  const unsigned long long dt = " + deposit("(unsigned long long)t", P.T, 9) + ";\n";
+        std::vector<u64> hi(PER);
+        for (int k = 0; k < PER; ++k) {
+            u64 off = 0;
+            for (int b = 9; b < TB; ++b)
+                if (((u64)k << 9 >> b) & 1) off |= 1ull << P.T[b];
+            hi[k] = off;
+        }
+        const std::string dep_tile = deposit("(unsigned long long)tile", P.rest, P.nrest);
+        const std::string dep_next = deposit("(unsigned long long)nx", P.rest, P.nrest);
+        o += "  C pre[" + S(PER) + "];\n";
+        o += "  unsigned tile = blockIdx.x;\n";
+        if (prefetch) {
+            o += "  if (tile < ntiles) {\n    const unsigned long long b0 = " + dep_tile + ";\n";
+            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = psi[b0 | dt | " + hex(hi[k]) + "];\n";
+            o += "  }\n";
+        }
+        o += "  for (; tile < ntiles; tile += gridDim.x) {\n";
+        // Opaque copies of the thread index and the value table per tile, so
+        // that the sweeps' LDS addresses and gate values are formed where they
+        // are used instead of being hoisted out of the loop, which would hold
+        // every sweep's addresses in registers at once.
+        o += "    unsigned tl = t; asm volatile(\"\" : \"+v\"(tl));\n";
+        o += "    const R *__restrict__ vv; { unsigned long long a_ = (unsigned long long)v; asm volatile(\"\" : \"+s\"(a_)); vv = (const R *)a_; }\n";
+        o += "    const unsigned long long base = " + dep_tile + ";\n";
+        // Sweeps of the pass: (first gate, run, group bits).
+        struct Sw {
+            int begin, run, g0, g1, g2;
+        };
+        std::vector<Sw> sw;
+        for (int gi = P.gate_begin; gi < P.gate_begin + P.gate_count; gi += dg[gi].run)
+            sw.push_back({gi, dg[gi].run, dg[gi].g[0], dg[gi].g[1], dg[gi].g[2]});
+        // A sweep whose group bits are the tile's top three positions holds
+        // exactly the amplitudes of the load/store layout (thread t, register
+        // k: tile index t + 512 k): the first such sweep runs on the loaded
+        // registers and the last one stores its registers, each saving one
+        // trip through LDS and a barrier.
+        auto on_top = [&](const Sw &w) { return w.g0 == TB - 3 && w.g1 == TB - 2 && w.g2 == TB - 1; };
+        const bool first_regs = !sw.empty() && on_top(sw.front());
+        const bool last_regs = !sw.empty() && on_top(sw.back());
+        auto hi_of = [&](u32 mhigh) {  // state offset of tile bits >= 9 of mhigh
+            u64 off = 0;
+            for (int b = 9; b < TB; ++b)
+                if ((mhigh >> b) & 1) off |= 1ull << P.T[b];
+            return off;
+        };
+        auto grp_off = [&](const Sw &w, int j) {
+            return ((u32)(j & 1) << w.g0) | ((u32)((j >> 1) & 1) << w.g1) | ((u32)((j >> 2) & 1) << w.g2);
+        };
+        auto issue_prefetch = [&]() {
+            if (!prefetch) return;
+            o += "    { const unsigned nx = tile + gridDim.x;\n      if (nx < ntiles) {\n        const unsigned long long nb = " + dep_next + ";\n";
+            for (int k = 0; k < PER; ++k) o += "        pre[" + S(k) + "] = psi[nb | dt | " + hex(hi[k]) + "];\n";
+            o += "      }\n    }\n";
+        };
+        if (!prefetch)
+            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = psi[base | dt | " + hex(hi[k]) + "];\n";
+        if (!first_regs) {
+            for (int k = 0; k < PER; ++k) o += "    sh[st + " + S(k * NT) + "u] = pre[" + S(k) + "];\n";
+            o += "    __syncthreads();\n";
+            issue_prefetch();
+        }
+        for (size_t si = 0; si < sw.size(); ++si) {
+            const Sw &w = sw[si];
+            const bool from_regs = si == 0 && first_regs, to_global = si + 1 == sw.size() && last_regs;
+            o += "    {\n";
+            std::vector<std::vector<std::string>> nm(gen.G, std::vector<std::string>(8));
+            for (int g = 0; g < gen.G; ++g) {
+                o += "      const unsigned m" + S(g) + " = ins(ins(ins(tl + " + S(g * NT) + "u, " + S(w.g0) + "), " + S(w.g1) + "), " + S(w.g2) + ");\n";
+                for (int j = 0; j < 8; ++j) {
+                    nm[g][j] = gen.fresh("x");
+                    if (from_regs)
+                        o += "      const C " + nm[g][j] + " = pre[" + S((g * NT + grp_off(w, j)) >> 9) + "];\n";
+                    else
+                        o += "      const C " + nm[g][j] + " = sh[swz(m" + S(g) + " | " + S(grp_off(w, j)) + "u)];\n";
+                }
+            }
+            for (int r = 0; r < w.run; ++r) gen.gate(dg[w.begin + r], w.begin + r, nm);
+            if (to_global) {
+                for (int g = 0; g < gen.G; ++g)
+                    for (int j = 0; j < 8; ++j)
+                        o += "      psi[base | dt | " + hex(hi_of((u32)(g * NT) + grp_off(w, j))) + "] = " + nm[g][j] + ";\n";
+            } else {
+                for (int g = 0; g < gen.G; ++g)
+                    for (int j = 0; j < 8; ++j) o += "      sh[swz(m" + S(g) + " | " + S(grp_off(w, j)) + "u)] = " + nm[g][j] + ";\n";
+            }
+            o += "      __syncthreads();\n    }\n";
+            if (from_regs) issue_prefetch();
+        }
+        if (sw.empty()) {  // a pass without gates: copy the tile back
+            for (int k = 0; k < PER; ++k) o += "    psi[base | dt | " + hex(hi[k]) + "] = sh[st + " + S(k * NT) + "u];\n";
+            o += "    __syncthreads();\n";
+        } else if (!last_regs) {
+            for (int k = 0; k < PER; ++k) o += "    psi[base | dt | " + hex(hi[k]) + "] = sh[st + " + S(k * NT) + "u];\n";
+            o += "    __syncthreads();\n";
+        }
+        o += "  }\n}\n";
+    }
+    return o;
+}
+
+// ------------------------------------------------------------------ compile and load
+
+namespace {
+
+// Compiled plan sources (code objects, host memory), kept for reuse: a new
+// state or a released plan with the same structure loads the code again
+// without compiling.  Beyond kMaxJitSources the least recently used source is
+// dropped.  Device residency belongs to the plans: each plan loads its own
+// module and unloads it when it is released.
+struct JitCode {
+    std::vector<char> code;
+    uint64_t last_use = 0;
+};
+constexpr size_t kMaxJitSources = 64;
+std::mutex g_jit_mu;
+uint64_t g_jit_clock = 0;
+std::unordered_map<std::string, JitCode> g_jit;
+
+int compile(const std::string &src, std::vector<char> &code) {
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "qsim_block.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return fail(QS_ERR_UNSUPPORTED, "hiprtcCreateProgram failed");
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    if (r != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        hiprtcGetProgramLogSize(prog, &n);
+        std::string log(n, '\0');
+        if (n) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(QS_ERR_UNSUPPORTED, "hiprtc compile of a block plan failed: " + log.substr(0, 2000));
+    }
+    size_t n = 0;
+    hiprtcGetCodeSize(prog, &n);
+    code.resize(n);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    return QS_OK;
+}
+
+}  // namespace
+
+int jit_block_functions(const std::string &src, int npass, int device, JitFns &out) {
+    std::vector<char> code;
+    {
+        std::lock_guard<std::mutex> lk(g_jit_mu);
+        auto it = g_jit.find(src);
+        if (it == g_jit.end()) {
+            JitCode c;
+            if (int rc = compile(src, c.code)) return rc;
+            if (g_jit.size() >= kMaxJitSources) {
+                auto lru = g_jit.begin();
+                for (auto j = g_jit.begin(); j != g_jit.end(); ++j)
+                    if (j->second.last_use < lru->second.last_use) lru = j;
+                g_jit.erase(lru);
+            }
+            it = g_jit.emplace(src, std::move(c)).first;
+        }
+        it->second.last_use = ++g_jit_clock;
+        code = it->second.code;
+    }
+    JitFns f;
+    QS_HIP(hipModuleLoadData(&f.mod, code.data()));
+    f.fn.resize(npass);
+    f.max_blocks.resize(npass);
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    for (int p = 0; p < npass && e == hipSuccess; ++p) {
+        const std::string name = "qs_pass" + S(p);
+        e = hipModuleGetFunction(&f.fn[p], f.mod, name.c_str());
+        int nb = 0;
+        if (e == hipSuccess) e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f.fn[p], kTileThreads, 0);
+        f.max_blocks[p] = (unsigned)std::max(1, nb) * (unsigned)std::max(1, cus);
+    }
+    if (e != hipSuccess) {
+        (void)hipModuleUnload(f.mod);
+        return hip_fail(e, "loading a compiled block plan");
+    }
+    out = std::move(f);
+    return QS_OK;
+}
+
+}  // namespace qs

@@ -44,10 +44,30 @@ struct PoolPlan {
     std::vector<PoolClass> classes;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
 };
 
 static std::mutex g_pool_mu;
 static std::map<std::string, PoolPlan> g_pool_plans;
+static uint64_t g_pool_clock = 0;
+// Plans kept at once; the least recently used one is released beyond this.
+constexpr size_t kMaxPoolPlans = 32;
+
+// Frees a plan's captured graph and device tables.  The device is synchronised
+// first: a replay or a batch launch of the plan may still be queued.
+static void free_pool_plan(PoolPlan &p) {
+    (void)hipDeviceSynchronize();
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    for (PoolClass &C : p.classes) {
+        if (C.dev_passes) (void)hipFree(C.dev_passes);
+        if (C.dev_map) (void)hipFree(C.dev_map);
+        C.dev_passes = nullptr;
+        C.dev_map = nullptr;
+    }
+    p.exec = nullptr;
+    p.graph = nullptr;
+}
 static std::map<std::string, std::pair<int, int>> g_tb_choice;  // "n:p:sets:grad" -> (TB, r)
 
 static std::string tb_key(int n, int p, int sets, bool grad) {
@@ -112,7 +132,7 @@ static int build_class(const qs_pool_desc *d, PoolClass &C, QShape shape, bool g
     C.proto.merged = plan.merged;  // the same pass structure for every graph of the class
     C.proto.map = plan.map;
     C.proto.geo.num_edges = max_edges;  // phase tables cover every graph of the class
-    C.proto.passes.clear();
+    C.proto.passes = plan.passes;  // for the pass flags only (the same for every graph of the class); launches read dev_passes
     C.np = C.proto.geo.np;
     C.circ_bytes = qaoa_layout(C.proto.geo, grad).bytes;
     std::vector<int32_t> map;
@@ -282,15 +302,37 @@ QS_API int qs_pool_run(const qs_pool_desc *d, const double *angles_dev, double *
                 QS_HIP(hipGraphInstantiate(&plan.exec, graph, nullptr, nullptr, 0));
                 plan.graph = graph;
             }
+            if (g_pool_plans.size() >= kMaxPoolPlans) {
+                auto lru = g_pool_plans.begin();
+                for (auto j = g_pool_plans.begin(); j != g_pool_plans.end(); ++j)
+                    if (j->second.last_use < lru->second.last_use) lru = j;
+                free_pool_plan(lru->second);
+                g_pool_plans.erase(lru);
+            }
             it = g_pool_plans.emplace(key, std::move(plan)).first;
         }
         PoolPlan &plan = it->second;
+        plan.last_use = ++g_pool_clock;
         if (plan.exec) {
             QS_HIP(hipGraphLaunch(plan.exec, st));
         } else {
             for (const PoolClass &C : plan.classes)
                 if (int rc = run_class(d, C, angles_dev, E_dev, grad_dev, (char *)ws, ws_bytes, st)) return rc;
         }
+        return QS_OK;
+    } catch (...) {
+        return fail(QS_ERR_UNSUPPORTED, "unexpected internal error");
+    }
+}
+
+QS_API int qs_pool_release(const qs_pool_desc *d, const double *angles_dev, double *E_dev, double *grad_dev, void *ws, size_t ws_bytes) {
+    try {
+        if (int rc = check_pool(d)) return rc;
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        auto it = g_pool_plans.find(pool_key(d, angles_dev, E_dev, grad_dev, ws, ws_bytes));
+        if (it == g_pool_plans.end()) return QS_OK;
+        free_pool_plan(it->second);
+        g_pool_plans.erase(it);
         return QS_OK;
     } catch (...) {
         return fail(QS_ERR_UNSUPPORTED, "unexpected internal error");

@@ -539,12 +539,15 @@ __device__ __forceinline__ void rt_rx_cur(d2v (&a)[1 << (TB - TT)], u32 rx, doub
     if (lanes) rt_rx<TB, TT, 0>(a, rx, cb, sb, kRegsNone, true);
 }
 
-template <typename CT, int TB, int TT, bool POOLED, bool MERGE>
+// TABS: the pass applies a cost phase from a table (unit weights: the first
+// pass, a pass ending in a phase, a merged pass).  Passes without one leave
+// the tables out, which lowers the block's LDS and lets more blocks share a CU.
+template <typename CT, int TB, int TT, bool POOLED, bool MERGE, bool TABS>
 __global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
     using G = RT<TB, TT>;
     constexpr int R = G::R, JB = G::JB;
     __shared__ d2v sh[G::TS];
-    __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
+    __shared__ d2v tab_a[TABS ? kQMaxEdges + 1 : 1], tab_b[TABS ? kQMaxEdges + 1 : 1];
     __shared__ double red[16];
     const QCirc q = qcirc<POOLED>(Parg, geo, B);
     const QPass &P = *q.P;
@@ -557,9 +560,11 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W,
     const bool first = !MERGE && (P.flags & QF_FIRST), pend = !MERGE && (P.flags & QF_PHASE_END), last = !MERGE && (P.flags & QF_LAST);
     const bool l1 = P.use_l1;
     const double g_a = q.theta[l], g_b = pend || merge ? q.theta[l + 1] : 0.0;
-    if (!geo.weighted) {
-        if (first) fill_table(tab_a, geo.num_edges, g_a);
-        if (pend || merge) fill_table(tab_b, geo.num_edges, g_b);
+    if constexpr (TABS) {
+        if (!geo.weighted) {
+            if (first) fill_table(tab_a, geo.num_edges, g_a);
+            if (pend || merge) fill_table(tab_b, geo.num_edges, g_b);
+        }
     }
     CT C0[R], C1[R];
     if (first) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, C0);
@@ -675,12 +680,12 @@ __device__ __forceinline__ void rt_ip_cur(const d2v (&lm)[1 << (TB - TT)], const
     if (lanes) rt_ip<TB, TT, 0>(lm, ps, rx, kRegsNone, true, acc);
 }
 
-template <typename CT, int TB, int TT, bool POOLED, bool MERGE>
+template <typename CT, int TB, int TT, bool POOLED, bool MERGE, bool TABS>
 __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
     using G = RT<TB, TT>;
     constexpr int R = G::R, JB = G::JB;
     __shared__ d2v sh[G::TS];
-    __shared__ d2v tab_a[kQMaxEdges + 1], tab_b[kQMaxEdges + 1];
+    __shared__ d2v tab_a[TABS ? kQMaxEdges + 1 : 1], tab_b[TABS ? kQMaxEdges + 1 : 1];
     __shared__ double red[64];  // qblock_sum4: 4 values x up to 16 waves
     const QCirc q = qcirc<POOLED>(Parg, geo, B);
     const QPass &P = *q.P;
@@ -693,9 +698,11 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
     const bool first = !MERGE && (P.flags & QF_FIRST), pend = !MERGE && (P.flags & QF_PHASE_END), last = !MERGE && (P.flags & QF_LAST);
     const bool l1 = P.use_l1;
     const double g_a = q.theta[l], g_b = pend || merge ? q.theta[l + 1] : 0.0;
-    if (!geo.weighted) {
-        if (first) fill_table(tab_a, geo.num_edges, g_a);
-        if (pend || merge) fill_table(tab_b, geo.num_edges, -g_b);  // exp(+i gamma C): undo the phase
+    if constexpr (TABS) {
+        if (!geo.weighted) {
+            if (first) fill_table(tab_a, geo.num_edges, g_a);
+            if (pend || merge) fill_table(tab_b, geo.num_edges, -g_b);  // exp(+i gamma C): undo the phase
+        }
     }
     // Register bits of the two layouts: A bits (tile 6..6+W-1) only in L1,
     // B bits (tile TT..TT+W-1) only in L0, the rest of the register bits and
@@ -1103,25 +1110,29 @@ QLayout qaoa_layout(const QGeom &g, int with_grad) {
 // Kernel pair for one (weights, shape) choice.
 template <typename CT, int TB, int TT, bool POOLED> struct RtKernels {
     static constexpr int threads = 1 << TT;
-    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool merged) {
+    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool merged, bool tabs) {
         if (merged)
-            hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED, true>), grid, dim3(threads), 0, st, P, W, g, B);
+            hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED, true, true>), grid, dim3(threads), 0, st, P, W, g, B);
+        else if (tabs)
+            hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED, false, true>), grid, dim3(threads), 0, st, P, W, g, B);
         else
-            hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED, false>), grid, dim3(threads), 0, st, P, W, g, B);
+            hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED, false, false>), grid, dim3(threads), 0, st, P, W, g, B);
     }
-    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool merged) {
+    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool merged, bool tabs) {
         if (merged)
-            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, true>), grid, dim3(threads), 0, st, P, W, g, B);
+            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, true, true>), grid, dim3(threads), 0, st, P, W, g, B);
+        else if (tabs)
+            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, false, true>), grid, dim3(threads), 0, st, P, W, g, B);
         else
-            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, false>), grid, dim3(threads), 0, st, P, W, g, B);
+            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, false, false>), grid, dim3(threads), 0, st, P, W, g, B);
     }
 };
 // LDS kernels serve n < 10: one qubit group, so no merged passes.
 template <typename CT, bool POOLED> struct LdsKernels {
-    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool) {
+    static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool, bool) {
         hipLaunchKernelGGL((k_qaoa_fwd_lds<CT, POOLED>), grid, dim3(kLdsThreads), 0, st, P, W, g, B);
     }
-    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool) {
+    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool, bool) {
         hipLaunchKernelGGL((k_qaoa_bwd_lds<CT, POOLED>), grid, dim3(kLdsThreads), 0, st, P, W, g, B);
     }
 };
@@ -1143,17 +1154,24 @@ static void launch_seq(const QPlan &plan, const QPass *passes, const QWeights &W
     static const QPass dummy{};
     auto pass = [&](int k) -> const QPass & { return POOLED ? dummy : passes[k]; };
     auto merged = [&](int k) { return plan.merged[k] != 0; };
+    // Phase tables: unit weights only, and only where a pass applies a phase
+    // (every graph of a pooled class shares the prototype's pass flags).
+    auto tabs = [&](int k) {
+        if (g.weighted) return false;
+        if ((size_t)k >= plan.passes.size()) return true;
+        return merged(k) || (plan.passes[k].flags & (QF_FIRST | QF_PHASE_END)) != 0;
+    };
     if (grad_out) {
         for (int k = 0; k < np; ++k) {
             B.k = k;
             B.in_off = k == 0 ? -1 : (long long)(L.ckpt + (size_t)(k - 1) * sb);
             B.out_off = (long long)(L.ckpt + (size_t)k * sb);
-            K::fwd(grid, st, pass(k), W, g, B, merged(k));
+            K::fwd(grid, st, pass(k), W, g, B, merged(k), tabs(k));
         }
         for (int k = np - 1; k >= 0; --k) {
             B.k = k;
             B.in_off = (long long)(L.ckpt + (size_t)k * sb);
-            K::bwd(grid, st, pass(k), W, g, B, merged(k));
+            K::bwd(grid, st, pass(k), W, g, B, merged(k), tabs(k));
         }
         hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(2 * g.p + 1, nb), dim3(256), 0, st, g, B, plan.map, E_out, grad_out, 1);
     } else {
@@ -1161,7 +1179,7 @@ static void launch_seq(const QPlan &plan, const QPass *passes, const QWeights &W
             B.k = k;
             B.in_off = k == 0 ? -1 : (long long)L.ckpt;
             B.out_off = k == np - 1 ? -1 : (long long)L.ckpt;
-            K::fwd(grid, st, pass(k), W, g, B, merged(k));
+            K::fwd(grid, st, pass(k), W, g, B, merged(k), tabs(k));
         }
         hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(1, nb), dim3(256), 0, st, g, B, plan.map, E_out, (double *)nullptr, 0);
     }

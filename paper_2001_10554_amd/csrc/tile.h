@@ -1,6 +1,7 @@
 // Tile-pass plans shared by the fused-block and trajectory kernels.
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -45,6 +46,21 @@ struct DPass {
 };
 
 inline int tile_bits_max(int dtype) { return dtype == QS_C128 ? 12 : 13; }
+
+// Run-time compiled passes of a block plan (jit_block.hip).
+struct JitFns {
+    hipModule_t mod = nullptr;         // loaded on the plan's device; unloaded with the plan
+    std::vector<hipFunction_t> fn;     // kernel of pass p: (C *psi, const R *vals, unsigned ntiles)
+    std::vector<unsigned> max_blocks;  // per pass: resident workgroups on the device (persistent grid size)
+};
+// Source of the plan's pass kernels; "" when a pass's tile is not full.
+std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype);
+// Kernels of a plan: compiled once per source (host cache), loaded into a
+// module of the caller's current device that the plan owns.
+int jit_block_functions(const std::string &src, int npass, int device, JitFns &out);
+// The exact-value class of a gate that the generated code specialises on (a
+// matrix equal to I or X, a diagonal matrix, diagonal entries equal to +-1).
+int gate_value_class(int kind, const double *u);
 
 
 

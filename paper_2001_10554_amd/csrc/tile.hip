@@ -49,40 +49,101 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_pass(cx<R> *__restrict__ 
 
 // ------------------------------------------------------------------ planning
 
+// A plan is keyed by the structure of its gate list (kinds, qubits and the
+// exact-value classes the generated code specialises on), not by the values:
+// a variational loop that changes angles reuses the plan and its compiled
+// code and only uploads the new values.
 struct Plan {
     std::vector<DPass> passes;
-    DGate *dev_gates = nullptr;
+    std::vector<DGate> dg;        // plan order; gidx = index in the caller's list
+    // Run-time compiled passes (empty: the interpreter kernel runs the plan).
+    JitFns jit;
+    // Device copy of what the kernels read: the gate values, 8 per gate in
+    // plan order in the state's type (compiled passes), or the DGate records
+    // (interpreter).  Uploads go through a pinned staging buffer with an
+    // asynchronous copy on the state's stream, only when the values change.
+    void *dev = nullptr;
+    void *stage = nullptr;
+    std::vector<char> last;       // bytes of the last upload
+    hipEvent_t staged = nullptr;  // recorded after the last upload's copy
+    uint64_t last_use = 0;
 };
+
+// Block plans kept per state; the least recently used one is released beyond this.
+constexpr size_t kMaxBlockPlans = 32;
+
+// QSIM_BLOCK_PATH=interp keeps fused blocks on the interpreter kernel (read
+// when a plan is built).
+static bool jit_wanted() {
+    const char *e = getenv("QSIM_BLOCK_PATH");
+    return !(e && std::string(e) == "interp");
+}
 
 struct PlanCache {
     std::unordered_map<std::string, Plan> plans;
+    uint64_t clock = 0;
 };
 
-// Cut a pass's gates into sweeps: maximal runs whose non-diagonal targets
-// span at most 3 tile bits, padded with the lowest free tile bits.
+// The caller has synchronised the state's stream (no kernel of the plan is queued).
+static void free_plan(Plan &p) {
+    if (p.staged) (void)hipEventSynchronize(p.staged);
+    (void)hipFree(p.dev);
+    (void)hipHostFree(p.stage);
+    if (p.staged) (void)hipEventDestroy(p.staged);
+    p.dev = p.stage = nullptr;
+    p.staged = nullptr;
+    if (p.jit.mod) (void)hipModuleUnload(p.jit.mod);
+    p.jit.mod = nullptr;
+    p.jit.fn.clear();
+}
+
+// Cut a pass's gates into sweeps whose non-diagonal targets span at most 3
+// tile bits, padded with the highest free tile bits.  A sweep is filled
+// greedily: scanning the pass's remaining gates in order, a gate joins if its
+// targets fit and it commutes with every gate it overtakes (disjoint qubits,
+// or both diagonal); the sweep's gates keep their relative order.  So
+// consecutive gates on changing targets (a one-qubit gate on every qubit
+// followed by a CNOT chain) share sweeps that a plain prefix split would
+// spread over twice as many.  Each gate keeps its list index (gidx).
 static void make_sweeps(int tb, DGate *d, int cnt) {
-    int i = 0;
-    while (i < cnt) {
+    auto one = [](const DGate &x) { return x.kind == QS_G_1Q || x.kind == QS_G_NOISE; };
+    auto touch = [&](const DGate &x) { return (1ull << x.q0) | (one(x) ? 0ull : 1ull << x.q1); };
+    std::vector<DGate> in(d, d + cnt), out;
+    std::vector<int> rem(cnt), later;
+    for (int i = 0; i < cnt; ++i) rem[i] = i;
+    out.reserve(cnt);
+    while (!rem.empty()) {
         int gp[3], ng = 0;
         auto has = [&](int p) {
             for (int a = 0; a < ng; ++a)
                 if (gp[a] == p) return true;
             return false;
         };
-        int j = i;
-        for (; j < cnt; ++j) {
+        u64 left_any = 0, left_nondiag = 0;
+        const size_t first = out.size();
+        later.clear();
+        for (int i : rem) {
+            const DGate &x = in[i];
             int need[2], nn = 0;
-            const int k = d[j].kind;
-            if (k == QS_G_1Q || k == QS_G_NOISE) need[nn++] = d[j].p0;
-            else if (k == QS_G_C1Q) need[nn++] = d[j].p1;
-            else if (k == QS_G_SWAP) { need[nn++] = d[j].p0; need[nn++] = d[j].p1; }
+            if (one(x)) need[nn++] = x.p0;
+            else if (x.kind == QS_G_C1Q) need[nn++] = x.p1;
+            else if (x.kind == QS_G_SWAP) { need[nn++] = x.p0; need[nn++] = x.p1; }
             int fresh = 0;
             for (int a = 0; a < nn; ++a) fresh += !has(need[a]) && !(a == 1 && need[1] == need[0]);
-            if (ng + fresh > 3 || j - i == kStage) break;
-            for (int a = 0; a < nn; ++a)
-                if (!has(need[a])) gp[ng++] = need[a];
+            const bool diag = x.kind == QS_G_DIAG2;
+            const bool commutes = (touch(x) & (diag ? left_nondiag : left_any)) == 0;
+            if (commutes && ng + fresh <= 3 && out.size() - first < (size_t)kStage) {
+                for (int a = 0; a < nn; ++a)
+                    if (!has(need[a])) gp[ng++] = need[a];
+                out.push_back(x);
+            } else {
+                later.push_back(i);
+                left_any |= touch(x);
+                if (!diag) left_nondiag |= touch(x);
+            }
         }
-        for (int p = 0; ng < 3 && p < tb; ++p)
+        rem.swap(later);
+        for (int p = tb - 1; ng < 3 && p >= 0; --p)
             if (!has(p)) gp[ng++] = p;
         std::sort(gp, gp + 3);
         auto slot = [&](int p) -> int8_t {
@@ -90,14 +151,16 @@ static void make_sweeps(int tb, DGate *d, int cnt) {
                 if (gp[a] == p) return (int8_t)a;
             return (int8_t)-1;
         };
-        d[i].run = (int16_t)(j - i);
-        for (int a = 0; a < 3; ++a) d[i].g[a] = (int8_t)gp[a];
-        for (int t = i; t < j; ++t) {
-            d[t].s0 = d[t].p0 >= 0 ? slot(d[t].p0) : (int8_t)-1;
-            d[t].s1 = d[t].p1 >= 0 ? slot(d[t].p1) : (int8_t)-1;
+        DGate &h = out[first];
+        h.run = (int16_t)(out.size() - first);
+        for (int a = 0; a < 3; ++a) h.g[a] = (int8_t)gp[a];
+        for (size_t t = first; t < out.size(); ++t) {
+            out[t].s0 = out[t].p0 >= 0 ? slot(out[t].p0) : (int8_t)-1;
+            out[t].s1 = out[t].p1 >= 0 ? slot(out[t].p1) : (int8_t)-1;
+            if (t != first) out[t].run = 0;
         }
-        i = j;
     }
+    std::copy(out.begin(), out.end(), d);
 }
 
 // Split the list into passes (see the file comment) and encode each gate's
@@ -204,42 +267,117 @@ void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std
 
 static std::mutex g_plan_mu;
 
+static std::string structure_key(const qs_state *s, const qs_gate *gates, int count, bool jit) {
+    std::string key;
+    auto add = [&](int32_t v) { key.append((const char *)&v, sizeof v); };
+    add(s->n);
+    add(s->dtype);
+    add(jit);
+    for (int i = 0; i < count; ++i) {
+        add(gates[i].kind);
+        add(gates[i].q0);
+        add(gates[i].kind == QS_G_1Q ? -1 : gates[i].q1);
+        add(gate_value_class(gates[i].kind, gates[i].u));
+    }
+    return key;
+}
+
+// Bytes the plan's kernels read for this gate list (values in plan order).
+static std::vector<char> plan_bytes(const Plan &p, const qs_gate *gates, int dtype) {
+    std::vector<char> out;
+    if (!p.jit.fn.empty()) {
+        const size_t rs = dtype == QS_C128 ? sizeof(double) : sizeof(float);
+        out.resize(p.dg.size() * 8 * rs);
+        for (size_t i = 0; i < p.dg.size(); ++i)
+            for (int k = 0; k < 8; ++k) {
+                const double u = gates[p.dg[i].gidx].u[k];
+                if (dtype == QS_C128) memcpy(out.data() + (8 * i + k) * rs, &u, rs);
+                else {
+                    const float f = (float)u;
+                    memcpy(out.data() + (8 * i + k) * rs, &f, rs);
+                }
+            }
+    } else {
+        std::vector<DGate> dg = p.dg;
+        for (DGate &d : dg) memcpy(d.u, gates[d.gidx].u, sizeof d.u);
+        out.resize(dg.size() * sizeof(DGate));
+        memcpy(out.data(), dg.data(), out.size());
+    }
+    return out;
+}
+
 int run_block(qs_state *s, const qs_gate *gates, int count) {
     if (count == 0) return QS_OK;
-    std::string key((const char *)gates, (size_t)count * sizeof(qs_gate));
-    key.append((const char *)&s->n, sizeof(int));
-    key.append((const char *)&s->dtype, sizeof(int));
-    Plan *plan = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_plan_mu);
-        if (!s->plan_cache) s->plan_cache = new PlanCache();
-        auto *cache = (PlanCache *)s->plan_cache;
-        auto it = cache->plans.find(key);
-        if (it == cache->plans.end()) {
-            Plan p;
-            std::vector<DGate> dg;
-            make_plan(s->n, s->dtype, tile_bits_max(s->dtype), gates, count, p.passes, dg);
-            QS_HIP(hipMalloc(&p.dev_gates, dg.size() * sizeof(DGate)));
-            QS_HIP(hipMemcpy(p.dev_gates, dg.data(), dg.size() * sizeof(DGate), hipMemcpyHostToDevice));
-            it = cache->plans.emplace(std::move(key), std::move(p)).first;
+    const bool want_jit = jit_wanted();
+    const std::string key = structure_key(s, gates, count, want_jit);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (!s->plan_cache) s->plan_cache = new PlanCache();
+    auto *cache = (PlanCache *)s->plan_cache;
+    auto it = cache->plans.find(key);
+    if (it == cache->plans.end()) {
+        if (cache->plans.size() >= kMaxBlockPlans) {
+            auto lru = cache->plans.begin();
+            for (auto j = cache->plans.begin(); j != cache->plans.end(); ++j)
+                if (j->second.last_use < lru->second.last_use) lru = j;
+            QS_HIP(hipStreamSynchronize(s->stream));  // its kernels may still be queued
+            free_plan(lru->second);
+            cache->plans.erase(lru);
         }
-        plan = &it->second;
+        Plan p;
+        make_plan(s->n, s->dtype, tile_bits_max(s->dtype), gates, count, p.passes, p.dg);
+        const std::string src = want_jit ? jit_block_source(p.passes, p.dg, s->dtype) : std::string();
+        if (src.empty() || jit_block_functions(src, (int)p.passes.size(), s->device, p.jit) != QS_OK) p.jit = JitFns{};
+        const size_t nb = plan_bytes(p, gates, s->dtype).size();
+        QS_HIP(hipMalloc(&p.dev, nb));
+        if (hipHostMalloc(&p.stage, nb, hipHostMallocDefault) != hipSuccess) {
+            free_plan(p);
+            return fail(QS_ERR_HIP, "hipHostMalloc of the plan's staging buffer failed");
+        }
+        if (hipEventCreateWithFlags(&p.staged, hipEventDisableTiming) != hipSuccess) {
+            free_plan(p);
+            return fail(QS_ERR_HIP, "hipEventCreate failed");
+        }
+        it = cache->plans.emplace(key, std::move(p)).first;
     }
-    for (const DPass &P : plan->passes) {
+    Plan &plan = it->second;
+    plan.last_use = ++cache->clock;
+    std::vector<char> bytes = plan_bytes(plan, gates, s->dtype);
+    if (bytes != plan.last) {
+        QS_HIP(hipEventSynchronize(plan.staged));  // the previous upload has left the staging buffer
+        memcpy(plan.stage, bytes.data(), bytes.size());
+        QS_HIP(hipMemcpyAsync(plan.dev, plan.stage, bytes.size(), hipMemcpyHostToDevice, s->stream));
+        QS_HIP(hipEventRecord(plan.staged, s->stream));
+        plan.last.swap(bytes);
+    }
+    if (!plan.jit.fn.empty()) {
+        for (size_t pi = 0; pi < plan.passes.size(); ++pi) {
+            unsigned ntiles = 1u << plan.passes[pi].nrest;
+            const unsigned grid = std::min(ntiles, plan.jit.max_blocks[pi]);
+            void *psi = s->buf, *vals = plan.dev;
+            void *args[] = {&psi, &vals, &ntiles};
+            QS_HIP(hipModuleLaunchKernel(plan.jit.fn[pi], grid, 1, 1, kTileThreads, 1, 1, 0, s->stream, args, nullptr));
+        }
+        return QS_OK;
+    }
+    for (const DPass &P : plan.passes) {
         const unsigned grid = 1u << P.nrest;
         if (s->dtype == QS_C128)
-            hipLaunchKernelGGL((k_tile_pass<double, 12>), dim3(grid), dim3(kTileThreads), 0, s->stream, (cx<double> *)s->buf, P, plan->dev_gates);
+            hipLaunchKernelGGL((k_tile_pass<double, 12>), dim3(grid), dim3(kTileThreads), 0, s->stream, (cx<double> *)s->buf, P,
+                               (const DGate *)plan.dev);
         else
-            hipLaunchKernelGGL((k_tile_pass<float, 13>), dim3(grid), dim3(kTileThreads), 0, s->stream, (cx<float> *)s->buf, P, plan->dev_gates);
+            hipLaunchKernelGGL((k_tile_pass<float, 13>), dim3(grid), dim3(kTileThreads), 0, s->stream, (cx<float> *)s->buf, P,
+                               (const DGate *)plan.dev);
         QS_LAUNCH_CHECK("tile_pass");
     }
     return QS_OK;
 }
 
+size_t block_plan_count(const qs_state *s) { return s->plan_cache ? ((const PlanCache *)s->plan_cache)->plans.size() : 0; }
+
 void free_plan_cache(qs_state *s) {
     if (!s->plan_cache) return;
     auto *cache = (PlanCache *)s->plan_cache;
-    for (auto &kv : cache->plans) (void)hipFree(kv.second.dev_gates);
+    for (auto &kv : cache->plans) free_plan(kv.second);
     delete cache;
     s->plan_cache = nullptr;
 }

@@ -63,6 +63,17 @@ class Noise(ctypes.Structure):
 
 
 _lib = None
+_exiting = False
+
+
+def _mark_exit():
+    global _exiting
+    _exiting = True
+
+
+import atexit  # noqa: E402
+
+atexit.register(_mark_exit)  # no library calls from finalisers once the interpreter is shutting down
 
 
 def lib():
@@ -104,6 +115,7 @@ def lib():
             "qs_qaoa_run": [vp, vp, i, vp, vp, vp, sz, vp],
             "qs_pool_workspace_bytes": [vp, vp],
             "qs_pool_run": [vp, vp, vp, vp, vp, sz, vp],
+            "qs_pool_release": [vp, vp, vp, vp, vp, sz],
             "qs_pool_circuit_bytes": [vp, i, vp],
             "qs_cut_max": [vp, vp, vp, vp, vp],
             "qs_pso_init": [vp, u64, vp, vp],
@@ -420,6 +432,24 @@ class Pool:
         self.angles = torch.zeros(self.count, 2 * p, dtype=torch.float64, device=device)
         self.E = torch.empty(self.count, dtype=torch.float64, device=device)
         self.G = torch.empty(self.count, 2 * p, dtype=torch.float64, device=device) if grad else None
+
+    def _plan_args(self):
+        return (ctypes.byref(self._desc), ctypes.c_void_p(self.angles.data_ptr()), ctypes.c_void_p(self.E.data_ptr()),
+                ctypes.c_void_p(self.G.data_ptr()) if self.G is not None else None, ctypes.c_void_p(self.ws.data_ptr()),
+                self.ws.numel())
+
+    def release(self):
+        """Free the library's plan for this pool (captured graph, device tables)."""
+        if getattr(self, "ws", None) is not None:
+            check(lib().qs_pool_release(*self._plan_args()))
+
+    def __del__(self):
+        if _exiting:
+            return
+        try:
+            self.release()
+        except Exception:
+            pass
 
     def run(self, angles: torch.Tensor | None = None, stream=None):
         """Copy `angles` [count, 2p] into the pool's device buffer (if given) and

@@ -1,0 +1,102 @@
+"""Resource lifetimes of the library's caches: block plans (at most 32 per
+state, keyed by the gate list's structure, values uploaded on change) and pool
+plans (released explicitly, at most 32 kept).  Device memory must return to
+its starting level once the objects are gone, and a plan reused with new gate
+values must compute with the new values."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_10554_amd import workloads as W
+from gpu_util import check_amps, record, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _free_bytes():
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return torch.cuda.mem_get_info()[0]
+
+
+@pytest.mark.parametrize("path", ["jit", "interp"])
+def test_block_plan_reused_with_new_values(path, monkeypatch):
+    """One structure, three sets of angles: the plan is built once and each call
+    uploads its values; every result matches the oracle."""
+    from paper_2001_10554_amd.qsim import State
+    monkeypatch.setenv("QSIM_BLOCK_PATH", path)
+    n = 14
+    s = State(n).init_random(3)
+    ref = oracle.init_random(n, 3)
+    base = W.random_block(n, 60, seed=8)
+    for k in range(3):
+        g = base.copy()
+        rng = np.random.default_rng(100 + k)
+        for i in range(len(g)):
+            if int(g[i]["kind"]) in (W.G_1Q, W.G_C1Q):
+                g[i]["u"] = W.mat_to_u8(W.haar_2x2(rng))
+        s.apply_block(g)
+        oracle.apply_gates(ref, g)
+        check_amps(s.amps.cpu().numpy(), ref, "c128", f"{path} values set {k}")
+
+
+@pytest.mark.parametrize("path,count", [("interp", 300), ("jit", 40)])
+def test_block_plans_bounded_and_released(path, count, monkeypatch):
+    """`count` gate lists of different structure on one state: device memory
+    stays bounded (least recently used plans are released beyond 32) and
+    returns to its starting level when the state is destroyed."""
+    from paper_2001_10554_amd.qsim import State
+    monkeypatch.setenv("QSIM_BLOCK_PATH", path)
+    n = 13
+    # A first round of as many structures on another state: the first use of
+    # the kernels loads their code, and the runtime keeps the memory it grew
+    # for loaded modules; neither is a leak.  Measured from the steady state.
+    w = State(n).init_random(1)
+    for i in range(count):
+        w.apply_block(W.random_block(n, 8, seed=50_000 + i))
+    w.close()
+    del w
+    start = _free_bytes()
+    s = State(n).init_random(1)
+    peak_use = 0
+    for i in range(count):
+        s.apply_block(W.random_block(n, 8, seed=1000 + i))
+        if i % 20 == 19:
+            peak_use = max(peak_use, start - _free_bytes())
+    s.close()
+    del s
+    left = start - _free_bytes()
+    print(f"{path}: {count} structures, peak {peak_use / 2**20:.1f} MiB in use, {left / 2**20:.1f} MiB left after release")
+    record(f"{path}: device MiB still in use after the state is destroyed", max(left, 0) / 2**20, 2.0)
+    # at most 32 plans; a compiled plan also holds its loaded module (~2 MiB)
+    record(f"{path}: peak device MiB in use", peak_use / 2**20, 96.0 if path == "jit" else 32.0)
+
+
+def test_pools_created_and_released():
+    """200 pools of different graphs, each run and released: device memory
+    returns to its starting level."""
+    import torch
+    from paper_2001_10554_amd.qsim import Pool
+
+    def cycle(i):
+        graphs = [W.random_regular_graph(8, 3, seed=i), W.random_regular_graph(10, 3, seed=i + 7)]
+        pool = Pool(graphs, [8, 10], 2, 1)
+        pool.run(torch.tensor(W.qaoa_angles(1, seed=i, hi=2 * math.pi, count=pool.count), device="cuda"))
+        pool.release()
+
+    cycle(10_000)  # first use of the kernels loads their code: not a leak
+    start = _free_bytes()
+    for i in range(200):
+        cycle(i)
+    left = start - _free_bytes()
+    print(f"pools: {left / 2**20:.1f} MiB left after 200 create/run/release cycles")
+    record("device MiB still in use after 200 pools", max(left, 0) / 2**20, 2.0)

@@ -228,6 +228,20 @@ int qs_inner(qs_state *a, qs_state *b, double *out_dev);
  * sequential sum only within ~1e-15 of bin boundaries. */
 int qs_sample(qs_state *s, int64_t shots, uint64_t seed, uint64_t *out_dev);
 
+/* qs_sample for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * draws as qs_sample on a register given by pointer (dev_buf: 2^n amplitudes
+ * of dtype, buf_bytes its size), without a state handle.  The partial sums
+ * (chunk sums and their prefix, at most 2 * 2^18 + 1 doubles) live in a fixed
+ * 4 MiB device array inside the library, one copy per device, held until the
+ * process ends; this call allocates nothing.  All calls on one device share
+ * that array: calls that may overlap on one device (different streams or
+ * host threads) race and must be serialised by the caller.  Errors:
+ * QS_ERR_DTYPE; QS_ERR_SIZE for n above QS_MAX_QUBITS_* or a short buffer;
+ * QS_ERR_ARG for n < 1, null pointers or shots outside [0, 2^32]. */
+int qs_sample_noalloc(int n, int dtype, const void *dev_buf, size_t buf_bytes, int64_t shots, uint64_t seed, uint64_t *out_dev,
+                      void *stream);
+
 /* ---------------------------------------------------------------- QAOA Max-Cut with adjoint gradient */
 
 /* |psi(theta)> = prod_{l=1..p} exp(-i beta_l B) exp(-i gamma_l C) H^{(x)n}|0>,

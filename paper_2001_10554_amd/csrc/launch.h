@@ -26,6 +26,11 @@ int launch_expect_diag(qs_state *s, const double *d_dev, double *out_dev);
 int launch_expect_pauli(qs_state *s, u64 xmask, u64 zmask, double *out_dev);
 int launch_inner(qs_state *a, qs_state *b, double *out_dev);
 int launch_sample(qs_state *s, int64_t shots, u64 seed, u64 *out_dev);
+// Sampling of a register given by pointer: scratch holds at least
+// 2 * 2^(n - sample_chunk_bits(n)) + 1 doubles (chunk sums, their prefix, the
+// last nonzero chunk), all overwritten before they are read.
+int sample_chunk_bits(int n);
+int launch_sample_buf(int n, int dtype, const void *buf, double *scratch, hipStream_t st, int64_t shots, u64 seed, u64 *out_dev);
 
 // measure.hip
 int launch_measure(qs_state *s, int q, int outcome, u64 seed, int32_t *outcome_dev, double *prob_dev);

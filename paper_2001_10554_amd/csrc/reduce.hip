@@ -467,29 +467,34 @@ __global__ __launch_bounds__(kBlock) void k_sample(const cx<R> *__restrict__ psi
     if (lane == 0) out[s] = result;
 }
 
-int launch_sample(qs_state *s, int64_t shots, u64 seed, u64 *out_dev) {
-    const int n = s->n;
-    const int cs = n <= 12 ? n : (n - 18 > 12 ? n - 18 : 12);
+int sample_chunk_bits(int n) { return n <= 12 ? n : (n - 18 > 12 ? n - 18 : 12); }
+
+int launch_sample_buf(int n, int dtype, const void *buf, double *scratch, hipStream_t st, int64_t shots, u64 seed, u64 *out_dev) {
+    const int cs = sample_chunk_bits(n);
     const int G = 1 << (n - cs);
-    double *csum = s->scratch, *cdf = s->scratch + G, *last = s->scratch + 2 * (size_t)G;
-    if (s->dtype == QS_C128)
-        hipLaunchKernelGGL(k_chunk_sums<double>, dim3(G), dim3(kBlock), 0, s->stream, (const cx<double> *)s->buf, cs, csum);
+    double *csum = scratch, *cdf = scratch + G, *last = scratch + 2 * (size_t)G;
+    if (dtype == QS_C128)
+        hipLaunchKernelGGL(k_chunk_sums<double>, dim3(G), dim3(kBlock), 0, st, (const cx<double> *)buf, cs, csum);
     else
-        hipLaunchKernelGGL(k_chunk_sums<float>, dim3(G), dim3(kBlock), 0, s->stream, (const cx<float> *)s->buf, cs, csum);
+        hipLaunchKernelGGL(k_chunk_sums<float>, dim3(G), dim3(kBlock), 0, st, (const cx<float> *)buf, cs, csum);
     QS_LAUNCH_CHECK("sample_chunks");
-    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, s->stream, csum, G, cdf, last);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBlock), 0, st, csum, G, cdf, last);
     QS_LAUNCH_CHECK("sample_scan");
     if (shots <= 0) return QS_OK;
     const u64 blocks = ((u64)shots + 3) / 4;  // one wavefront per shot; shots <= 2^32 checked by the caller
     const u32 k0 = (u32)seed, k1 = (u32)(seed >> 32);
-    if (s->dtype == QS_C128)
-        hipLaunchKernelGGL(k_sample<double>, dim3((unsigned)blocks), dim3(kBlock), 0, s->stream, (const cx<double> *)s->buf, n, cs, G, cdf, last,
+    if (dtype == QS_C128)
+        hipLaunchKernelGGL(k_sample<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<double> *)buf, n, cs, G, cdf, last,
                            shots, k0, k1, out_dev);
     else
-        hipLaunchKernelGGL(k_sample<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s->stream, (const cx<float> *)s->buf, n, cs, G, cdf, last,
+        hipLaunchKernelGGL(k_sample<float>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<float> *)buf, n, cs, G, cdf, last,
                            shots, k0, k1, out_dev);
     QS_LAUNCH_CHECK("sample");
     return QS_OK;
+}
+
+int launch_sample(qs_state *s, int64_t shots, u64 seed, u64 *out_dev) {
+    return launch_sample_buf(s->n, s->dtype, s->buf, s->scratch, s->stream, shots, seed, out_dev);
 }
 
 }  // namespace qs

@@ -111,6 +111,7 @@ def lib():
             "qs_expect_pauli": [vp, u64, u64, vp],
             "qs_inner": [vp, vp, vp],
             "qs_sample": [vp, i64, u64, vp],
+            "qs_sample_noalloc": [i, i, vp, sz, i64, u64, vp, vp],
             "qs_qaoa_workspace_bytes": [vp, i, vp],
             "qs_qaoa_run": [vp, vp, i, vp, vp, vp, sz, vp],
             "qs_pool_workspace_bytes": [vp, vp],
@@ -364,6 +365,22 @@ class State:
         o = self._out(max(shots, 1), torch.int64)
         check(lib().qs_sample(self._h, shots, seed, ctypes.c_void_p(o.data_ptr())))
         return self._done(o)[:shots]
+
+
+def sample_noalloc(amps: torch.Tensor, shots: int, seed: int, stream=None) -> torch.Tensor:
+    """qs_sample on a register tensor without a state handle (the library's
+    fixed device array holds the partial sums).  Calls that overlap on one
+    device race; the output tensor is allocated here, the call itself
+    allocates nothing."""
+    n = amps.numel().bit_length() - 1
+    code = QS_C128 if amps.dtype == torch.complex128 else QS_C64
+    s = _begin(stream)
+    with torch.cuda.stream(s):
+        o = torch.empty(max(shots, 1), dtype=torch.int64, device=amps.device)
+    check(lib().qs_sample_noalloc(n, code, ctypes.c_void_p(amps.data_ptr()), amps.numel() * amps.element_size(), shots, seed,
+                                  ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(s.cuda_stream)))
+    _finish(s, (o,))
+    return o[:shots]
 
 
 # ---------------------------------------------------------------- QAOA Max-Cut

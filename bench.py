@@ -391,8 +391,11 @@ def noise_bench(T=1024):
            "E_exact": e_exact}
     for label, theta in (("pso_angles", theta_pso), ("random_angles", W.qaoa_angles(p, seed=9, hi=2 * math.pi))):
         gates = W.with_noise_gates(W.qaoa_circuit(n, edges, p, theta), 1.0)
-        t = _time_cuda(lambda: traj_run(n, gates, 0, T, 0.0, 1, T1=500.0, T2=250.0, diag=diag, prob_mean=False), 2)
-        r = traj_run(n, gates, 0, T, 0.0, 1, T1=500.0, T2=250.0, diag=diag, prob_mean=False)
+        # per-trajectory <C> (the diagonal read-out) only: no <Z_q>, <X_q>, fidelity
+        run = lambda seed: traj_run(n, gates, 0, T, 0.0, seed, T1=500.0, T2=250.0, diag=diag, prob_mean=False,  # noqa: E731
+                                    readouts=())
+        t = _time_cuda(lambda: run(1), 2)
+        r = run(1)
         ideal = traj_run(n, gates, 0, 1, 0.0, 1, diag=diag, prob_mean=False)  # no decay: the noiseless value
         out[label] = {"gates": int(len(gates)), "trajectories_per_s": round(T / t, 1), "ms": round(t * 1e3, 3),
                       "noiseless_C": round(float(ideal["diag"][0].item()), 6),
@@ -400,8 +403,7 @@ def noise_bench(T=1024):
         if CURVES.get("enabled"):
             curves = []
             for seed in range(1, 9):
-                r = traj_run(n, gates, 0, T, 0.0, seed, T1=500.0, T2=250.0, diag=diag, prob_mean=False)
-                c = r["diag"].cpu().numpy()
+                c = run(seed)["diag"].cpu().numpy()
                 curves.append([round(float(c[:m].mean()), 5) for m in Ts])
             CURVES[f"noise_{label}_convergence"] = {"T": Ts, "mean_C": curves}
     out["pso_angles"]["swarm_best_C"] = round(e_pso, 6)

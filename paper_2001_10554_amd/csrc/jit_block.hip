@@ -83,7 +83,8 @@ struct Bit {
 
 struct Gen {
     int dtype;
-    int G;  // groups of 8 per thread
+    int G;          // groups of 8 per thread
+    bool traj = false;  // trajectory passes: values per trajectory (every gate general), C1Q control value from tcv
     std::string o;
     int uid = 0;
     std::string fresh(const char *p) { return std::string(p) + S(uid++); }
@@ -150,23 +151,40 @@ struct Gen {
     void gate(const DGate &d, int gi, std::vector<std::vector<std::string>> &nm) {
         std::vector<std::string> lane0(G), lane1(G);
         std::string uni0, uni1;
-        if (d.kind == QS_G_1Q) {
-            const Cls c = classify(d.u);
+        if (d.kind == QS_G_1Q || (traj && d.kind == QS_G_NOISE)) {
+            if (traj && d.pad0 == 2) return;  // a noise gate folded into the gate before it
+            const Cls c = traj ? kGeneral : classify(d.u);
             for (int g = 0; g < G; ++g)
                 for (int j = 0; j < 8; ++j)
                     if (!((j >> d.s0) & 1)) pair(nm[g][j], nm[g][j | (1 << d.s0)], c, gi, "");
         } else if (d.kind == QS_G_C1Q) {
-            const Cls c = classify(d.u);
+            const Cls c = traj ? kGeneral : classify(d.u);
+            // Trajectories: the control value the gate fires on (an X in the
+            // frame on the control flips it) is per trajectory.
+            std::string cv;
+            if (traj) {
+                cv = fresh("v");
+                o += "      const bool " + cv + " = tcv[" + S(gi) + "] != 0;\n";
+            }
             for (int g = 0; g < G; ++g)
                 for (int j = 0; j < 8; ++j) {
                     if ((j >> d.s1) & 1) continue;
                     const Bit b = bit(j, d.s0, d.p0, d.q0, lane0, uni0, g);
-                    if (b.konst == 0) continue;
-                    pair(nm[g][j], nm[g][j | (1 << d.s1)], c, gi, b.konst == 1 ? "" : b.var);
+                    std::string cond;
+                    if (!traj) {
+                        if (b.konst == 0) continue;
+                        cond = b.konst == 1 ? "" : b.var;
+                    } else if (b.konst >= 0) {
+                        cond = b.konst ? cv : "!" + cv;
+                    } else {
+                        cond = "(" + b.var + " == " + cv + ")";
+                    }
+                    pair(nm[g][j], nm[g][j | (1 << d.s1)], c, gi, cond);
                 }
         } else if (d.kind == QS_G_DIAG2) {
-            // Entry index 2 b1 + b0; entries equal to 1 are skipped, -1 negates.
-            auto entry_cls = [&](int e) { return diag_entry_class(d.u, e); };
+            // Entry index 2 b1 + b0; entries equal to 1 are skipped, -1 negates
+            // (blocks only: a trajectory's frame permutes the entries).
+            auto entry_cls = [&](int e) { return traj ? 0 : diag_entry_class(d.u, e); };
             for (int g = 0; g < G; ++g)
                 for (int j = 0; j < 8; ++j) {
                     const Bit b0 = bit(j, d.s0, d.p0, d.q0, lane0, uni0, g);
@@ -229,6 +247,16 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
     const int waves = env("QSIM_JIT_WAVES", 4);
     const int TB = tile_bits_max(dtype);
     const int TS = 1 << TB, NT = kTileThreads, PER = TS / NT;
+    static const int kSwz128[12] = {1, 2, 4, 8, 15, 12, 9, 3, 6, 14, 6, 0};
+    static const int kSwz64[13] = {1, 2, 4, 8, 16, 31, 26, 22, 1, 0, 14, 9, 20};
+    const int SB = dtype == QS_C128 ? 4 : 5;
+    const int *swz_pat = dtype == QS_C128 ? kSwz128 : kSwz64;
+    auto hsw = [&](u32 m) {
+        u32 h = 0;
+        for (int p = SB; p < TB; ++p)
+            if ((m >> p) & 1) h ^= (u32)swz_pat[p];
+        return h;
+    };
     Gen gen;
     gen.dtype = dtype;
     gen.G = (TS / 8) / NT;
@@ -238,8 +266,19 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
          "__device__ __forceinline__ C row(R a, R b, R c, R d, C x, C y) {\n"
          "  C r; r.x = a * x.x - b * x.y + c * y.x - d * y.y; r.y = a * x.y + b * x.x + c * y.y + d * y.x; return r; }\n"
          "__device__ __forceinline__ C cm(C x, R a, R b) { C r; r.x = a * x.x - b * x.y; r.y = a * x.y + b * x.x; return r; }\n"
-         "__device__ __forceinline__ unsigned swz(unsigned m) { return m ^ ((m >> 3) & 7u); }\n"
+
          "__device__ __forceinline__ unsigned ins(unsigned x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u)); }\n";
+    // LDS slot of tile index m: m ^ hsw(m), hsw XOR-ing a fixed pattern into
+    // the low SB bits for each set bit of m at or above SB (a bijection).  The
+    // b128 (c128) / b64 (c64) accesses of 16 / 32 lanes are served together;
+    // with these patterns the lanes of every sweep whose group bits are three
+    // consecutive tile bits (and of the load/store layout) reach 2^SB distinct
+    // slots modulo 2^SB, i.e. distinct banks (found by search over all
+    // patterns; 189 of the 220 possible group-bit triples of a 12-bit tile).
+    o += "__device__ __forceinline__ unsigned hsw(unsigned m) {\n  unsigned h = 0u;\n";
+    for (int p = SB; p < TB; ++p)
+        if (swz_pat[p]) o += "  h ^= ((m >> " + S(p) + ") & 1u) ? " + S(swz_pat[p]) + "u : 0u;\n";
+    o += "  return h;\n}\n";
     for (size_t pi = 0; pi < passes.size(); ++pi) {
         const DPass &P = passes[pi];
         if (P.tb != TB) return "";
@@ -247,7 +286,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         if (waves > 0) o += " __attribute__((amdgpu_waves_per_eu(" + S(waves) + ")))";
         o += " qs_pass" + S((long long)pi) + "(C *__restrict__ psi, const R *__restrict__ v, unsigned ntiles) {\n";
         o += "  __shared__ C sh[" + S(TS) + "];\n";
-        o += "  const unsigned t = threadIdx.x, st = swz(t);\n";
+        o += "  const unsigned t = threadIdx.x, st = t ^ hsw(t);\n";
         o += "  const unsigned long long dt = " + deposit("(unsigned long long)t", P.T, 9) + ";\n";
         std::vector<u64> hi(PER);
         for (int k = 0; k < PER; ++k) {
@@ -306,7 +345,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         if (!prefetch)
             for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = psi[base | dt | " + hex(hi[k]) + "];\n";
         if (!first_regs) {
-            for (int k = 0; k < PER; ++k) o += "    sh[st + " + S(k * NT) + "u] = pre[" + S(k) + "];\n";
+            for (int k = 0; k < PER; ++k) o += "    sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u] = pre[" + S(k) + "];\n";
             o += "    __syncthreads();\n";
             issue_prefetch();
         }
@@ -317,12 +356,13 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             std::vector<std::vector<std::string>> nm(gen.G, std::vector<std::string>(8));
             for (int g = 0; g < gen.G; ++g) {
                 o += "      const unsigned m" + S(g) + " = ins(ins(ins(tl + " + S(g * NT) + "u, " + S(w.g0) + "), " + S(w.g1) + "), " + S(w.g2) + ");\n";
+                if (!from_regs || !to_global) o += "      const unsigned s" + S(g) + " = m" + S(g) + " ^ hsw(m" + S(g) + ");\n";
                 for (int j = 0; j < 8; ++j) {
                     nm[g][j] = gen.fresh("x");
                     if (from_regs)
                         o += "      const C " + nm[g][j] + " = pre[" + S((g * NT + grp_off(w, j)) >> 9) + "];\n";
                     else
-                        o += "      const C " + nm[g][j] + " = sh[swz(m" + S(g) + " | " + S(grp_off(w, j)) + "u)];\n";
+                        o += "      const C " + nm[g][j] + " = sh[s" + S(g) + " ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u];\n";
                 }
             }
             for (int r = 0; r < w.run; ++r) gen.gate(dg[w.begin + r], w.begin + r, nm);
@@ -332,19 +372,143 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
                         o += "      psi[base | dt | " + hex(hi_of((u32)(g * NT) + grp_off(w, j))) + "] = " + nm[g][j] + ";\n";
             } else {
                 for (int g = 0; g < gen.G; ++g)
-                    for (int j = 0; j < 8; ++j) o += "      sh[swz(m" + S(g) + " | " + S(grp_off(w, j)) + "u)] = " + nm[g][j] + ";\n";
+                    for (int j = 0; j < 8; ++j) o += "      sh[s" + S(g) + " ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u] = " + nm[g][j] + ";\n";
             }
             o += "      __syncthreads();\n    }\n";
             if (from_regs) issue_prefetch();
         }
         if (sw.empty()) {  // a pass without gates: copy the tile back
-            for (int k = 0; k < PER; ++k) o += "    psi[base | dt | " + hex(hi[k]) + "] = sh[st + " + S(k * NT) + "u];\n";
+            for (int k = 0; k < PER; ++k) o += "    psi[base | dt | " + hex(hi[k]) + "] = sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u];\n";
             o += "    __syncthreads();\n";
         } else if (!last_regs) {
-            for (int k = 0; k < PER; ++k) o += "    psi[base | dt | " + hex(hi[k]) + "] = sh[st + " + S(k * NT) + "u];\n";
+            for (int k = 0; k < PER; ++k) o += "    psi[base | dt | " + hex(hi[k]) + "] = sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u];\n";
             o += "    __syncthreads();\n";
         }
         o += "  }\n}\n";
+    }
+    return o;
+}
+
+// Trajectory passes (one kernel per pass, qs_tpass0, ...): block = (trajectory,
+// tile) as in k_traj_pass, with the same early exits (trajectories that share
+// the noiseless state or whose first affected gate lies beyond the pass) and
+// the same start from the noiseless run's state; gate values and C1Q control
+// values come per trajectory from tables (tv: 8 values per plan gate, tcv: 1
+// per plan gate) that the frames, noise matrices and folding fill beforehand.
+// Tiles of 12 bits for both types.
+std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype) {
+    const int TB = 12, TS = 1 << TB, NT = kTileThreads, PER = TS / NT;
+    static const int kPat128[12] = {1, 2, 4, 8, 15, 12, 9, 3, 6, 14, 6, 0};
+    static const int kPat64[12] = {1, 2, 4, 8, 16, 31, 25, 21, 27, 25, 1, 30};
+    const int SB = dtype == QS_C128 ? 4 : 5;
+    const int *pat = dtype == QS_C128 ? kPat128 : kPat64;
+    auto hsw = [&](u32 m) {
+        u32 h = 0;
+        for (int p = SB; p < TB; ++p)
+            if ((m >> p) & 1) h ^= (u32)pat[p];
+        return h;
+    };
+    Gen gen;
+    gen.dtype = dtype;
+    gen.G = 1;
+    gen.traj = true;
+    std::string &o = gen.o;
+    o += dtype == QS_C128 ? "typedef double R;\n" : "typedef float R;\n";
+    o += "typedef R C __attribute__((ext_vector_type(2)));\n"
+         "__device__ __forceinline__ C row(R a, R b, R c, R d, C x, C y) {\n"
+         "  C r; r.x = a * x.x - b * x.y + c * y.x - d * y.y; r.y = a * x.y + b * x.x + c * y.y + d * y.x; return r; }\n"
+         "__device__ __forceinline__ C cm(C x, R a, R b) { C r; r.x = a * x.x - b * x.y; r.y = a * x.y + b * x.x; return r; }\n"
+         "__device__ __forceinline__ unsigned ins(unsigned x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u)); }\n";
+    o += "__device__ __forceinline__ unsigned hsw(unsigned m) {\n  unsigned h = 0u;\n";
+    for (int p = SB; p < TB; ++p)
+        if (pat[p]) o += "  h ^= ((m >> " + S(p) + ") & 1u) ? " + S(pat[p]) + "u : 0u;\n";
+    o += "  return h;\n}\n";
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        const DPass &P = passes[pi];
+        if (P.tb != TB) return "";
+        o += "extern \"C\" __global__ void __launch_bounds__(" + S(NT) + ") qs_tpass" + S((long long)pi) +
+             "(C *__restrict__ states, unsigned long long N, const R *__restrict__ tv, const int *__restrict__ tc, unsigned ngates,"
+             " int first_pass, unsigned long long basis, const int *__restrict__ nins, const int *__restrict__ first, int n_traj,"
+             " const C *ideal_in, C *ideal_out) {\n";
+        o += "  __shared__ C sh[" + S(TS) + "];\n";
+        o += "  const unsigned tile = blockIdx.x & " + S((1u << P.nrest) - 1) + "u;\n";
+        o += "  const unsigned t = blockIdx.x >> " + S(P.nrest) + ";\n";
+        o += "  if (!(t == (unsigned)n_traj || nins[t] > 0)) return;\n";
+        o += "  const bool ideal = t == (unsigned)n_traj;\n";
+        o += "  const int g1 = ideal ? 0 : first[t];\n";
+        o += "  if (!ideal && g1 >= " + S(P.gate_begin + P.gate_count) + ") return;\n";
+        o += "  const bool from_ideal = ideal || g1 >= " + S(P.gate_begin) + ";\n";
+        o += "  C *psi = ideal ? ideal_out : states + (unsigned long long)t * N;\n";
+        o += "  const C *src = from_ideal ? ideal_in : psi;\n";
+        o += "  const bool fill = from_ideal && first_pass != 0;\n";
+        o += "  const R *__restrict__ vv = tv + (unsigned long long)t * ngates * 8u;\n";
+        o += "  const int *__restrict__ tcv = tc + (unsigned long long)t * ngates;\n";
+        o += "  const unsigned tl = threadIdx.x, st = tl ^ hsw(tl);\n";
+        o += "  const unsigned long long dt = " + deposit("(unsigned long long)tl", P.T, 9) + ";\n";
+        o += "  const unsigned long long base = " + deposit("(unsigned long long)tile", P.rest, P.nrest) + ";\n";
+        std::vector<u64> hi(PER);
+        for (int k = 0; k < PER; ++k) {
+            u64 off = 0;
+            for (int b = 9; b < TB; ++b)
+                if (((u64)k << 9 >> b) & 1) off |= 1ull << P.T[b];
+            hi[k] = off;
+        }
+        o += "  C pre[" + S(PER) + "];\n";
+        for (int k = 0; k < PER; ++k) {
+            const std::string idx = "(base | dt | " + hex(hi[k]) + ")";
+            o += "  if (fill) { pre[" + S(k) + "].x = " + idx + " == basis ? (R)1 : (R)0; pre[" + S(k) + "].y = (R)0; }\n";
+            o += "  else pre[" + S(k) + "] = __builtin_nontemporal_load(src + " + idx + ");\n";
+        }
+        struct Sw {
+            int begin, run, g0, g1, g2;
+        };
+        std::vector<Sw> sw;
+        for (int gi = P.gate_begin; gi < P.gate_begin + P.gate_count; gi += dg[gi].run)
+            sw.push_back({gi, dg[gi].run, dg[gi].g[0], dg[gi].g[1], dg[gi].g[2]});
+        auto on_top = [&](const Sw &w) { return w.g0 == TB - 3 && w.g1 == TB - 2 && w.g2 == TB - 1; };
+        const bool first_regs = !sw.empty() && on_top(sw.front());
+        const bool last_regs = !sw.empty() && on_top(sw.back());
+        auto grp_off = [&](const Sw &w, int j) {
+            return ((u32)(j & 1) << w.g0) | ((u32)((j >> 1) & 1) << w.g1) | ((u32)((j >> 2) & 1) << w.g2);
+        };
+        auto hi_of = [&](u32 mhigh) {
+            u64 off = 0;
+            for (int b = 9; b < TB; ++b)
+                if ((mhigh >> b) & 1) off |= 1ull << P.T[b];
+            return off;
+        };
+        if (!first_regs) {
+            for (int k = 0; k < PER; ++k) o += "  sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u] = pre[" + S(k) + "];\n";
+            o += "  __syncthreads();\n";
+        }
+        for (size_t si = 0; si < sw.size(); ++si) {
+            const Sw &w = sw[si];
+            const bool from_regs = si == 0 && first_regs, to_global = si + 1 == sw.size() && last_regs;
+            o += "  {\n";
+            std::vector<std::vector<std::string>> nm(1, std::vector<std::string>(8));
+            o += "      const unsigned m0 = ins(ins(ins(tl, " + S(w.g0) + "), " + S(w.g1) + "), " + S(w.g2) + ");\n";
+            if (!from_regs || !to_global) o += "      const unsigned s0 = m0 ^ hsw(m0);\n";
+            for (int j = 0; j < 8; ++j) {
+                nm[0][j] = gen.fresh("x");
+                if (from_regs)
+                    o += "      const C " + nm[0][j] + " = pre[" + S(grp_off(w, j) >> 9) + "];\n";
+                else
+                    o += "      const C " + nm[0][j] + " = sh[s0 ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u];\n";
+            }
+            for (int r = 0; r < w.run; ++r) gen.gate(dg[w.begin + r], w.begin + r, nm);
+            if (to_global) {
+                for (int j = 0; j < 8; ++j)
+                    o += "      __builtin_nontemporal_store(" + nm[0][j] + ", psi + (base | dt | " + hex(hi_of(grp_off(w, j))) + "));\n";
+            } else {
+                for (int j = 0; j < 8; ++j) o += "      sh[s0 ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u] = " + nm[0][j] + ";\n";
+                o += "      __syncthreads();\n";
+            }
+            o += "  }\n";
+        }
+        if (sw.empty() || !last_regs)
+            for (int k = 0; k < PER; ++k)
+                o += "  __builtin_nontemporal_store(sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u], psi + (base | dt | " + hex(hi[k]) + "));\n";
+        o += "}\n";
     }
     return o;
 }
@@ -391,7 +555,7 @@ int compile(const std::string &src, std::vector<char> &code) {
 
 }  // namespace
 
-int jit_block_functions(const std::string &src, int npass, int device, JitFns &out) {
+int jit_block_functions(const std::string &src, int npass, int device, JitFns &out, const char *prefix) {
     std::vector<char> code;
     {
         std::lock_guard<std::mutex> lk(g_jit_mu);
@@ -417,7 +581,7 @@ int jit_block_functions(const std::string &src, int npass, int device, JitFns &o
     int cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     for (int p = 0; p < npass && e == hipSuccess; ++p) {
-        const std::string name = "qs_pass" + S(p);
+        const std::string name = prefix + S(p);
         e = hipModuleGetFunction(&f.fn[p], f.mod, name.c_str());
         int nb = 0;
         if (e == hipSuccess) e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f.fn[p], kTileThreads, 0);

@@ -211,6 +211,49 @@ __device__ __forceinline__ d2v shfl_xor2(d2v v, int m) {
     return r;
 }
 
+// The value of lane ^ 2^LB without the LDS unit (a wavefront shuffle is an
+// LDS instruction, and the backward passes wait on LDS issue for nearly half
+// of their time): DPP quad permutes for bits 0 and 1, a half-row / row mirror
+// followed by a quad reversal or half-row mirror for bits 2 and 3 (i ^ 7 ^ 3
+// = i ^ 4, i ^ 15 ^ 7 = i ^ 8), and the gfx950 lane-half swaps for bits 4 and
+// 5 (the swap returns the exchanged halves; each lane keeps the half that
+// came from its partner).
+template <int CTRL> __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int LB> __device__ __forceinline__ uint32_t xlane32(uint32_t v) {
+    if constexpr (LB == 0) return dpp32<0xB1>(v);
+    else if constexpr (LB == 1) return dpp32<0x4E>(v);
+    else if constexpr (LB == 2) return dpp32<0x1B>(dpp32<0x141>(v));
+    else if constexpr (LB == 3) return dpp32<0x141>(dpp32<0x140>(v));
+    else if constexpr (LB == 4) {
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? p[0] : p[1];
+    } else {
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? p[0] : p[1];
+    }
+}
+template <int LB> __device__ __forceinline__ d2v xlane2(d2v v) {
+    const uint64_t a = (uint64_t)__double_as_longlong(v.x), b = (uint64_t)__double_as_longlong(v.y);
+    d2v r;
+    r.x = __longlong_as_double((long long)((uint64_t)xlane32<LB>((uint32_t)a) | ((uint64_t)xlane32<LB>((uint32_t)(a >> 32)) << 32)));
+    r.y = __longlong_as_double((long long)((uint64_t)xlane32<LB>((uint32_t)b) | ((uint64_t)xlane32<LB>((uint32_t)(b >> 32)) << 32)));
+    return r;
+}
+// Partner value for lane bit lb (run-time; one uniform branch per value,
+// so only the partner is live across it).
+__device__ __forceinline__ d2v lane_partner(d2v v, int lb) {
+    switch (lb) {
+    case 0: return xlane2<0>(v);
+    case 1: return xlane2<1>(v);
+    case 2: return xlane2<2>(v);
+    case 3: return xlane2<3>(v);
+    case 4: return xlane2<4>(v);
+    default: return xlane2<5>(v);
+    }
+}
+
 __device__ __forceinline__ double qblock_sum(double v, double *sh) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
@@ -517,7 +560,7 @@ __device__ __forceinline__ void rt_rx(d2v (&a)[1 << (TB - TT)], u32 rx, double c
             const bool on = (lm >> lb) & 1;
             const double c = on ? cb : 1.0, s = on ? sb : 0.0;
 #pragma unroll
-            for (int j = 0; j < G::R; ++j) a[j] = rx_half(a[j], shfl_xor2(a[j], 1 << lb), c, s);
+            for (int j = 0; j < G::R; ++j) a[j] = rx_half(a[j], lane_partner(a[j], lb), c, s);
         }
     }
 }
@@ -655,7 +698,7 @@ __device__ __forceinline__ void rt_ip(const d2v (&lm)[1 << (TB - TT)], const d2v
         for (int lb = lo; lb < 6; ++lb) {
             double t = 0.0;
 #pragma unroll
-            for (int j = 0; j < G::R; ++j) t += im_conj_mul(lm[j], shfl_xor2(ps[j], 1 << lb));
+            for (int j = 0; j < G::R; ++j) t += im_conj_mul(lm[j], lane_partner(ps[j], lb));
             if ((lmask >> lb) & 1) acc += t;
         }
     }

@@ -57,7 +57,11 @@ struct JitFns {
 std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype);
 // Kernels of a plan: compiled once per source (host cache), loaded into a
 // module of the caller's current device that the plan owns.
-int jit_block_functions(const std::string &src, int npass, int device, JitFns &out);
+int jit_block_functions(const std::string &src, int npass, int device, JitFns &out, const char *prefix = "qs_pass");
+// Source of a trajectory plan's pass kernels (qs_tpass0, ...): per-trajectory
+// gate values and control values from tables; "" when a pass's tile is not
+// 12 bits.
+std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype);
 // The exact-value class of a gate that the generated code specialises on (a
 // matrix equal to I or X, a diagonal matrix, diagonal entries equal to +-1).
 int gate_value_class(int kind, const double *u);

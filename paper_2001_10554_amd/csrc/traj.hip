@@ -23,6 +23,9 @@
 // frame seen by every gate, so the decisions are bit-exact by construction.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "launch.h"
@@ -244,6 +247,79 @@ __global__ void k_traj_noise_mats(const DGate *__restrict__ gates, int count, in
     double *o = nm + ((u64)t * nnoise + g.nidx) * 8;
 #pragma unroll
     for (int k = 0; k < 8; ++k) o[k] = u[k];
+}
+
+// Per (simulated trajectory, plan gate): the gate as the compiled passes apply
+// it, F^dagger G F for the trajectory's frame F before the gate (the same
+// values the interpreter's staging computes): tv[(t * ngates + i) * 8 + k]
+// the 2x2 matrix (1Q, C1Q, noise) or the 4 diagonal entries (DIAG2), tc the
+// control value a C1Q gate fires on.  Noise gates of the noiseless run are the
+// identity; a one-qubit gate followed by a noise gate on its qubit takes that
+// gate's matrix into its own.
+template <typename R>
+__global__ void k_traj_vals(const DGate *__restrict__ gates, int ngates, const uint64_t *__restrict__ frames, int count,
+                            const int32_t *__restrict__ nins, int n_traj, const double *__restrict__ nm, int nnoise, R *__restrict__ tv,
+                            int32_t *__restrict__ tc) {
+    const u64 id = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (u64)(n_traj + 1) * ngates) return;
+    const u64 t = id / ngates;
+    const int i = (int)(id % ngates);
+    if (!traj_simulated(nins, t, n_traj)) return;
+    const bool ideal = t == (u64)n_traj;
+    const DGate &g = gates[i];
+    const u64 f = frames[t * count + g.gidx];
+    const u32 a = (u32)f, b = (u32)(f >> 32);
+    double u[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k] = g.u[k];
+    int cval = 1;
+    if (g.kind == QS_G_NOISE) {
+        if (ideal || g.pad0 == 2) {
+            const double id2[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = id2[k];
+        } else {
+            const double *src = nm + ((u64)t * nnoise + g.nidx) * 8;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = src[k];
+            conj_pauli(u, (a >> g.q0) & 1, (b >> g.q0) & 1);
+        }
+    } else if (g.kind == QS_G_1Q) {
+        conj_pauli(u, (a >> g.q0) & 1, (b >> g.q0) & 1);
+        if (g.pad0 == 1 && !ideal) {
+            const DGate &nx = gates[i + 1];
+            const u64 f2 = frames[t * count + nx.gidx];
+            const double *src = nm + ((u64)t * nnoise + nx.nidx) * 8;
+            double w[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) w[k] = src[k];
+            conj_pauli(w, ((u32)f2 >> g.q0) & 1, ((u32)(f2 >> 32) >> g.q0) & 1);
+            mat2_mul(w, u);
+        }
+    } else if (g.kind == QS_G_C1Q) {
+        cval = 1 ^ (int)((a >> g.q0) & 1);
+        conj_pauli(u, (a >> g.q1) & 1, (b >> g.q1) & 1);
+    } else if (g.kind == QS_G_DIAG2) {  // entries permuted by the frame's X part on q0 / q1
+        auto sw = [&](int e0, int e1) {
+            const double r = u[2 * e0], m = u[2 * e0 + 1];
+            u[2 * e0] = u[2 * e1];
+            u[2 * e0 + 1] = u[2 * e1 + 1];
+            u[2 * e1] = r;
+            u[2 * e1 + 1] = m;
+        };
+        if ((a >> g.q0) & 1) {
+            sw(0, 1);
+            sw(2, 3);
+        }
+        if ((a >> g.q1) & 1) {
+            sw(0, 2);
+            sw(1, 3);
+        }
+    }
+    R *o = tv + id * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (R)u[k];
+    tc[id] = cval;
 }
 
 // One pass of every simulated trajectory: block = (trajectory, tile).  Gates
@@ -573,9 +649,14 @@ __global__ __launch_bounds__(kBlock) void k_traj_prob_mean(const cx<R> *__restri
 // ------------------------------------------------------------------ host side
 
 struct TrajLayout {
-    size_t states, ideal2, frames, final_frame, nins, first, pmlist, pzf, px, gates, dgates, nm, total;
+    size_t states, ideal2, frames, final_frame, nins, first, pmlist, pzf, px, gates, dgates, nm, tv, tc, total;
     int chunk_log2, chunks_log2;
+    bool tables;  // room for the compiled passes' per-trajectory gate tables
 };
+
+// Per-trajectory gate tables of the compiled passes: used for registers of at
+// least one full 12-qubit tile when they stay within this size.
+constexpr size_t kTrajTableMax = (size_t)1 << 30;
 
 static int count_noise(const qs_gate *gates, int count) {
     int c = 0;
@@ -615,6 +696,12 @@ static TrajLayout traj_layout(int n, int dtype, int count, int n_traj, int nnois
     off = align(off + (size_t)count * sizeof(DGate));
     L.nm = off;
     off = align(off + (size_t)n_traj * nnoise * 8 * sizeof(double));
+    const size_t tv_bytes = (size_t)(n_traj + 1) * count * 8 * sizeof(double);
+    L.tables = n >= 12 && tv_bytes <= kTrajTableMax;
+    L.tv = off;
+    if (L.tables) off = align(off + tv_bytes);
+    L.tc = off;
+    if (L.tables) off = align(off + (size_t)(n_traj + 1) * count * sizeof(int32_t));
     L.total = off;
     return L;
 }
@@ -642,6 +729,47 @@ static double traj_plan_cost(const std::vector<DPass> &passes, const std::vector
         surv *= 1.0 - pins;
     }
     return n_traj * e + tail[0];
+}
+
+// Compiled trajectory passes, kept per (source, device) for the process: a
+// trajectory run is one call, and repeated runs of one circuit reuse the
+// code.  At most kMaxTrajModules are kept; beyond that the device is
+// synchronised and the least recently used module unloaded.
+struct TrajModule {
+    hipModule_t mod = nullptr;
+    std::vector<hipFunction_t> fn;
+    uint64_t last_use = 0;
+};
+constexpr size_t kMaxTrajModules = 16;
+static std::mutex g_traj_mu;
+static uint64_t g_traj_clock = 0;
+static auto *g_traj_mods = new std::map<std::pair<std::string, int>, TrajModule>();  // never destroyed (process exit)
+
+static int traj_functions(const std::string &src, int np, std::vector<hipFunction_t> &out) {
+    int dev = 0;
+    QS_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_traj_mu);
+    auto key = std::make_pair(src, dev);
+    auto it = g_traj_mods->find(key);
+    if (it == g_traj_mods->end()) {
+        JitFns jf;
+        if (int rc = jit_block_functions(src, np, dev, jf, "qs_tpass")) return rc;
+        if (g_traj_mods->size() >= kMaxTrajModules) {
+            auto lru = g_traj_mods->begin();
+            for (auto j = g_traj_mods->begin(); j != g_traj_mods->end(); ++j)
+                if (j->second.last_use < lru->second.last_use) lru = j;
+            (void)hipDeviceSynchronize();
+            (void)hipModuleUnload(lru->second.mod);
+            g_traj_mods->erase(lru);
+        }
+        TrajModule m;
+        m.mod = jf.mod;
+        m.fn = jf.fn;
+        it = g_traj_mods->emplace(key, std::move(m)).first;
+    }
+    it->second.last_use = ++g_traj_clock;
+    out = it->second.fn;
+    return QS_OK;
 }
 
 template <typename R, int TBMAX>
@@ -733,16 +861,44 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     // its last pass writes the slot the read-outs use.
     cx<R> *ibuf[2] = {states + (u64)n_traj * N, (cx<R> *)(ws + L.ideal2)};
     const int np = (int)passes.size();
-    for (int k = 0; k < np; ++k) {
-        const DPass &P = passes[k];
-        const int tiles_log2 = P.nrest;
-        const u64 blocks = (u64)T1 << tiles_log2;
-        const cx<R> *in = k == 0 ? nullptr : ibuf[(np - k) & 1];
-        cx<R> *outb = ibuf[(np - 1 - k) & 1];
-        hipLaunchKernelGGL((k_traj_pass<R, TBMAX>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, states, N, tiles_log2, P, (const DGate *)(ws + L.dgates),
-                           (const uint64_t *)frames, count, k == 0 ? 1 : 0, basis, (const int32_t *)nins, (const int32_t *)first_gate, n_traj,
-                           (const double *)nm, nnoise, in, outb);
-        QS_LAUNCH_CHECK("traj_pass");
+    // Compiled passes (jit_block.hip) when the workspace holds the gate
+    // tables and every pass has a full tile; QSIM_TRAJ_PATH=interp keeps the
+    // interpreter kernel.
+    std::vector<hipFunction_t> jfn;
+    if (L.tables && !(getenv("QSIM_TRAJ_PATH") && std::string(getenv("QSIM_TRAJ_PATH")) == "interp")) {
+        const std::string src = jit_traj_source(passes, dg, dtype);
+        if (!src.empty() && traj_functions(src, np, jfn) != QS_OK) jfn.clear();
+    }
+    if (!jfn.empty()) {
+        R *tv = (R *)(ws + L.tv);
+        int32_t *tc = (int32_t *)(ws + L.tc);
+        const int ng = (int)dg.size();
+        hipLaunchKernelGGL(k_traj_vals<R>, dim3(grid_for((u64)T1 * ng, 256)), dim3(256), 0, st, (const DGate *)(ws + L.dgates), ng,
+                           (const uint64_t *)frames, count, (const int32_t *)nins, n_traj, (const double *)nm, nnoise, tv, tc);
+        QS_LAUNCH_CHECK("traj_vals");
+        for (int k = 0; k < np; ++k) {
+            const u64 blocks = (u64)T1 << passes[k].nrest;
+            const cx<R> *in = k == 0 ? nullptr : ibuf[(np - k) & 1];
+            cx<R> *outb = ibuf[(np - 1 - k) & 1];
+            void *a_states = states, *a_tv = tv, *a_tc = tc, *a_nins = nins, *a_first = first_gate, *a_in = (void *)in, *a_out = outb;
+            unsigned long long a_N = N, a_basis = basis;
+            unsigned a_ng = (unsigned)ng;
+            int a_fp = k == 0 ? 1 : 0, a_nt = n_traj;
+            void *args[] = {&a_states, &a_N, &a_tv, &a_tc, &a_ng, &a_fp, &a_basis, &a_nins, &a_first, &a_nt, &a_in, &a_out};
+            QS_HIP(hipModuleLaunchKernel(jfn[k], (unsigned)blocks, 1, 1, kTileThreads, 1, 1, 0, st, args, nullptr));
+        }
+    } else {
+        for (int k = 0; k < np; ++k) {
+            const DPass &P = passes[k];
+            const int tiles_log2 = P.nrest;
+            const u64 blocks = (u64)T1 << tiles_log2;
+            const cx<R> *in = k == 0 ? nullptr : ibuf[(np - k) & 1];
+            cx<R> *outb = ibuf[(np - 1 - k) & 1];
+            hipLaunchKernelGGL((k_traj_pass<R, TBMAX>), dim3((unsigned)blocks), dim3(kTileThreads), 0, st, states, N, tiles_log2, P,
+                               (const DGate *)(ws + L.dgates), (const uint64_t *)frames, count, k == 0 ? 1 : 0, basis, (const int32_t *)nins,
+                               (const int32_t *)first_gate, n_traj, (const double *)nm, nnoise, in, outb);
+            QS_LAUNCH_CHECK("traj_pass");
+        }
     }
     double *pzf = (double *)(ws + L.pzf), *px = (double *)(ws + L.px);
     const int chunks = 1 << L.chunks_log2;

@@ -550,12 +550,17 @@ class Swarm:
 
 def traj_run(n: int, gates: np.ndarray, basis_index: int, n_traj: int, p: float, seed: int, dtype=torch.complex128,
              log_cap: int = 0, prob_mean: bool = True, device="cuda", stream=None, T1: float = math.inf, T2: float = math.inf,
-             diag: torch.Tensor | None = None) -> dict:
+             diag: torch.Tensor | None = None, readouts=("z", "x", "fid")) -> dict:
     """Noise trajectories with stochastic Pauli insertion (probability p per
     touched qubit) and stochastic noise gates (kind 5, timescales T1, T2).
     Returns device tensors: z, x [n_traj, n]; fid [n_traj]; counts [n_traj];
     prob_mean [2^n]; log [n_traj, log_cap]; diag [n_traj] (per-trajectory
-    expectation of the diagonal observable `diag`, a float64 [2^n] device tensor)."""
+    expectation of the diagonal observable `diag`, a float64 [2^n] device tensor).
+    `readouts` names which of z, x, fid are computed (the others are absent
+    from the result; <X_q> costs a read of every state per qubit)."""
+    bad = set(readouts) - {"z", "x", "fid"}
+    if bad:
+        raise ValueError(f"unknown read-outs {sorted(bad)}")
     g = np.ascontiguousarray(gates, dtype=W.GATE_DTYPE)
     code = QS_C128 if dtype == torch.complex128 else QS_C64
     nbytes = ctypes.c_size_t()
@@ -564,8 +569,8 @@ def traj_run(n: int, gates: np.ndarray, basis_index: int, n_traj: int, p: float,
     with torch.cuda.stream(s):  # workspace and outputs belong to the stream the kernels run on
         ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
         f64 = dict(dtype=torch.float64, device=device)
-        res = {"z": torch.empty(n_traj, n, **f64), "x": torch.empty(n_traj, n, **f64), "fid": torch.empty(n_traj, **f64),
-               "counts": torch.empty(n_traj, dtype=torch.int32, device=device)}
+        res = {k: torch.empty((n_traj, n) if k != "fid" else (n_traj,), **f64) for k in ("z", "x", "fid") if k in readouts}
+        res["counts"] = torch.empty(n_traj, dtype=torch.int32, device=device)
         if prob_mean:
             res["prob_mean"] = torch.empty(1 << n, **f64)
         if log_cap:
@@ -573,7 +578,8 @@ def traj_run(n: int, gates: np.ndarray, basis_index: int, n_traj: int, p: float,
         if diag is not None:
             assert diag.dtype == torch.float64 and diag.is_cuda and diag.numel() == 1 << n
             res["diag"] = torch.empty(n_traj, **f64)
-    out = TrajOut(res["z"].data_ptr(), res["x"].data_ptr(), res["fid"].data_ptr(),
+    opt = lambda k: res[k].data_ptr() if k in res else None  # noqa: E731
+    out = TrajOut(opt("z"), opt("x"), opt("fid"),
                   res["prob_mean"].data_ptr() if prob_mean else None, res["counts"].data_ptr(),
                   res["log"].data_ptr() if log_cap else None, log_cap,
                   diag.data_ptr() if diag is not None else None, res["diag"].data_ptr() if diag is not None else None)

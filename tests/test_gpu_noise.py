@@ -66,6 +66,12 @@ def test_noise_qaoa16_p4_against_oracle():
     check_val(r["diag"].cpu().numpy(), ref["diag"], "c128", "per-trajectory <C>")
     check_val(r["fid"].cpu().numpy(), ref["fid"], "c128", "fidelity")
     check_val(r["x"].cpu().numpy(), ref["x"], "c128", "<X_q>")
+    # Only the diagonal read-out asked for: the same per-trajectory values,
+    # bit for bit, and no <X_q> / <Z_q> / fidelity outputs.
+    r2 = traj_run(n, gates, 0, T, 0.0, 31, T1=500.0, T2=250.0, diag=torch.tensor(d, device="cuda"), prob_mean=False, readouts=())
+    assert not {"x", "z", "fid"} & set(r2)
+    assert np.array_equal(r2["diag"].cpu().numpy(), r["diag"].cpu().numpy())
+    assert np.array_equal(r2["counts"].cpu().numpy(), r["counts"].cpu().numpy())
     # the noiseless energy of the same circuit
     e0 = oracle.qaoa_energy(n, edges, p, theta)
     ideal = oracle.init_basis(n, 0)

@@ -124,9 +124,23 @@ def sweep_bench(n, steps, warmup):
         b.synchronize()
         copy_t.append(a.elapsed_time(b) * 1e-3)
     copy_gbs = 2 * (16 << n) / min(copy_t) / 1e9
-    del s, dst
+    del dst
+    # The same sweep as one fused block on the same register: read+write
+    # passes instead of one pass per gate.
+    from paper_2001_10554_amd.qsim import block_passes
+    gates = W.gates_array([W.gate(W.G_1Q, q, -1, m) for q, m in enumerate(mats)]
+                          + [W.gate(W.G_C1Q, c, t, X) for c, t in cnots])
+    log("timing the sweep as one fused block")
+    t_fused = _time_cuda(lambda: s.apply_block(gates), 2)
+    passes = block_passes(n, gates)
+    gate_by_gate = sum(statistics.median(v) for v in per_1q.values()) + sum(statistics.median(v) for v in per_cx.values())
+    fused = {"workload": f"the same {n}-qubit sweep ({len(gates)} gates) as one fused block", "passes": passes,
+             "ms": round(t_fused * 1e3, 3), "pass_GB_per_s": round(passes * 2 * (16 << n) / t_fused / 1e9, 1),
+             "pass_frac": round(passes * 2 * (16 << n) / t_fused / 1e9 / PEAK_HBM_GBS, 4),
+             "gate_by_gate_ms": round(gate_by_gate * 1e3, 3), "speedup": round(gate_by_gate / t_fused, 2)}
+    del s
     torch.cuda.empty_cache()
-    return wall, per_1q, per_cx, norm, copy_gbs
+    return wall, per_1q, per_cx, norm, copy_gbs, fused
 
 
 def _time_cuda(fn, reps):
@@ -571,7 +585,7 @@ def main():
         print(json.dumps({"section": args.section, **SECTIONS[args.section]()}), flush=True)
         return
     n = args.n
-    wall, per_1q, per_cx, norm, copy_gbs = sweep_bench(n, args.steps, args.warmup)
+    wall, per_1q, per_cx, norm, copy_gbs, fused = sweep_bench(n, args.steps, args.warmup)
     bytes_1q = 2 * (1 << n) * 16
     t1q = sum(sum(v) for v in per_1q.values())
     launches_1q = sum(len(v) for v in per_1q.values())
@@ -615,6 +629,7 @@ def main():
         "device_copy_gbs": round(copy_gbs, 1),
         "value_over_device_copy": round(gbs / copy_gbs, 3),
         "norm_after": norm,
+        f"fused{n}": fused,
     }
     if args.curves:
         CURVES["enabled"] = True

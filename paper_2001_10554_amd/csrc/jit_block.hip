@@ -245,6 +245,11 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
     };
     const bool prefetch = env("QSIM_JIT_PREFETCH", 1) != 0;
     const int waves = env("QSIM_JIT_WAVES", 4);
+    // QSIM_JIT_ORDER=k (k > 0): the tile counter's first k bits go to the k
+    // lowest non-tile qubits and its other bits to the remaining non-tile
+    // qubits from the highest down, so that the tiles in flight at one time
+    // spread over distant parts of the state instead of one contiguous stretch.
+    const int order_k = env("QSIM_JIT_ORDER", 0);
     const int TB = tile_bits_max(dtype);
     const int TS = 1 << TB, NT = kTileThreads, PER = TS / NT;
     static const int kSwz128[12] = {1, 2, 4, 8, 15, 12, 9, 3, 6, 14, 6, 0};
@@ -262,11 +267,11 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
     gen.G = (TS / 8) / NT;
     std::string &o = gen.o;
     o += dtype == QS_C128 ? "typedef double R;\n" : "typedef float R;\n";
+    o += "typedef __attribute__((address_space(4))) const R CR;\n";
     o += "typedef R C __attribute__((ext_vector_type(2)));\n"
          "__device__ __forceinline__ C row(R a, R b, R c, R d, C x, C y) {\n"
          "  C r; r.x = a * x.x - b * x.y + c * y.x - d * y.y; r.y = a * x.y + b * x.x + c * y.y + d * y.x; return r; }\n"
          "__device__ __forceinline__ C cm(C x, R a, R b) { C r; r.x = a * x.x - b * x.y; r.y = a * x.y + b * x.x; return r; }\n"
-
          "__device__ __forceinline__ unsigned ins(unsigned x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u)); }\n";
     // LDS slot of tile index m: m ^ hsw(m), hsw XOR-ing a fixed pattern into
     // the low SB bits for each set bit of m at or above SB (a bijection).  The
@@ -295,8 +300,12 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
                 if (((u64)k << 9 >> b) & 1) off |= 1ull << P.T[b];
             hi[k] = off;
         }
-        const std::string dep_tile = deposit("(unsigned long long)tile", P.rest, P.nrest);
-        const std::string dep_next = deposit("(unsigned long long)nx", P.rest, P.nrest);
+        uint8_t rest_order[40];
+        for (int b = 0; b < P.nrest; ++b) rest_order[b] = P.rest[b];
+        if (order_k > 0 && order_k < P.nrest)
+            for (int b = order_k; b < P.nrest; ++b) rest_order[b] = P.rest[P.nrest - 1 - (b - order_k)];
+        const std::string dep_tile = deposit("(unsigned long long)tile", rest_order, P.nrest);
+        const std::string dep_next = deposit("(unsigned long long)nx", rest_order, P.nrest);
         o += "  C pre[" + S(PER) + "];\n";
         o += "  unsigned tile = blockIdx.x;\n";
         if (prefetch) {
@@ -304,13 +313,17 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = psi[b0 | dt | " + hex(hi[k]) + "];\n";
             o += "  }\n";
         }
-        o += "  for (; tile < ntiles; tile += gridDim.x) {\n";
+        const size_t body_at = o.size();  // the loop header goes here
         // Opaque copies of the thread index and the value table per tile, so
         // that the sweeps' LDS addresses and gate values are formed where they
         // are used instead of being hoisted out of the loop, which would hold
-        // every sweep's addresses in registers at once.
+        // every sweep's addresses in registers at once.  The table is read
+        // through the constant address space: its uniform entries then come
+        // from scalar loads, which do not share the vector-memory counter
+        // with the prefetch and the stores (a generic pointer gives flat
+        // loads, and every sweep would wait for the whole prefetch).
         o += "    unsigned tl = t; asm volatile(\"\" : \"+v\"(tl));\n";
-        o += "    const R *__restrict__ vv; { unsigned long long a_ = (unsigned long long)v; asm volatile(\"\" : \"+s\"(a_)); vv = (const R *)a_; }\n";
+        o += "    CR *vv; { unsigned long long a_ = (unsigned long long)v; asm volatile(\"\" : \"+s\"(a_)); vv = (CR *)a_; }\n";
         o += "    const unsigned long long base = " + dep_tile + ";\n";
         // Sweeps of the pass: (first gate, run, group bits).
         struct Sw {
@@ -384,6 +397,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             for (int k = 0; k < PER; ++k) o += "    psi[base | dt | " + hex(hi[k]) + "] = sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u];\n";
             o += "    __syncthreads();\n";
         }
+        o.insert(body_at, "  for (; tile < ntiles; tile += gridDim.x) {\n");
         o += "  }\n}\n";
     }
     return o;

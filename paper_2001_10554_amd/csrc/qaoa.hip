@@ -211,47 +211,28 @@ __device__ __forceinline__ d2v shfl_xor2(d2v v, int m) {
     return r;
 }
 
-// The value of lane ^ 2^LB without the LDS unit (a wavefront shuffle is an
-// LDS instruction, and the backward passes wait on LDS issue for nearly half
-// of their time): DPP quad permutes for bits 0 and 1, a half-row / row mirror
-// followed by a quad reversal or half-row mirror for bits 2 and 3 (i ^ 7 ^ 3
-// = i ^ 4, i ^ 15 ^ 7 = i ^ 8), and the gfx950 lane-half swaps for bits 4 and
-// 5 (the swap returns the exchanged halves; each lane keeps the half that
-// came from its partner).
+// The value of lane ^ 2^lb.  Bits 0 and 1 use a DPP quad permute (one VALU
+// move per dword); the other bits use ds_bpermute.  A DPP / permlane form of
+// bits 2..5 costs two VALU operations per dword, which run at the FP64 issue
+// rate here and were measured slower than the LDS-unit permutes, whereas the
+// single quad permute takes load off the LDS issue queue that the backward
+// passes wait on.
 template <int CTRL> __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
-template <int LB> __device__ __forceinline__ uint32_t xlane32(uint32_t v) {
-    if constexpr (LB == 0) return dpp32<0xB1>(v);
-    else if constexpr (LB == 1) return dpp32<0x4E>(v);
-    else if constexpr (LB == 2) return dpp32<0x1B>(dpp32<0x141>(v));
-    else if constexpr (LB == 3) return dpp32<0x141>(dpp32<0x140>(v));
-    else if constexpr (LB == 4) {
-        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-        return (threadIdx.x & 16) ? p[0] : p[1];
-    } else {
-        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-        return (threadIdx.x & 32) ? p[0] : p[1];
-    }
-}
-template <int LB> __device__ __forceinline__ d2v xlane2(d2v v) {
+template <int CTRL> __device__ __forceinline__ d2v dpp2(d2v v) {
     const uint64_t a = (uint64_t)__double_as_longlong(v.x), b = (uint64_t)__double_as_longlong(v.y);
     d2v r;
-    r.x = __longlong_as_double((long long)((uint64_t)xlane32<LB>((uint32_t)a) | ((uint64_t)xlane32<LB>((uint32_t)(a >> 32)) << 32)));
-    r.y = __longlong_as_double((long long)((uint64_t)xlane32<LB>((uint32_t)b) | ((uint64_t)xlane32<LB>((uint32_t)(b >> 32)) << 32)));
+    r.x = __longlong_as_double((long long)((uint64_t)dpp32<CTRL>((uint32_t)a) | ((uint64_t)dpp32<CTRL>((uint32_t)(a >> 32)) << 32)));
+    r.y = __longlong_as_double((long long)((uint64_t)dpp32<CTRL>((uint32_t)b) | ((uint64_t)dpp32<CTRL>((uint32_t)(b >> 32)) << 32)));
     return r;
 }
 // Partner value for lane bit lb (run-time; one uniform branch per value,
 // so only the partner is live across it).
 __device__ __forceinline__ d2v lane_partner(d2v v, int lb) {
-    switch (lb) {
-    case 0: return xlane2<0>(v);
-    case 1: return xlane2<1>(v);
-    case 2: return xlane2<2>(v);
-    case 3: return xlane2<3>(v);
-    case 4: return xlane2<4>(v);
-    default: return xlane2<5>(v);
-    }
+    if (lb == 0) return dpp2<0xB1>(v);  // quad_perm [1,0,3,2]
+    if (lb == 1) return dpp2<0x4E>(v);  // quad_perm [2,3,0,1]
+    return shfl_xor2(v, 1 << lb);
 }
 
 __device__ __forceinline__ double qblock_sum(double v, double *sh) {
@@ -723,6 +704,55 @@ __device__ __forceinline__ void rt_ip_cur(const d2v (&lm)[1 << (TB - TT)], const
     if (lanes) rt_ip<TB, TT, 0>(lm, ps, rx, kRegsNone, true, acc);
 }
 
+// Inner products and RX(2 beta) on both vectors, bit by bit: for each bit
+// the inner product is taken with lambda and psi at the same point, then the
+// bit's gate is applied to both (bits of one mixer commute, so every inner
+// product is the one at the mixer's end).  A lane bit exchanges each vector
+// once and uses the partner values for the inner product and both updates.
+template <int TB, int TT, int L>
+__device__ __forceinline__ void rt_ip_rx2(d2v (&lm)[1 << (TB - TT)], d2v (&ps)[1 << (TB - TT)], u32 rx, double cb, double sb, int regs, bool lanes,
+                                          double &acc) {
+    using G = RT<TB, TT>;
+#pragma unroll
+    for (int x = 0; x < G::JB; ++x) {
+        if (regs == kRegsNone || (regs == kRegsLow && x >= G::W)) continue;
+        const bool on = (rx >> G::reg_bit(L, x)) & 1;
+        if (on) {
+#pragma unroll
+            for (int j = 0; j < G::R; ++j) {
+                if ((j >> x) & 1) continue;
+                const int k = j | (1 << x);
+                acc += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
+            }
+        }
+        const double c = on ? cb : 1.0, s = on ? sb : 0.0;
+#pragma unroll
+        for (int j = 0; j < G::R; ++j)
+            if (!((j >> x) & 1)) {
+                rx_pair(lm[j], lm[j | (1 << x)], c, s);
+                rx_pair(ps[j], ps[j | (1 << x)], c, s);
+            }
+    }
+    if (lanes) {
+        const u32 lmask = rx & 63u;
+        const int lo = lmask ? __builtin_ctz(lmask) : 6;
+#pragma unroll 1
+        for (int lb = lo; lb < 6; ++lb) {
+            const bool on = (lmask >> lb) & 1;
+            const double c = on ? cb : 1.0, s = on ? sb : 0.0;
+            double t = 0.0;
+#pragma unroll
+            for (int j = 0; j < G::R; ++j) {
+                const d2v pp = lane_partner(ps[j], lb), pl = lane_partner(lm[j], lb);
+                t += im_conj_mul(lm[j], pp);
+                lm[j] = rx_half(lm[j], pl, c, s);
+                ps[j] = rx_half(ps[j], pp, c, s);
+            }
+            if (on) acc += t;
+        }
+    }
+}
+
 template <typename CT, int TB, int TT, bool POOLED, bool MERGE, bool TABS>
 __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
     using G = RT<TB, TT>;
@@ -790,15 +820,11 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
         double sb2, cb2;
         sincos(q.theta[p + l + 1], &sb2, &cb2);
         const double sn2 = -sb2;
-        rt_ip<TB, TT, 0>(lm, ps, rx, kRegsAll, true, ipb2);
-        rt_rx<TB, TT, 0>(lm, rx, cb2, sn2, kRegsAll, true);
-        rt_rx<TB, TT, 0>(ps, rx, cb2, sn2, kRegsAll, true);
+        rt_ip_rx2<TB, TT, 0>(lm, ps, rx, cb2, sn2, kRegsAll, true, ipb2);
         if (l1) {
             rt_transpose<TB, TT, 0>(lm, sh);
             rt_transpose<TB, TT, 0>(ps, sh);
-            rt_ip<TB, TT, 1>(lm, ps, rx, kRegsLow, false, ipb2);
-            rt_rx<TB, TT, 1>(lm, rx, cb2, sn2, kRegsLow, false);
-            rt_rx<TB, TT, 1>(ps, rx, cb2, sn2, kRegsLow, false);
+            rt_ip_rx2<TB, TT, 1>(lm, ps, rx, cb2, sn2, kRegsLow, false, ipb2);
             in_l1 = true;
         }
         // The cost phase between the two mixers, in the current layout.  Its

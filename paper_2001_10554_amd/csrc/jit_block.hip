@@ -250,6 +250,15 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
     // qubits from the highest down, so that the tiles in flight at one time
     // spread over distant parts of the state instead of one contiguous stretch.
     const int order_k = env("QSIM_JIT_ORDER", 0);
+    // QSIM_JIT_XCD=1: workgroup b (on XCD b mod 8) starts at tile
+    // (b mod 8) * (grid / 8) + b / 8, so that neighbouring tiles run on one
+    // XCD at the same time.  QSIM_JIT_NT=1: non-temporal state loads/stores.
+    const bool xcd = env("QSIM_JIT_XCD", 0) != 0;
+    const bool nt = env("QSIM_JIT_NT", 0) != 0;
+    auto ld = [&](const std::string &addr) { return nt ? "__builtin_nontemporal_load(psi + (" + addr + "))" : "psi[" + addr + "]"; };
+    auto stv = [&](const std::string &addr, const std::string &v) {
+        return nt ? "__builtin_nontemporal_store(" + v + ", psi + (" + addr + "));\n" : "psi[" + addr + "] = " + v + ";\n";
+    };
     const int TB = tile_bits_max(dtype);
     const int TS = 1 << TB, NT = kTileThreads, PER = TS / NT;
     static const int kSwz128[12] = {1, 2, 4, 8, 15, 12, 9, 3, 6, 14, 6, 0};
@@ -307,10 +316,13 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         const std::string dep_tile = deposit("(unsigned long long)tile", rest_order, P.nrest);
         const std::string dep_next = deposit("(unsigned long long)nx", rest_order, P.nrest);
         o += "  C pre[" + S(PER) + "];\n";
-        o += "  unsigned tile = blockIdx.x;\n";
+        if (xcd)
+            o += "  unsigned tile = (gridDim.x & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);\n";
+        else
+            o += "  unsigned tile = blockIdx.x;\n";
         if (prefetch) {
             o += "  if (tile < ntiles) {\n    const unsigned long long b0 = " + dep_tile + ";\n";
-            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = psi[b0 | dt | " + hex(hi[k]) + "];\n";
+            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = " + ld("b0 | dt | " + hex(hi[k])) + ";\n";
             o += "  }\n";
         }
         const size_t body_at = o.size();  // the loop header goes here
@@ -352,11 +364,11 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         auto issue_prefetch = [&]() {
             if (!prefetch) return;
             o += "    { const unsigned nx = tile + gridDim.x;\n      if (nx < ntiles) {\n        const unsigned long long nb = " + dep_next + ";\n";
-            for (int k = 0; k < PER; ++k) o += "        pre[" + S(k) + "] = psi[nb | dt | " + hex(hi[k]) + "];\n";
+            for (int k = 0; k < PER; ++k) o += "        pre[" + S(k) + "] = " + ld("nb | dt | " + hex(hi[k])) + ";\n";
             o += "      }\n    }\n";
         };
         if (!prefetch)
-            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = psi[base | dt | " + hex(hi[k]) + "];\n";
+            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = " + ld("base | dt | " + hex(hi[k])) + ";\n";
         if (!first_regs) {
             for (int k = 0; k < PER; ++k) o += "    sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u] = pre[" + S(k) + "];\n";
             o += "    __syncthreads();\n";
@@ -382,7 +394,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             if (to_global) {
                 for (int g = 0; g < gen.G; ++g)
                     for (int j = 0; j < 8; ++j)
-                        o += "      psi[base | dt | " + hex(hi_of((u32)(g * NT) + grp_off(w, j))) + "] = " + nm[g][j] + ";\n";
+                        o += "      " + stv("base | dt | " + hex(hi_of((u32)(g * NT) + grp_off(w, j))), nm[g][j]);
             } else {
                 for (int g = 0; g < gen.G; ++g)
                     for (int j = 0; j < 8; ++j) o += "      sh[s" + S(g) + " ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u] = " + nm[g][j] + ";\n";
@@ -391,10 +403,10 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             if (from_regs) issue_prefetch();
         }
         if (sw.empty()) {  // a pass without gates: copy the tile back
-            for (int k = 0; k < PER; ++k) o += "    psi[base | dt | " + hex(hi[k]) + "] = sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u];\n";
+            for (int k = 0; k < PER; ++k) o += "    " + stv("base | dt | " + hex(hi[k]), "sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u]");
             o += "    __syncthreads();\n";
         } else if (!last_regs) {
-            for (int k = 0; k < PER; ++k) o += "    psi[base | dt | " + hex(hi[k]) + "] = sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u];\n";
+            for (int k = 0; k < PER; ++k) o += "    " + stv("base | dt | " + hex(hi[k]), "sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u]");
             o += "    __syncthreads();\n";
         }
         o.insert(body_at, "  for (; tile < ntiles; tile += gridDim.x) {\n");

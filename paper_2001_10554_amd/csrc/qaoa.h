@@ -30,16 +30,17 @@ struct QEdge {
     uint8_t a, b, wi, pad;
 };
 
-// One pass.  Edge lists are classified for the two register layouts of the
-// register-tiled kernels (list 0 also serves the LDS kernels).
+// One pass.  Edge lists are classified for the three register layouts of
+// the register-tiled kernels (list 0 also serves the LDS kernels).
 struct QPass {
     int tb, nrest, layer, flags, pidx;
     uint32_t rx_mask;  // tile bits that receive RX
-    int use_l1;        // some RX bit is only reachable in the second layout
+    int use_l2;        // register-tiled kernels: upper lane bits take RX in the third layout
+    int lay_mid;       // register-tiled forward kernel: the layout its first mixer ends in
     alignas(4) uint8_t T[16];     // read as 32-bit words on the device
     alignas(4) uint8_t rest[40];
-    int32_t cnt[2][EC_N];  // 32-bit: read with scalar loads at a run-time layout index
-    QEdge e[2][kQMaxEdges];
+    int32_t cnt[3][EC_N];  // 32-bit: read with scalar loads at a run-time layout index
+    QEdge e[3][kQMaxEdges];
 };
 
 struct QWeights {

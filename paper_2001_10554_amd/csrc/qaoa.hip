@@ -459,30 +459,62 @@ __global__ __launch_bounds__(kLdsThreads) void k_qaoa_bwd_lds(QPass Parg, QWeigh
 
 // ================================================================== register-tiled kernels (n >= 10)
 
+// Thread maps of a (TB, TT) tile.  Thread t = lane bits 0..5 and wave bits
+// 6..TT-1; each thread holds registers j = 0..R-1 (JB bits).  Three layouts:
+//   L0  thread bit b -> tile bit b, register bit x -> tile bit TT + x
+//       (a wavefront's loads and stores cover 1 KiB contiguous);
+//   L1  the wave bits trade places with register bits 0..W-1;
+//   L2  lane bits LS..5 trade places with register bits 0..S-1 (S = min(3, JB)).
+// RX on a tile bit is a register-pair update in a layout that holds the bit
+// in a register, or an update across lanes (wavefront exchanges).  The
+// forward kernel walks all three layouts: when a pass uses L2, only lane bits
+// below LS need exchanges, as an LDS transpose of the register array costs
+// less than exchanging every register for three lane bits.  The backward
+// kernel, which carries two vectors, uses L0 and L1 only: there the third
+// layout's extra transposes and the psi updates it needs before them cost
+// more (measured) than the exchanges they save.
 template <int TB, int TT> struct RT {
     static constexpr int NT = 1 << TT, W = TT - 6, JB = TB - TT, R = 1 << JB, TS = 1 << TB;
+    static constexpr int S = JB < 3 ? JB : 3, LS = 6 - S;
     static_assert(JB >= W, "the second layout needs a register bit per wave bit");
-    __device__ static int m0(int t, int j) { return t | (j << TT); }
-    __device__ static int m1(int t, int j) { return (t & 63) | ((j & ((1 << W) - 1)) << 6) | ((t >> 6) << TT) | ((j >> W) << (TT + W)); }
-    // tile bit of register bit x in layout L
-    __host__ __device__ static constexpr int reg_bit(int L, int x) { return L == 0 ? TT + x : (x < W ? 6 + x : TT + x); }
+    // The layout is a uniform run-time value; the maps below select between
+    // the three forms without branching, so one copy of the code (and one
+    // set of registers) serves every layout.
+    // tile index of (thread t, register j) in layout L: tpart(L, t) | jpart(L, j)
+    __device__ static int tpart(int L, int t) {
+        constexpr int lmask = ((1 << S) - 1) << LS;
+        const int t1 = (t & 63) | ((t >> 6) << TT);
+        const int t2 = (t & ~lmask) | (((t >> LS) & ((1 << S) - 1)) << TT);
+        return L == 0 ? t : L == 1 ? t1 : t2;
+    }
+    __device__ static int jpart(int L, int j) {
+        const int j1 = ((j & ((1 << W) - 1)) << 6) | ((j >> W) << (TT + W));
+        const int j2 = ((j & ((1 << S) - 1)) << LS) | ((j >> S) << (TT + S));
+        return L == 0 ? j << TT : L == 1 ? j1 : j2;
+    }
+    // tile bit of register bit x / of thread bit b in layout L
+    __host__ __device__ static constexpr int reg_bit(int L, int x) {
+        return L == 0 ? TT + x : L == 1 ? (x < W ? 6 + x : TT + x) : (x < S ? LS + x : TT + x);
+    }
+    __host__ __device__ static constexpr int thr_bit(int L, int b) {
+        return L == 0 ? b : L == 1 ? (b < 6 ? b : TT + (b - 6)) : (b >= LS && b < 6 ? TT + (b - LS) : b);
+    }
+    // tile bits layout L holds in registers
+    __host__ __device__ static constexpr u32 regs(int L) {
+        u32 r = 0;
+        for (int x = 0; x < JB; ++x) r |= 1u << reg_bit(L, x);
+        return r;
+    }
 };
 
 // Global offsets (relative to the tile base) of the thread's amplitudes in layout L.
-template <int TB, int TT, int L>
-__device__ __forceinline__ void rt_offsets(const QPass &P, int t, u64 (&off)[1 << (TB - TT)]) {
+template <int TB, int TT>
+__device__ __forceinline__ void rt_offsets(const QPass &P, int t, int L, u64 (&off)[1 << (TB - TT)]) {
     using G = RT<TB, TT>;
     // Branch-free in t, so the map entries are uniform scalar loads.
     u64 ot = 0;
-    if (L == 0) {
 #pragma unroll
-        for (int b = 0; b < TT; ++b) ot |= (u64)((t >> b) & 1) << pbyte(P.T, b);
-    } else {
-#pragma unroll
-        for (int b = 0; b < 6; ++b) ot |= (u64)((t >> b) & 1) << pbyte(P.T, b);
-#pragma unroll
-        for (int w = 0; w < G::W; ++w) ot |= (u64)((t >> (6 + w)) & 1) << pbyte(P.T, TT + w);
-    }
+    for (int b = 0; b < TT; ++b) ot |= (u64)((t >> b) & 1) << pbyte(P.T, G::thr_bit(L, b));
 #pragma unroll
     for (int j = 0; j < G::R; ++j) {
         u64 o = ot;
@@ -493,18 +525,174 @@ __device__ __forceinline__ void rt_offsets(const QPass &P, int t, u64 (&off)[1 <
     }
 }
 
-// LDS transpose of one register array between the layouts (ends with a barrier).
-template <int TB, int TT, int FROM>
-__device__ __forceinline__ void rt_transpose(d2v (&a)[1 << (TB - TT)], d2v *sh) {
+// LDS transpose of one register array from layout `from` to layout `to`
+// (ends with a barrier).
+template <int TB, int TT>
+__device__ __forceinline__ void rt_xpose(d2v (&a)[1 << (TB - TT)], d2v *sh, int from, int to) {
     using G = RT<TB, TT>;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, tf = G::tpart(from, t), tt = G::tpart(to, t);
 #pragma unroll
-    for (int j = 0; j < G::R; ++j) sh[FROM == 0 ? G::m0(t, j) : G::m1(t, j)] = a[j];
+    for (int j = 0; j < G::R; ++j) sh[tf | G::jpart(from, j)] = a[j];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < G::R; ++j) a[j] = sh[FROM == 0 ? G::m1(t, j) : G::m0(t, j)];
+    for (int j = 0; j < G::R; ++j) a[j] = sh[tt | G::jpart(to, j)];
     __syncthreads();
 }
+
+// RX(2 beta), (cb, sb) = (cos beta, sin beta), on the register bits of layout
+// L whose tile bits are in `todo` (a uniform skip for the others: a walk
+// revisits bits that an earlier layout has done).
+template <int TB, int TT>
+__device__ __forceinline__ void rt_rx_regs(d2v (&a)[1 << (TB - TT)], u32 todo, double cb, double sb, int L) {
+    using G = RT<TB, TT>;
+#pragma unroll
+    for (int x = 0; x < G::JB; ++x) {
+        if (!((todo >> G::reg_bit(L, x)) & 1)) continue;
+#pragma unroll
+        for (int j = 0; j < G::R; ++j)
+            if (!((j >> x) & 1)) rx_pair(a[j], a[j | (1 << x)], cb, sb);
+    }
+}
+
+// Lane bits (a mask below 64; every layout keeps lane bits 0..LS-1 on tile
+// bits 0..LS-1, and L0 / L1 keep all six) through wavefront exchanges, one
+// bit at a time.
+template <int R>
+__device__ __forceinline__ void rt_rx_lanes(d2v (&a)[R], u32 lanes, double cb, double sb) {
+#pragma unroll 1
+    for (u32 m = lanes; m; m &= m - 1) {
+        const int lb = __builtin_ctz(m);
+#pragma unroll
+        for (int j = 0; j < R; ++j) a[j] = rx_half(a[j], lane_partner(a[j], lb), cb, sb);
+    }
+}
+
+// Next layout of a mixer walk: one that holds some of the remaining bits in
+// registers, L0 last (stores from L0 cover 1 KiB per wavefront).
+template <int TB, int TT>
+__device__ __forceinline__ int rt_next(u32 todo, int cur) {
+    using G = RT<TB, TT>;
+    if (cur != 2 && (todo & G::regs(2))) return 2;
+    if (cur != 1 && (todo & G::regs(1))) return 1;
+    return 0;
+}
+
+template <int TB, int TT>
+__device__ __forceinline__ u32 rt_regs(int L) {
+    using G = RT<TB, TT>;
+    return L == 0 ? G::regs(0) : L == 1 ? G::regs(1) : G::regs(2);
+}
+
+// One mixer: RX(cb, sb) on every tile bit of `todo`, starting in layout
+// `cur`: the exchange lane bits `xl`, the current layout's register bits,
+// then the layouts that hold the remaining bits (every tile bit is a lane
+// bit below LS, in `xl`, or a register bit of some layout, so at most three
+// layouts are visited).  Returns the final layout.
+template <int TB, int TT>
+__device__ __forceinline__ int rt_mixer(d2v (&a)[1 << (TB - TT)], d2v *sh, u32 todo, u32 xl, double cb, double sb, int cur) {
+    rt_rx_lanes(a, todo & xl, cb, sb);
+    todo &= ~xl;
+#pragma unroll 1
+    for (int step = 0; step < 3; ++step) {
+        const u32 here = todo & rt_regs<TB, TT>(cur);
+        rt_rx_regs<TB, TT>(a, here, cb, sb, cur);
+        todo &= ~here;
+        if (!todo) break;
+        const int next = rt_next<TB, TT>(todo, cur);
+        rt_xpose<TB, TT>(a, sh, cur, next);
+        cur = next;
+    }
+    return cur;
+}
+
+// Lane bits a pass updates through exchanges: all six, or those below LS
+// when the pass uses the third layout.
+template <int TB, int TT>
+__device__ __forceinline__ u32 rt_exchange_lanes(const QPass &P) {
+    return P.use_l2 ? (1u << RT<TB, TT>::LS) - 1u : 63u;
+}
+
+// TABS: the pass applies a cost phase from a table (unit weights: the first
+// pass, a pass ending in a phase, a merged pass).  Passes without one leave
+// the tables out, which lowers the block's LDS and lets more blocks share a CU.
+template <typename CT, int TB, int TT, bool POOLED, bool MERGE, bool TABS>
+__global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
+    using G = RT<TB, TT>;
+    constexpr int R = G::R, JB = G::JB;
+    __shared__ d2v sh[G::TS];
+    __shared__ d2v tab_a[TABS ? kQMaxEdges + 1 : 1], tab_b[TABS ? kQMaxEdges + 1 : 1];
+    __shared__ double red[16];
+    const QCirc q = qcirc<POOLED>(Parg, geo, B);
+    const QPass &P = *q.P;
+    const d2v *in = B.in_off >= 0 ? (const d2v *)(q.region + B.in_off) : nullptr;
+    d2v *out = B.out_off >= 0 ? (d2v *)(q.region + B.out_off) : nullptr;
+    const int t = threadIdx.x, l = P.layer, p = geo.p;
+    const u64 base = qtile_base(P, q.tile);
+    // Merged passes are never first or last and carry no end phase.
+    constexpr bool merge = MERGE;
+    const bool first = !MERGE && (P.flags & QF_FIRST), pend = !MERGE && (P.flags & QF_PHASE_END), last = !MERGE && (P.flags & QF_LAST);
+    const double g_a = q.theta[l], g_b = pend || merge ? q.theta[l + 1] : 0.0;
+    if constexpr (TABS) {
+        if (!geo.weighted) {
+            if (first) fill_table(tab_a, geo.num_edges, g_a);
+            if (pend || merge) fill_table(tab_b, geo.num_edges, g_b);
+        }
+    }
+    // Cut values of the phase after the first mixer, in the layout that
+    // mixer ends in (the plan's lay_mid), computed while the loads are in
+    // flight.
+    CT C0[R], C1[R];
+    if (first) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, C0);
+    if (pend || last || merge) cut_values<CT, JB>(P, P.lay_mid, W, geo.weighted, base, t, C1);
+    __syncthreads();
+    const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
+    d2v a[R];
+    {
+        u64 off[R];
+        rt_offsets<TB, TT>(P, t, 0, off);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (first) {
+                const d2v f = Phase<CT>::get(tab_a, g_a, C0[j]);
+                a[j].x = amp0 * f.x;
+                a[j].y = amp0 * f.y;
+            } else {
+                a[j] = ld<true>(in + (base | off[j]));
+            }
+        }
+    }
+    double sb, cb;
+    sincos(q.theta[p + l], &sb, &cb);  // RX(2 beta): cos(beta), sin(beta)
+    const u32 rx = P.rx_mask, xl = rt_exchange_lanes<TB, TT>(P);
+    int cur = rt_mixer<TB, TT>(a, sh, rx, xl, cb, sb, 0);
+    if constexpr (MERGE) {
+        // exp(-i gamma_{l+1} C), then layer l+1's RX gates on the same bits,
+        // starting in the layout the first set ended in.
+#pragma unroll
+        for (int j = 0; j < R; ++j) a[j] = cmul2(a[j], Phase<CT>::get(tab_b, g_b, C1[j]));
+        double sb2, cb2;
+        sincos(q.theta[p + l + 1], &sb2, &cb2);
+        cur = rt_mixer<TB, TT>(a, sh, rx, xl, cb2, sb2, cur);
+    }
+    int ts = t;
+    asm volatile("" : "+v"(ts));  // offsets formed here, not kept live through the pass
+    u64 off[R];
+    rt_offsets<TB, TT>(P, ts, cur, off);
+    double e_acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        d2v v = a[j];
+        if (pend) v = cmul2(v, Phase<CT>::get(tab_b, g_b, C1[j]));
+        if (last) e_acc += (double)C1[j] * (v.x * v.x + v.y * v.y);
+        if (out) st<true>(out + (base | off[j]), v);
+    }
+    if (last) {
+        const double s = qblock_sum(e_acc, red);
+        if (t == 0) ((double *)(q.region + B.epart_off))[q.tile] = s;
+    }
+}
+
+// ------------------------------------------------------------ backward helpers (L0 and L1)
 
 // Which register bits a helper covers: none, register bits 0..W-1 (the bits
 // the other layout holds as wave bits), or all.
@@ -518,7 +706,7 @@ enum { kRegsNone = 0, kRegsLow = 1, kRegsAll = 2 };
 // in-place update of the register array makes the compiler copy the whole
 // array, and register bits almost always take the gate.
 template <int TB, int TT, int L>
-__device__ __forceinline__ void rt_rx(d2v (&a)[1 << (TB - TT)], u32 rx, double cb, double sb, int regs, bool lanes) {
+__device__ __forceinline__ void rt_rx_sel(d2v (&a)[1 << (TB - TT)], u32 rx, double cb, double sb, int regs, bool lanes) {
     using G = RT<TB, TT>;
 #pragma unroll
     for (int x = 0; x < G::JB; ++x) {
@@ -560,105 +748,14 @@ __device__ __forceinline__ void rt_rx_cur(d2v (&a)[1 << (TB - TT)], u32 rx, doub
         for (int j = 0; j < G::R; ++j)
             if (!((j >> x) & 1)) rx_pair(a[j], a[j | (1 << x)], c, s);
     }
-    if (lanes) rt_rx<TB, TT, 0>(a, rx, cb, sb, kRegsNone, true);
-}
-
-// TABS: the pass applies a cost phase from a table (unit weights: the first
-// pass, a pass ending in a phase, a merged pass).  Passes without one leave
-// the tables out, which lowers the block's LDS and lets more blocks share a CU.
-template <typename CT, int TB, int TT, bool POOLED, bool MERGE, bool TABS>
-__global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
-    using G = RT<TB, TT>;
-    constexpr int R = G::R, JB = G::JB;
-    __shared__ d2v sh[G::TS];
-    __shared__ d2v tab_a[TABS ? kQMaxEdges + 1 : 1], tab_b[TABS ? kQMaxEdges + 1 : 1];
-    __shared__ double red[16];
-    const QCirc q = qcirc<POOLED>(Parg, geo, B);
-    const QPass &P = *q.P;
-    const d2v *in = B.in_off >= 0 ? (const d2v *)(q.region + B.in_off) : nullptr;
-    d2v *out = B.out_off >= 0 ? (d2v *)(q.region + B.out_off) : nullptr;
-    const int t = threadIdx.x, l = P.layer, p = geo.p;
-    const u64 base = qtile_base(P, q.tile);
-    // Merged passes are never first or last and carry no end phase.
-    constexpr bool merge = MERGE;
-    const bool first = !MERGE && (P.flags & QF_FIRST), pend = !MERGE && (P.flags & QF_PHASE_END), last = !MERGE && (P.flags & QF_LAST);
-    const bool l1 = P.use_l1;
-    const double g_a = q.theta[l], g_b = pend || merge ? q.theta[l + 1] : 0.0;
-    if constexpr (TABS) {
-        if (!geo.weighted) {
-            if (first) fill_table(tab_a, geo.num_edges, g_a);
-            if (pend || merge) fill_table(tab_b, geo.num_edges, g_b);
-        }
-    }
-    CT C0[R], C1[R];
-    if (first) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, C0);
-    if (pend || last || merge) cut_values<CT, JB>(P, l1 ? 1 : 0, W, geo.weighted, base, t, C1);
-    __syncthreads();
-    const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
-    d2v a[R];
-    {
-        u64 off[R];
-        rt_offsets<TB, TT, 0>(P, t, off);
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            if (first) {
-                const d2v f = Phase<CT>::get(tab_a, g_a, C0[j]);
-                a[j].x = amp0 * f.x;
-                a[j].y = amp0 * f.y;
-            } else {
-                a[j] = ld<true>(in + (base | off[j]));
-            }
-        }
-    }
-    double sb, cb;
-    sincos(q.theta[p + l], &sb, &cb);  // RX(2 beta): cos(beta), sin(beta)
-    const u32 rx = P.rx_mask;
-    // Layout L0: register bits (tile bits TT..TB-1) and lane bits (0..5);
-    // then, if needed, layout L1 for the wave bits 6..6+W-1.
-    rt_rx<TB, TT, 0>(a, rx, cb, sb, kRegsAll, true);
-    if (l1) {
-        rt_transpose<TB, TT, 0>(a, sh);
-        rt_rx<TB, TT, 1>(a, rx, cb, sb, kRegsLow, false);
-    }
-    bool in_l1 = l1;
-    if constexpr (MERGE) {
-        // exp(-i gamma_{l+1} C), then layer l+1's RX gates on the same bits,
-        // starting in the layout the first set ended in and ending in L0.
-#pragma unroll
-        for (int j = 0; j < R; ++j) a[j] = cmul2(a[j], Phase<CT>::get(tab_b, g_b, C1[j]));
-        double sb2, cb2;
-        sincos(q.theta[p + l + 1], &sb2, &cb2);
-        rt_rx_cur<TB, TT>(a, rx, cb2, sb2, l1, true);
-        if (l1) {
-            rt_transpose<TB, TT, 1>(a, sh);
-            rt_rx<TB, TT, 0>(a, rx, cb2, sb2, kRegsLow, false);  // the register bits only L0 holds
-        }
-        in_l1 = false;
-    }
-    u64 off[R];
-    if (in_l1)
-        rt_offsets<TB, TT, 1>(P, t, off);
-    else
-        rt_offsets<TB, TT, 0>(P, t, off);
-    double e_acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        d2v v = a[j];
-        if (pend) v = cmul2(v, Phase<CT>::get(tab_b, g_b, C1[j]));
-        if (last) e_acc += (double)C1[j] * (v.x * v.x + v.y * v.y);
-        if (out) st<true>(out + (base | off[j]), v);
-    }
-    if (last) {
-        const double s = qblock_sum(e_acc, red);
-        if (t == 0) ((double *)(q.region + B.epart_off))[q.tile] = s;
-    }
+    if (lanes) rt_rx_sel<TB, TT, 0>(a, rx, cb, sb, kRegsNone, true);
 }
 
 // Inner products 2 Im<lam|X_j|psi> (without the factor 2) summed over the
-// tile bits j of `rx` that layout L reaches, with the same selection as rt_rx.
+// tile bits j of `rx` that layout L reaches, with the same selection as rt_rx_sel.
 // A lane pair contributes both of its terms, one in each lane.
 template <int TB, int TT, int L>
-__device__ __forceinline__ void rt_ip(const d2v (&lm)[1 << (TB - TT)], const d2v (&ps)[1 << (TB - TT)], u32 rx, int regs, bool lanes, double &acc) {
+__device__ __forceinline__ void rt_ip_sel(const d2v (&lm)[1 << (TB - TT)], const d2v (&ps)[1 << (TB - TT)], u32 rx, int regs, bool lanes, double &acc) {
     using G = RT<TB, TT>;
 #pragma unroll
     for (int x = 0; x < G::JB; ++x) {
@@ -701,7 +798,7 @@ __device__ __forceinline__ void rt_ip_cur(const d2v (&lm)[1 << (TB - TT)], const
             acc += im_conj_mul(lm[j], ps[k]) + im_conj_mul(lm[k], ps[j]);
         }
     }
-    if (lanes) rt_ip<TB, TT, 0>(lm, ps, rx, kRegsNone, true, acc);
+    if (lanes) rt_ip_sel<TB, TT, 0>(lm, ps, rx, kRegsNone, true, acc);
 }
 
 // Inner products and RX(2 beta) on both vectors, bit by bit: for each bit
@@ -710,7 +807,7 @@ __device__ __forceinline__ void rt_ip_cur(const d2v (&lm)[1 << (TB - TT)], const
 // product is the one at the mixer's end).  A lane bit exchanges each vector
 // once and uses the partner values for the inner product and both updates.
 template <int TB, int TT, int L>
-__device__ __forceinline__ void rt_ip_rx2(d2v (&lm)[1 << (TB - TT)], d2v (&ps)[1 << (TB - TT)], u32 rx, double cb, double sb, int regs, bool lanes,
+__device__ __forceinline__ void rt_ip_rx2_sel(d2v (&lm)[1 << (TB - TT)], d2v (&ps)[1 << (TB - TT)], u32 rx, double cb, double sb, int regs, bool lanes,
                                           double &acc) {
     using G = RT<TB, TT>;
 #pragma unroll
@@ -769,7 +866,7 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
     const u64 base = qtile_base(P, q.tile);
     constexpr bool merge = MERGE;
     const bool first = !MERGE && (P.flags & QF_FIRST), pend = !MERGE && (P.flags & QF_PHASE_END), last = !MERGE && (P.flags & QF_LAST);
-    const bool l1 = P.use_l1;
+    const bool l1 = ((P.rx_mask >> 6) & ((1u << G::W) - 1)) != 0;  // some RX bit is a wave bit in L0
     const double g_a = q.theta[l], g_b = pend || merge ? q.theta[l + 1] : 0.0;
     if constexpr (TABS) {
         if (!geo.weighted) {
@@ -790,7 +887,7 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
         if (last || pend) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, Cs);
         __syncthreads();  // phase tables
         u64 off[R];
-        rt_offsets<TB, TT, 0>(P, t, off);
+        rt_offsets<TB, TT>(P, t, 0, off);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             ps[j] = ld<true>(ckpt + (base | off[j]));
@@ -813,19 +910,19 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
     sincos(q.theta[p + l], &sb, &cb);
     const double sn = -sb;  // RX(-2 beta)
     const u32 rx = P.rx_mask;
-    bool in_l1 = false;
+    int lay = 0;  // the layout the registers end in
     if constexpr (MERGE) {
         // Layer l+1's RX gates: inner products at the end point, then undone
         // on both vectors (psi is needed again below), L0 first, then L1.
         double sb2, cb2;
         sincos(q.theta[p + l + 1], &sb2, &cb2);
         const double sn2 = -sb2;
-        rt_ip_rx2<TB, TT, 0>(lm, ps, rx, cb2, sn2, kRegsAll, true, ipb2);
+        rt_ip_rx2_sel<TB, TT, 0>(lm, ps, rx, cb2, sn2, kRegsAll, true, ipb2);
         if (l1) {
-            rt_transpose<TB, TT, 0>(lm, sh);
-            rt_transpose<TB, TT, 0>(ps, sh);
-            rt_ip_rx2<TB, TT, 1>(lm, ps, rx, cb2, sn2, kRegsLow, false, ipb2);
-            in_l1 = true;
+            rt_xpose<TB, TT>(lm, sh, 0, 1);
+            rt_xpose<TB, TT>(ps, sh, 0, 1);
+            rt_ip_rx2_sel<TB, TT, 1>(lm, ps, rx, cb2, sn2, kRegsLow, false, ipb2);
+            lay = 1;
         }
         // The cost phase between the two mixers, in the current layout.  Its
         // inner product Im(conj(lam) C psi) is unchanged by the common unit
@@ -847,33 +944,33 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
         // the rest and is stored from L0.
         rt_ip_cur<TB, TT>(lm, ps, rx, l1, true, ipb);
         if (l1) {
-            rt_rx<TB, TT, 1>(lm, rx, cb, sn, kRegsLow, false);
-            rt_rx<TB, TT, 1>(ps, rx, cb, sn, kRegsLow, false);
-            rt_transpose<TB, TT, 1>(lm, sh);
-            rt_transpose<TB, TT, 1>(ps, sh);
-            rt_ip<TB, TT, 0>(lm, ps, rx, kRegsLow, false, ipb);
+            rt_rx_sel<TB, TT, 1>(lm, rx, cb, sn, kRegsLow, false);
+            rt_rx_sel<TB, TT, 1>(ps, rx, cb, sn, kRegsLow, false);
+            rt_xpose<TB, TT>(lm, sh, 1, 0);
+            rt_xpose<TB, TT>(ps, sh, 1, 0);
+            rt_ip_sel<TB, TT, 0>(lm, ps, rx, kRegsLow, false, ipb);
         }
-        rt_rx<TB, TT, 0>(lm, rx, cb, sn, kRegsAll, true);
-        in_l1 = false;
+        rt_rx_sel<TB, TT, 0>(lm, rx, cb, sn, kRegsAll, true);
+        lay = 0;
     } else {
         // One mixer: inner products of the L0 bits; if some RX bit needs L1,
         // undo the B bits on both, transpose, take the A-bit inner products;
         // psi is then dead and lambda undoes every bit not yet undone.
-        rt_ip<TB, TT, 0>(lm, ps, rx, kRegsAll, true, ipb);
+        rt_ip_sel<TB, TT, 0>(lm, ps, rx, kRegsAll, true, ipb);
         if (l1) {
-            rt_rx<TB, TT, 0>(lm, rx, cb, sn, kRegsLow, false);
-            rt_rx<TB, TT, 0>(ps, rx, cb, sn, kRegsLow, false);
-            rt_transpose<TB, TT, 0>(lm, sh);
-            rt_transpose<TB, TT, 0>(ps, sh);
-            rt_ip<TB, TT, 1>(lm, ps, rx, kRegsLow, false, ipb);
-            in_l1 = true;
+            rt_rx_sel<TB, TT, 0>(lm, rx, cb, sn, kRegsLow, false);
+            rt_rx_sel<TB, TT, 0>(ps, rx, cb, sn, kRegsLow, false);
+            rt_xpose<TB, TT>(lm, sh, 0, 1);
+            rt_xpose<TB, TT>(ps, sh, 0, 1);
+            rt_ip_sel<TB, TT, 1>(lm, ps, rx, kRegsLow, false, ipb);
+            lay = 1;
         }
         rt_rx_cur<TB, TT>(lm, rx, cb, sn, l1, true);
     }
     const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
     if (first) {
         CT Cf[R];
-        cut_values<CT, JB>(P, in_l1 ? 1 : 0, W, geo.weighted, base, t, Cf);
+        cut_values<CT, JB>(P, lay, W, geo.weighted, base, t, Cf);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const d2v f = Phase<CT>::get(tab_a, g_a, Cf[j]);  // phi_1 = 2^{-n/2} exp(-i gamma_1 C)
@@ -885,10 +982,7 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
         int ts = t;
         asm volatile("" : "+v"(ts));
         u64 off[R];
-        if (in_l1)
-            rt_offsets<TB, TT, 1>(P, ts, off);
-        else
-            rt_offsets<TB, TT, 0>(P, ts, off);
+        rt_offsets<TB, TT>(P, ts, lay, off);
 #pragma unroll
         for (int j = 0; j < R; ++j) st<true>(lam + (base | off[j]), lm[j]);
     }
@@ -985,18 +1079,47 @@ std::vector<QShape> qaoa_candidate_shapes(int n) {
     return v;
 }
 
-// Tile bit b -> (is thread bit, index) in layout L of a (TB, TT) tile.
-static void layout_kind(int L, int TT, int b, bool &thread, int &idx) {
-    const int W = TT - 6;
+// Tile bit b -> (is thread bit, index) in layout L of a (TB, TT) tile (the
+// thread maps of RT in the kernels).
+static void layout_kind(int L, int TB, int TT, int b, bool &thread, int &idx) {
+    const int W = TT - 6, S = TB - TT < 3 ? TB - TT : 3, LS = 6 - S;
     if (L == 0) {
         thread = b < TT;
         idx = thread ? b : b - TT;
         return;
     }
-    if (b < 6) { thread = true; idx = b; }
-    else if (b < 6 + W) { thread = false; idx = b - 6; }
-    else if (b < TT + W) { thread = true; idx = 6 + (b - TT); }
+    if (L == 1) {
+        if (b < 6) { thread = true; idx = b; }
+        else if (b < 6 + W) { thread = false; idx = b - 6; }
+        else if (b < TT + W) { thread = true; idx = 6 + (b - TT); }
+        else { thread = false; idx = b - TT; }
+        return;
+    }
+    if (b < LS) { thread = true; idx = b; }
+    else if (b < 6) { thread = false; idx = b - LS; }
+    else if (b < TT) { thread = true; idx = b; }
+    else if (b < TT + S) { thread = true; idx = LS + (b - TT); }
     else { thread = false; idx = b - TT; }
+}
+
+// The layout a mixer walk of the register-tiled forward kernel ends in,
+// from layout `cur` (the same register maps and choice of the next layout as
+// RT, rt_next and rt_mixer on the device).
+static int rt_walk_end(int TB, int TT, uint32_t todo, uint32_t xl, int cur) {
+    const int W = TT - 6, JB = TB - TT, S = JB < 3 ? JB : 3, LS = 6 - S;
+    auto reg_bit = [&](int L, int x) { return L == 0 ? TT + x : L == 1 ? (x < W ? 6 + x : TT + x) : (x < S ? LS + x : TT + x); };
+    auto regs = [&](int L) {
+        uint32_t r = 0;
+        for (int x = 0; x < JB; ++x) r |= 1u << reg_bit(L, x);
+        return r;
+    };
+    todo &= ~xl;
+    for (int step = 0; step < 3; ++step) {
+        todo &= ~regs(cur);
+        if (!todo) break;
+        cur = cur != 2 && (todo & regs(2)) ? 2 : cur != 1 && (todo & regs(1)) ? 1 : 0;
+    }
+    return cur;
 }
 
 int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double *w, QShape shape, QPlan &plan) {
@@ -1088,7 +1211,7 @@ int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double 
     plan.geo = QGeom{n, p, P, tb, 1 << (n - tb), n - tb, num_edges, w != nullptr, (int)seq.size()};
     for (int e = 0; e < num_edges; ++e) plan.W.w[e] = w ? w[e] : 1.0;
     plan.passes.clear();
-    const int TT = shape.TT, Wb = TT - 6;
+    const int TT = shape.TT;
     for (int k = 0; k < (int)seq.size(); ++k) {
         {
             const int l = seq[k].layer, g = seq[k].g;
@@ -1115,19 +1238,30 @@ int build_qplan(int n, int p, int num_edges, const int32_t *edges, const double 
             }
             Q.rx_mask = 0;
             for (int q : groups[g]) Q.rx_mask |= 1u << pos[q];
-            Q.use_l1 = rt && ((Q.rx_mask >> 6) & ((1u << Wb) - 1)) != 0;
+            {
+                // Upper lane bits taking RX: through the third layout unless
+                // QSIM_QAOA_L2=0 (then by wavefront exchanges).
+                static const bool l2_on = [] {
+                    const char *e = getenv("QSIM_QAOA_L2");
+                    return !e || atoi(e) != 0;
+                }();
+                const int S = tb - TT < 3 ? tb - TT : 3;
+                Q.use_l2 = rt && l2_on && S > 0 && ((Q.rx_mask >> (6 - S)) & ((1u << S) - 1)) != 0;
+                const uint32_t xl = Q.use_l2 ? (1u << (6 - S)) - 1u : 63u;
+                Q.lay_mid = rt ? rt_walk_end(tb, TT, Q.rx_mask, xl, 0) : 0;
+            }
             Q.layer = l;
             Q.pidx = k;
             Q.flags = seq[k].flags;
-            for (int L = 0; L < (rt ? 2 : 1); ++L) {
+            for (int L = 0; L < (rt ? 3 : 1); ++L) {
                 std::vector<QEdge> cls[EC_N];
                 for (int e = 0; e < num_edges; ++e) {
                     int u = edges[2 * e], v = edges[2 * e + 1];
                     // kind: 0 = thread bit, 1 = register bit, 2 = fixed per tile
                     int ku = 2, kv = 2, iu = u, iv = v;
                     bool th;
-                    if (pos[u] >= 0) { layout_kind(L, TT, pos[u], th, iu); ku = th ? 0 : 1; }
-                    if (pos[v] >= 0) { layout_kind(L, TT, pos[v], th, iv); kv = th ? 0 : 1; }
+                    if (pos[u] >= 0) { layout_kind(L, tb, TT, pos[u], th, iu); ku = th ? 0 : 1; }
+                    if (pos[v] >= 0) { layout_kind(L, tb, TT, pos[v], th, iv); kv = th ? 0 : 1; }
                     if (ku > kv) {
                         std::swap(ku, kv);
                         std::swap(iu, iv);

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_1q_lane(cx<R> *__restrict__ ps
 // pairs / amplitudes (pair / lane kernel); QSIM_1Q_LCHUNK the lane kernel's
 // block remap; QSIM_C1Q_SPREAD the controlled kernel's spread.
 struct Shape1q {
-    int ppt, nt, lane, dlog, ldlog, cdlog, cppt;
+    int ppt, nt, lane, dlog, ldlog, cdlog, cppt, qdlog, sdlog;
     u32 chunk, lchunk, cchunk, dchunk;
 };
 
@@ -232,11 +232,17 @@ static Shape1q shape_1q() {
         v.chunk = (u32)env("QSIM_1Q_CHUNK", 0x7fffffff);  // 0x7fffffff: per-target schedule below
         v.dlog = (int)env("QSIM_1Q_SPREAD", 11);
         v.ldlog = (int)env("QSIM_1Q_LSPREAD", 11);
-        v.cdlog = (int)env("QSIM_C1Q_SPREAD", 8);  // controlled gates: no gain from spreading (measured)
+        // Controlled gates: a thread's quads 2^11 apart.  Measured per control
+        // on a 32-qubit CNOT(c, c+1) sweep: spreads of 2^9..2^13 raise the
+        // weakest control (c = 7) from 5.46 to 5.6-6.0 TB/s and the mean from
+        // 5.91 to 5.92-5.94 TB/s; 2^11 gave c = 7 its best rate in two runs.
+        v.cdlog = (int)env("QSIM_C1Q_SPREAD", 11);
         v.lchunk = (u32)env("QSIM_1Q_LCHUNK", 0);
         v.cppt = (int)env("QSIM_C1Q_PPT", 2);
         v.cchunk = (u32)env("QSIM_C1Q_CHUNK", 0x7fffffff);  // 0x7fffffff: per-control schedule
         v.dchunk = (u32)env("QSIM_QUAD_CHUNK", 0x7fffffff);  // diagonal / SWAP block remap
+        v.qdlog = (int)env("QSIM_DIAG_SPREAD", 8);          // two-qubit diagonal spread
+        v.sdlog = (int)env("QSIM_SWAP_SPREAD", 11);         // SWAP spread
         return v;
     }();
     return sh;
@@ -251,6 +257,16 @@ static u32 chunk_for_target(int q) {
     if (q <= 12 || q == 17) return 256;
     if (q <= 16) return 128;
     return 16u << ((q - 20) & 3);
+}
+
+// Spread of the two quads of a diagonal / SWAP thread (2^dlog apart; 8 =
+// consecutive 256-quad slices), used when the quad count is a multiple of
+// the region it implies.  Measured on a 30-qubit complex128 register: SWAP
+// gains 1-4% from 2^11 (SWAP(5,25): 5.39 -> 5.62 TB/s of the touched
+// quarters), the diagonal loses 1-2%, so it keeps consecutive slices.
+static int quad_spread(int want, u64 nquads) {
+    const int dlog = want >= 8 && want < 40 ? want : 8;
+    return nquads % (2ull << dlog) ? 8 : dlog;
 }
 
 // Controlled gates with the control outside the 128-byte line, diagonal and
@@ -383,17 +399,19 @@ template <typename R> struct Diag4 {
 
 // Two quads per thread, loads before stores; blocks remapped to XCD runs as
 // for the controlled gate.
+// dlog: the thread's quads are 2^dlog apart (as for the controlled gate).
 template <typename R, int PPT>
 __global__ __launch_bounds__(kBlock) void k_apply_diag2(cx<R> *__restrict__ psi, u64 nquads, int q0, int q1, Diag4<R> d, int touch, u32 chunk,
-                                                        u64 blk0) {
+                                                        int dlog, u64 blk0) {
     const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
     const u64 lb = logical_block(chunk, blk0);
-    const u64 first = lb * (kBlock * PPT) + threadIdx.x;
+    const int rlog = dlog - 8;
+    const u64 first = ((lb >> rlog) * PPT << dlog) + ((lb & ((1ull << rlog) - 1)) << 8) + threadIdx.x;
     cx<R> v[PPT][4];
     u64 base[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const u64 k = first + (u64)j * kBlock;
+        const u64 k = first + ((u64)j << dlog);
         base[j] = insert0(insert0(k, lo), hi);
         if (k < nquads) {
 #pragma unroll
@@ -403,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_diag2(cx<R> *__restrict__ psi,
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        if (first + (u64)j * kBlock >= nquads) continue;
+        if (first + ((u64)j << dlog) >= nquads) continue;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             if (!((touch >> e) & 1)) continue;
@@ -416,15 +434,16 @@ __global__ __launch_bounds__(kBlock) void k_apply_diag2(cx<R> *__restrict__ psi,
 }
 
 template <typename R, int PPT>
-__global__ __launch_bounds__(kBlock) void k_apply_swap(cx<R> *__restrict__ psi, u64 nquads, int a, int b, u32 chunk, u64 blk0) {
+__global__ __launch_bounds__(kBlock) void k_apply_swap(cx<R> *__restrict__ psi, u64 nquads, int a, int b, u32 chunk, int dlog, u64 blk0) {
     const int lo = a < b ? a : b, hi = a < b ? b : a;
     const u64 lb = logical_block(chunk, blk0);
-    const u64 first = lb * (kBlock * PPT) + threadIdx.x;
+    const int rlog = dlog - 8;
+    const u64 first = ((lb >> rlog) * PPT << dlog) + ((lb & ((1ull << rlog) - 1)) << 8) + threadIdx.x;
     cx<R> x[PPT], y[PPT];
     u64 i[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const u64 k = first + (u64)j * kBlock;
+        const u64 k = first + ((u64)j << dlog);
         i[j] = insert0(insert0(k, lo), hi);
         if (k < nquads) {
             x[j] = ld<true>(psi + (i[j] | (1ull << a)));
@@ -433,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_swap(cx<R> *__restrict__ psi, 
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        if (first + (u64)j * kBlock >= nquads) continue;
+        if (first + ((u64)j << dlog) >= nquads) continue;
         st<true>(psi + (i[j] | (1ull << a)), y[j]);
         st<true>(psi + (i[j] | (1ull << b)), x[j]);
     }
@@ -451,8 +470,10 @@ template <typename R> static int launch_diag2_t(qs_state *s, int q0, int q1, con
     if (!touch) return QS_OK;
     const Shape1q v = shape_1q();
     const u32 chunk = v.dchunk == 0x7fffffffu ? chunk_for_control(q0, q1) : v.dchunk;
+    const int dlog = quad_spread(v.qdlog, nquads);
     for_pieces(grid_for(nquads, kBlock * 2), [&](unsigned g, u64 b0) {
-        hipLaunchKernelGGL((k_apply_diag2<R, 2>), dim3(g), dim3(kBlock), 0, s->stream, (cx<R> *)s->buf, nquads, q0, q1, dd, touch, chunk, b0);
+        hipLaunchKernelGGL((k_apply_diag2<R, 2>), dim3(g), dim3(kBlock), 0, s->stream, (cx<R> *)s->buf, nquads, q0, q1, dd, touch, chunk, dlog,
+                           b0);
     });
     QS_LAUNCH_CHECK("apply_diag2");
     return QS_OK;
@@ -466,13 +487,14 @@ int launch_apply_swap(qs_state *s, int a, int b) {
     const u64 nquads = 1ull << (s->n - 2);
     const Shape1q v = shape_1q();
     const u32 chunk = v.dchunk == 0x7fffffffu ? chunk_for_control(a, b) : v.dchunk;
+    const int dlog = quad_spread(v.sdlog, nquads);
     if (s->dtype == QS_C128)
         for_pieces(grid_for(nquads, kBlock * 2), [&](unsigned g, u64 b0) {
-            hipLaunchKernelGGL((k_apply_swap<double, 2>), dim3(g), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, nquads, a, b, chunk, b0);
+            hipLaunchKernelGGL((k_apply_swap<double, 2>), dim3(g), dim3(kBlock), 0, s->stream, (cx<double> *)s->buf, nquads, a, b, chunk, dlog, b0);
         });
     else
         for_pieces(grid_for(nquads, kBlock * 2), [&](unsigned g, u64 b0) {
-            hipLaunchKernelGGL((k_apply_swap<float, 2>), dim3(g), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, nquads, a, b, chunk, b0);
+            hipLaunchKernelGGL((k_apply_swap<float, 2>), dim3(g), dim3(kBlock), 0, s->stream, (cx<float> *)s->buf, nquads, a, b, chunk, dlog, b0);
         });
     QS_LAUNCH_CHECK("apply_swap");
     return QS_OK;

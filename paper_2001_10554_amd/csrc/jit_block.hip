@@ -235,7 +235,20 @@ int gate_value_class(int kind, const double *u) {
 // Source of one kernel per pass (qs_pass0, qs_pass1, ...) for passes whose
 // tile is full (tb = the dtype's tile size).  Returns "" if a pass does not
 // qualify (the caller then uses the interpreter).
-std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype) {
+void jit_tile_shape(int n, int dtype, int &tile_bits, int &threads) {
+    static const int env_tb = [] {
+        const char *e = getenv("QSIM_JIT_TB");
+        return e ? atoi(e) : 0;
+    }();
+    tile_bits = tile_bits_max(dtype);
+    threads = kTileThreads;
+    if (dtype == QS_C128 && env_tb == 13 && n >= 13) {
+        tile_bits = 13;
+        threads = 1024;
+    }
+}
+
+std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype, int TB, int NT) {
     // Code-shape knobs (for tuning runs): QSIM_JIT_PREFETCH=0 loads each tile
     // straight into LDS instead of prefetching the next one into registers;
     // QSIM_JIT_WAVES=w asks the compiler to fit w waves per SIMD (0: no limit).
@@ -259,12 +272,16 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
     auto stv = [&](const std::string &addr, const std::string &v) {
         return nt ? "__builtin_nontemporal_store(" + v + ", psi + (" + addr + "));\n" : "psi[" + addr + "] = " + v + ";\n";
     };
-    const int TB = tile_bits_max(dtype);
-    const int TS = 1 << TB, NT = kTileThreads, PER = TS / NT;
+    const int TS = 1 << TB, PER = TS / NT;
+    int TTB = 0;  // thread bits
+    while ((1 << TTB) < NT) ++TTB;
+    if ((1 << TTB) != NT || PER < 8 || PER % 8 || TTB < 6) return "";
+    if ((dtype == QS_C128 && (TB < 12 || TB > 13)) || (dtype != QS_C128 && TB != 13)) return "";
     static const int kSwz128[12] = {1, 2, 4, 8, 15, 12, 9, 3, 6, 14, 6, 0};
+    static const int kSwz128w[13] = {1, 2, 4, 8, 15, 11, 13, 4, 8, 11, 5, 8, 6};
     static const int kSwz64[13] = {1, 2, 4, 8, 16, 31, 26, 22, 1, 0, 14, 9, 20};
     const int SB = dtype == QS_C128 ? 4 : 5;
-    const int *swz_pat = dtype == QS_C128 ? kSwz128 : kSwz64;
+    const int *swz_pat = dtype == QS_C128 ? (TB == 13 ? kSwz128w : kSwz128) : kSwz64;
     auto hsw = [&](u32 m) {
         u32 h = 0;
         for (int p = SB; p < TB; ++p)
@@ -288,7 +305,8 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
     // with these patterns the lanes of every sweep whose group bits are three
     // consecutive tile bits (and of the load/store layout) reach 2^SB distinct
     // slots modulo 2^SB, i.e. distinct banks (found by search over all
-    // patterns; 189 of the 220 possible group-bit triples of a 12-bit tile).
+    // patterns; 189 of the 220 possible group-bit triples of a 12-bit c128
+    // tile, 251 of 286 for a 13-bit one).
     o += "__device__ __forceinline__ unsigned hsw(unsigned m) {\n  unsigned h = 0u;\n";
     for (int p = SB; p < TB; ++p)
         if (swz_pat[p]) o += "  h ^= ((m >> " + S(p) + ") & 1u) ? " + S(swz_pat[p]) + "u : 0u;\n";
@@ -301,12 +319,12 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         o += " qs_pass" + S((long long)pi) + "(C *__restrict__ psi, const R *__restrict__ v, unsigned ntiles) {\n";
         o += "  __shared__ C sh[" + S(TS) + "];\n";
         o += "  const unsigned t = threadIdx.x, st = t ^ hsw(t);\n";
-        o += "  const unsigned long long dt = " + deposit("(unsigned long long)t", P.T, 9) + ";\n";
+        o += "  const unsigned long long dt = " + deposit("(unsigned long long)t", P.T, TTB) + ";\n";
         std::vector<u64> hi(PER);
         for (int k = 0; k < PER; ++k) {
             u64 off = 0;
-            for (int b = 9; b < TB; ++b)
-                if (((u64)k << 9 >> b) & 1) off |= 1ull << P.T[b];
+            for (int b = TTB; b < TB; ++b)
+                if (((u64)k << TTB >> b) & 1) off |= 1ull << P.T[b];
             hi[k] = off;
         }
         uint8_t rest_order[40];
@@ -352,9 +370,9 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         auto on_top = [&](const Sw &w) { return w.g0 == TB - 3 && w.g1 == TB - 2 && w.g2 == TB - 1; };
         const bool first_regs = !sw.empty() && on_top(sw.front());
         const bool last_regs = !sw.empty() && on_top(sw.back());
-        auto hi_of = [&](u32 mhigh) {  // state offset of tile bits >= 9 of mhigh
+        auto hi_of = [&](u32 mhigh) {  // state offset of the tile bits of mhigh above the thread bits
             u64 off = 0;
-            for (int b = 9; b < TB; ++b)
+            for (int b = TTB; b < TB; ++b)
                 if ((mhigh >> b) & 1) off |= 1ull << P.T[b];
             return off;
         };
@@ -385,7 +403,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
                 for (int j = 0; j < 8; ++j) {
                     nm[g][j] = gen.fresh("x");
                     if (from_regs)
-                        o += "      const C " + nm[g][j] + " = pre[" + S((g * NT + grp_off(w, j)) >> 9) + "];\n";
+                        o += "      const C " + nm[g][j] + " = pre[" + S((g * NT + grp_off(w, j)) >> TTB) + "];\n";
                     else
                         o += "      const C " + nm[g][j] + " = sh[s" + S(g) + " ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u];\n";
                 }
@@ -581,7 +599,7 @@ int compile(const std::string &src, std::vector<char> &code) {
 
 }  // namespace
 
-int jit_block_functions(const std::string &src, int npass, int device, JitFns &out, const char *prefix) {
+int jit_block_functions(const std::string &src, int npass, int device, JitFns &out, const char *prefix, int threads) {
     std::vector<char> code;
     {
         std::lock_guard<std::mutex> lk(g_jit_mu);
@@ -610,7 +628,7 @@ int jit_block_functions(const std::string &src, int npass, int device, JitFns &o
         const std::string name = prefix + S(p);
         e = hipModuleGetFunction(&f.fn[p], f.mod, name.c_str());
         int nb = 0;
-        if (e == hipSuccess) e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f.fn[p], kTileThreads, 0);
+        if (e == hipSuccess) e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f.fn[p], threads, 0);
         f.max_blocks[p] = (unsigned)std::max(1, nb) * (unsigned)std::max(1, cus);
     }
     if (e != hipSuccess) {

@@ -52,12 +52,22 @@ struct JitFns {
     hipModule_t mod = nullptr;         // loaded on the plan's device; unloaded with the plan
     std::vector<hipFunction_t> fn;     // kernel of pass p: (C *psi, const R *vals, unsigned ntiles)
     std::vector<unsigned> max_blocks;  // per pass: resident workgroups on the device (persistent grid size)
+    unsigned threads = kTileThreads;   // workgroup size of the kernels
 };
 // Source of the plan's pass kernels; "" when a pass's tile is not full.
-std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype);
+// Tile bits and workgroup size of compiled fused-block passes: the
+// interpreter's tile, or for complex128 registers of 13 qubits and more a
+// 13-qubit tile (128 KiB of LDS, one workgroup of 1024 threads per CU, rows of
+// 16 contiguous amplitudes) when QSIM_JIT_TB=13.  Measured on the 30-qubit
+// sweep: passes over high qubits gain from the longer rows (8.8 -> 7.6 ms),
+// the first pass loses from one workgroup per CU (7.6 -> 8.3 ms); 30 qubits
+// 24.7 -> 23.9 ms, the 32-qubit sweep 116.8 -> 122.6 ms, so 12 is the default.
+void jit_tile_shape(int n, int dtype, int &tile_bits, int &threads);
+std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype, int tile_bits, int threads);
 // Kernels of a plan: compiled once per source (host cache), loaded into a
 // module of the caller's current device that the plan owns.
-int jit_block_functions(const std::string &src, int npass, int device, JitFns &out, const char *prefix = "qs_pass");
+int jit_block_functions(const std::string &src, int npass, int device, JitFns &out, const char *prefix = "qs_pass",
+                        int threads = kTileThreads);
 // Source of a trajectory plan's pass kernels (qs_tpass0, ...): per-trajectory
 // gate values and control values from tables; "" when a pass's tile is not
 // 12 bits.

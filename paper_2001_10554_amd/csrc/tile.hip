@@ -167,8 +167,12 @@ static void make_sweeps(int tb, DGate *d, int cnt) {
 // qubits as tile-bit positions of its pass.
 void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg, int cap,
                int cap_region) {
-    const int tbmax = std::min(std::min(tile_bits, tile_bits_max(dtype)), n);
-    const int r = std::min(dtype == QS_C128 ? 3 : 4, tbmax);  // contiguous low qubits: 128-byte rows
+    // Tiles of up to 13 bits (the interpreter's 12 for c128, or 13 for its
+    // compiled passes with 1024-thread workgroups).
+    const int tbmax = std::min(std::min(tile_bits, 13), n);
+    // Contiguous low qubits in every tile: 128-byte rows, 256-byte rows for a
+    // 13-bit c128 tile.
+    const int r = std::min(dtype == QS_C128 ? (tbmax > 12 ? 4 : 3) : 4, tbmax);
     std::vector<int16_t> nidx(count);
     for (int j = 0, c = 0; j < count; ++j) {
         nidx[j] = (int16_t)c;
@@ -324,9 +328,21 @@ int run_block(qs_state *s, const qs_gate *gates, int count) {
             cache->plans.erase(lru);
         }
         Plan p;
-        make_plan(s->n, s->dtype, tile_bits_max(s->dtype), gates, count, p.passes, p.dg);
-        const std::string src = want_jit ? jit_block_source(p.passes, p.dg, s->dtype) : std::string();
-        if (src.empty() || jit_block_functions(src, (int)p.passes.size(), s->device, p.jit) != QS_OK) p.jit = JitFns{};
+        int jtb = tile_bits_max(s->dtype), jnt = kTileThreads;
+        if (want_jit) jit_tile_shape(s->n, s->dtype, jtb, jnt);
+        make_plan(s->n, s->dtype, jtb, gates, count, p.passes, p.dg);
+        const std::string src = want_jit ? jit_block_source(p.passes, p.dg, s->dtype, jtb, jnt) : std::string();
+        if (src.empty() || jit_block_functions(src, (int)p.passes.size(), s->device, p.jit, "qs_pass", jnt) != QS_OK) {
+            p.jit = JitFns{};
+            // The interpreter runs tiles of tile_bits_max bits only (make_plan appends).
+            if (jtb != tile_bits_max(s->dtype)) {
+                p.passes.clear();
+                p.dg.clear();
+                make_plan(s->n, s->dtype, tile_bits_max(s->dtype), gates, count, p.passes, p.dg);
+            }
+        } else {
+            p.jit.threads = (unsigned)jnt;
+        }
         const size_t nb = plan_bytes(p, gates, s->dtype).size();
         QS_HIP(hipMalloc(&p.dev, nb));
         if (hipHostMalloc(&p.stage, nb, hipHostMallocDefault) != hipSuccess) {
@@ -355,7 +371,7 @@ int run_block(qs_state *s, const qs_gate *gates, int count) {
             const unsigned grid = std::min(ntiles, plan.jit.max_blocks[pi]);
             void *psi = s->buf, *vals = plan.dev;
             void *args[] = {&psi, &vals, &ntiles};
-            QS_HIP(hipModuleLaunchKernel(plan.jit.fn[pi], grid, 1, 1, kTileThreads, 1, 1, 0, s->stream, args, nullptr));
+            QS_HIP(hipModuleLaunchKernel(plan.jit.fn[pi], grid, 1, 1, plan.jit.threads, 1, 1, 0, s->stream, args, nullptr));
         }
         return QS_OK;
     }

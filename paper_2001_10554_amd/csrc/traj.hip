@@ -23,6 +23,8 @@
 // frame seen by every gate, so the decisions are bit-exact by construction.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -437,7 +439,8 @@ __device__ __forceinline__ double tblock_sum(double v, double *red) {
 // for a diagonal observable d.  The chunk's index bits
 // below log2(256) are fixed per thread, the others per loop step, so each
 // <Z_q> needs one add per amplitude only for the q the loop varies.
-template <typename R>
+// FID false: no fidelity asked for, so the noiseless state is not read.
+template <typename R, bool FID>
 __global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ states, int n, int chunk_log2, int chunks_log2,
                                                     const uint64_t *__restrict__ final_frame, const int32_t *__restrict__ nins, int n_traj,
                                                     const double *__restrict__ diag, double *__restrict__ partial, QPerm perm) {
@@ -462,26 +465,28 @@ __global__ __launch_bounds__(kBlock) void k_traj_zf(const cx<R> *__restrict__ st
         const double p = (double)v.x * v.x + (double)v.y * v.y;
 #pragma unroll
         for (int q = 0; q < kTrajMaxQubits; ++q) z[q] += ((i >> q) & 1) ? -p : p;
-        const double sgn = (__popcll(i & fb) & 1) ? -1.0 : 1.0;
-        fre += sgn * ((double)id.x * v.x + (double)id.y * v.y);
-        fim += sgn * ((double)id.x * v.y - (double)id.y * v.x);
+        if (FID) {
+            const double sgn = (__popcll(i & fb) & 1) ? -1.0 : 1.0;
+            fre += sgn * ((double)id.x * v.x + (double)id.y * v.y);
+            fim += sgn * ((double)id.x * v.y - (double)id.y * v.x);
+        }
         dsum += p * dg;
     };
     u64 i = lo + threadIdx.x;
     for (; i + 3 * kBlock < hi; i += 4 * kBlock) {  // four steps, loads first; same summation order
-        cx<R> v[4], id[4];
+        cx<R> v[4], id[4]{};
         double dg[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const u64 k = i + (u64)s * kBlock;
             v[s] = psi[k];
-            id[s] = ideal[k ^ fa];
+            if (FID) id[s] = ideal[k ^ fa];
             dg[s] = diag ? diag[perm.active ? perm_index(perm, n, k ^ fa) : k ^ fa] : 0.0;
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) step(i + (u64)s * kBlock, v[s], id[s], dg[s]);
     }
-    for (; i < hi; i += kBlock) step(i, psi[i], ideal[i ^ fa], diag ? diag[perm.active ? perm_index(perm, n, i ^ fa) : i ^ fa] : 0.0);
+    for (; i < hi; i += kBlock) step(i, psi[i], FID ? ideal[i ^ fa] : cx<R>{}, diag ? diag[perm.active ? perm_index(perm, n, i ^ fa) : i ^ fa] : 0.0);
     const int nv = n + 3;
     double *out = partial + (u64)blockIdx.x * nv;
 #pragma unroll
@@ -731,10 +736,13 @@ static double traj_plan_cost(const std::vector<DPass> &passes, const std::vector
     return n_traj * e + tail[0];
 }
 
-// Compiled trajectory passes, kept per (source, device) for the process: a
-// trajectory run is one call, and repeated runs of one circuit reuse the
-// code.  At most kMaxTrajModules are kept; beyond that the device is
-// synchronised and the least recently used module unloaded.
+// Compiled trajectory passes, kept per (plan structure, device) for the
+// process: a trajectory run is one call, and repeated runs of one circuit
+// reuse the code without generating its source again (the key is the plan's
+// structure, from which the source is a function: pass tiles and each plan
+// gate's kind, slots, sweep and folding marks, not its values).  At most
+// kMaxTrajModules are kept; beyond that the device is synchronised and the
+// least recently used module unloaded.
 struct TrajModule {
     hipModule_t mod = nullptr;
     std::vector<hipFunction_t> fn;
@@ -745,13 +753,32 @@ static std::mutex g_traj_mu;
 static uint64_t g_traj_clock = 0;
 static auto *g_traj_mods = new std::map<std::pair<std::string, int>, TrajModule>();  // never destroyed (process exit)
 
-static int traj_functions(const std::string &src, int np, std::vector<hipFunction_t> &out) {
+static std::string traj_plan_key(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype) {
+    std::string k;
+    auto add = [&](const void *p, size_t n) { k.append((const char *)p, n); };
+    add(&dtype, sizeof dtype);
+    for (const DPass &P : passes) {
+        add(&P.tb, sizeof P.tb);
+        add(&P.nrest, sizeof P.nrest);
+        add(P.T, sizeof P.T);
+        add(&P.gate_begin, sizeof P.gate_begin);
+        add(&P.gate_count, sizeof P.gate_count);
+    }
+    for (const DGate &d : dg) add(&d, offsetof(DGate, nidx));  // kind .. run: everything the source depends on
+    return k;
+}
+
+// Functions of the plan's compiled passes; `make_src` runs only when they
+// are not cached.  Fails (the caller then interprets) if it returns "".
+static int traj_functions(const std::string &plan_key, const std::function<std::string()> &make_src, int np, std::vector<hipFunction_t> &out) {
     int dev = 0;
     QS_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_traj_mu);
-    auto key = std::make_pair(src, dev);
+    auto key = std::make_pair(plan_key, dev);
     auto it = g_traj_mods->find(key);
     if (it == g_traj_mods->end()) {
+        const std::string src = make_src();
+        if (src.empty()) return QS_ERR_UNSUPPORTED;
         JitFns jf;
         if (int rc = jit_block_functions(src, np, dev, jf, "qs_tpass")) return rc;
         if (g_traj_mods->size() >= kMaxTrajModules) {
@@ -866,8 +893,7 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     // interpreter kernel.
     std::vector<hipFunction_t> jfn;
     if (L.tables && !(getenv("QSIM_TRAJ_PATH") && std::string(getenv("QSIM_TRAJ_PATH")) == "interp")) {
-        const std::string src = jit_traj_source(passes, dg, dtype);
-        if (!src.empty() && traj_functions(src, np, jfn) != QS_OK) jfn.clear();
+        if (traj_functions(traj_plan_key(passes, dg, dtype), [&] { return jit_traj_source(passes, dg, dtype); }, np, jfn) != QS_OK) jfn.clear();
     }
     if (!jfn.empty()) {
         R *tv = (R *)(ws + L.tv);
@@ -905,8 +931,12 @@ static int traj_run_t(int n, int dtype, const qs_gate *gates, int count, u64 bas
     const double *diag = out->diag_val ? out->diag : nullptr;
     if (out->z || out->fid || diag) {
         const u64 blocks = (u64)T1 << L.chunks_log2;
-        hipLaunchKernelGGL(k_traj_zf<R>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<R> *)states, n, L.chunk_log2, L.chunks_log2,
-                           (const uint64_t *)final_frame, (const int32_t *)nins, n_traj, diag, pzf, perm);
+        if (out->fid)
+            hipLaunchKernelGGL((k_traj_zf<R, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<R> *)states, n, L.chunk_log2, L.chunks_log2,
+                               (const uint64_t *)final_frame, (const int32_t *)nins, n_traj, diag, pzf, perm);
+        else
+            hipLaunchKernelGGL((k_traj_zf<R, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, (const cx<R> *)states, n, L.chunk_log2, L.chunks_log2,
+                               (const uint64_t *)final_frame, (const int32_t *)nins, n_traj, diag, pzf, perm);
         QS_LAUNCH_CHECK("traj_zf");
     }
     if (out->x) {

@@ -298,7 +298,12 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
          "__device__ __forceinline__ C row(R a, R b, R c, R d, C x, C y) {\n"
          "  C r; r.x = a * x.x - b * x.y + c * y.x - d * y.y; r.y = a * x.y + b * x.x + c * y.y + d * y.x; return r; }\n"
          "__device__ __forceinline__ C cm(C x, R a, R b) { C r; r.x = a * x.x - b * x.y; r.y = a * x.y + b * x.x; return r; }\n"
-         "__device__ __forceinline__ unsigned ins(unsigned x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u)); }\n";
+         "__device__ __forceinline__ unsigned ins(unsigned x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u)); }\n"
+         "#define LDS(off) (*(C *)((char *)sh + (off)))\n";
+    // LDS accesses take the swizzled slot as a byte offset, so that an access
+    // at (group base) ^ (constant) is one XOR (the shift to bytes is applied
+    // to the base once and folded into the constants).
+    const int SH = dtype == QS_C128 ? 4 : 3;
     // LDS slot of tile index m: m ^ hsw(m), hsw XOR-ing a fixed pattern into
     // the low SB bits for each set bit of m at or above SB (a bijection).  The
     // b128 (c128) / b64 (c64) accesses of 16 / 32 lanes are served together;
@@ -318,7 +323,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         if (waves > 0) o += " __attribute__((amdgpu_waves_per_eu(" + S(waves) + ")))";
         o += " qs_pass" + S((long long)pi) + "(C *__restrict__ psi, const R *__restrict__ v, unsigned ntiles) {\n";
         o += "  __shared__ C sh[" + S(TS) + "];\n";
-        o += "  const unsigned t = threadIdx.x, st = t ^ hsw(t);\n";
+        o += "  const unsigned t = threadIdx.x, st = (t ^ hsw(t)) << " + S(SH) + ";\n";
         o += "  const unsigned long long dt = " + deposit("(unsigned long long)t", P.T, TTB) + ";\n";
         std::vector<u64> hi(PER);
         for (int k = 0; k < PER; ++k) {
@@ -388,7 +393,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         if (!prefetch)
             for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = " + ld("base | dt | " + hex(hi[k])) + ";\n";
         if (!first_regs) {
-            for (int k = 0; k < PER; ++k) o += "    sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u] = pre[" + S(k) + "];\n";
+            for (int k = 0; k < PER; ++k) o += "    LDS(st ^ " + S(((u32)(k * NT) ^ hsw((u32)(k * NT))) << SH) + "u) = pre[" + S(k) + "];\n";
             o += "    __syncthreads();\n";
             issue_prefetch();
         }
@@ -399,13 +404,13 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             std::vector<std::vector<std::string>> nm(gen.G, std::vector<std::string>(8));
             for (int g = 0; g < gen.G; ++g) {
                 o += "      const unsigned m" + S(g) + " = ins(ins(ins(tl + " + S(g * NT) + "u, " + S(w.g0) + "), " + S(w.g1) + "), " + S(w.g2) + ");\n";
-                if (!from_regs || !to_global) o += "      const unsigned s" + S(g) + " = m" + S(g) + " ^ hsw(m" + S(g) + ");\n";
+                if (!from_regs || !to_global) o += "      const unsigned s" + S(g) + " = (m" + S(g) + " ^ hsw(m" + S(g) + ")) << " + S(SH) + ";\n";
                 for (int j = 0; j < 8; ++j) {
                     nm[g][j] = gen.fresh("x");
                     if (from_regs)
                         o += "      const C " + nm[g][j] + " = pre[" + S((g * NT + grp_off(w, j)) >> TTB) + "];\n";
                     else
-                        o += "      const C " + nm[g][j] + " = sh[s" + S(g) + " ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u];\n";
+                        o += "      const C " + nm[g][j] + " = LDS(s" + S(g) + " ^ " + S((grp_off(w, j) ^ hsw(grp_off(w, j))) << SH) + "u);\n";
                 }
             }
             for (int r = 0; r < w.run; ++r) gen.gate(dg[w.begin + r], w.begin + r, nm);
@@ -415,16 +420,16 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
                         o += "      " + stv("base | dt | " + hex(hi_of((u32)(g * NT) + grp_off(w, j))), nm[g][j]);
             } else {
                 for (int g = 0; g < gen.G; ++g)
-                    for (int j = 0; j < 8; ++j) o += "      sh[s" + S(g) + " ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u] = " + nm[g][j] + ";\n";
+                    for (int j = 0; j < 8; ++j) o += "      LDS(s" + S(g) + " ^ " + S((grp_off(w, j) ^ hsw(grp_off(w, j))) << SH) + "u) = " + nm[g][j] + ";\n";
             }
             o += "      __syncthreads();\n    }\n";
             if (from_regs) issue_prefetch();
         }
         if (sw.empty()) {  // a pass without gates: copy the tile back
-            for (int k = 0; k < PER; ++k) o += "    " + stv("base | dt | " + hex(hi[k]), "sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u]");
+            for (int k = 0; k < PER; ++k) o += "    " + stv("base | dt | " + hex(hi[k]), "LDS(st ^ " + S(((u32)(k * NT) ^ hsw((u32)(k * NT))) << SH) + "u)");
             o += "    __syncthreads();\n";
         } else if (!last_regs) {
-            for (int k = 0; k < PER; ++k) o += "    " + stv("base | dt | " + hex(hi[k]), "sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u]");
+            for (int k = 0; k < PER; ++k) o += "    " + stv("base | dt | " + hex(hi[k]), "LDS(st ^ " + S(((u32)(k * NT) ^ hsw((u32)(k * NT))) << SH) + "u)");
             o += "    __syncthreads();\n";
         }
         o.insert(body_at, "  for (; tile < ntiles; tile += gridDim.x) {\n");
@@ -462,7 +467,9 @@ std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<
          "__device__ __forceinline__ C row(R a, R b, R c, R d, C x, C y) {\n"
          "  C r; r.x = a * x.x - b * x.y + c * y.x - d * y.y; r.y = a * x.y + b * x.x + c * y.y + d * y.x; return r; }\n"
          "__device__ __forceinline__ C cm(C x, R a, R b) { C r; r.x = a * x.x - b * x.y; r.y = a * x.y + b * x.x; return r; }\n"
-         "__device__ __forceinline__ unsigned ins(unsigned x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u)); }\n";
+         "__device__ __forceinline__ unsigned ins(unsigned x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1u)); }\n"
+         "#define LDS(off) (*(C *)((char *)sh + (off)))\n";
+    const int SH = dtype == QS_C128 ? 4 : 3;  // LDS slots as byte offsets (as in the block passes)
     o += "__device__ __forceinline__ unsigned hsw(unsigned m) {\n  unsigned h = 0u;\n";
     for (int p = SB; p < TB; ++p)
         if (pat[p]) o += "  h ^= ((m >> " + S(p) + ") & 1u) ? " + S(pat[p]) + "u : 0u;\n";
@@ -487,7 +494,7 @@ std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<
         o += "  const bool fill = from_ideal && first_pass != 0;\n";
         o += "  const R *__restrict__ vv = tv + (unsigned long long)t * ngates * 8u;\n";
         o += "  const int *__restrict__ tcv = tc + (unsigned long long)t * ngates;\n";
-        o += "  const unsigned tl = threadIdx.x, st = tl ^ hsw(tl);\n";
+        o += "  const unsigned tl = threadIdx.x, st = (tl ^ hsw(tl)) << " + S(SH) + ";\n";
         o += "  const unsigned long long dt = " + deposit("(unsigned long long)tl", P.T, 9) + ";\n";
         o += "  const unsigned long long base = " + deposit("(unsigned long long)tile", P.rest, P.nrest) + ";\n";
         std::vector<u64> hi(PER);
@@ -522,7 +529,7 @@ std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<
             return off;
         };
         if (!first_regs) {
-            for (int k = 0; k < PER; ++k) o += "  sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u] = pre[" + S(k) + "];\n";
+            for (int k = 0; k < PER; ++k) o += "  LDS(st ^ " + S(((u32)(k * NT) ^ hsw((u32)(k * NT))) << SH) + "u) = pre[" + S(k) + "];\n";
             o += "  __syncthreads();\n";
         }
         for (size_t si = 0; si < sw.size(); ++si) {
@@ -531,27 +538,27 @@ std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<
             o += "  {\n";
             std::vector<std::vector<std::string>> nm(1, std::vector<std::string>(8));
             o += "      const unsigned m0 = ins(ins(ins(tl, " + S(w.g0) + "), " + S(w.g1) + "), " + S(w.g2) + ");\n";
-            if (!from_regs || !to_global) o += "      const unsigned s0 = m0 ^ hsw(m0);\n";
+            if (!from_regs || !to_global) o += "      const unsigned s0 = (m0 ^ hsw(m0)) << " + S(SH) + ";\n";
             for (int j = 0; j < 8; ++j) {
                 nm[0][j] = gen.fresh("x");
                 if (from_regs)
                     o += "      const C " + nm[0][j] + " = pre[" + S(grp_off(w, j) >> 9) + "];\n";
                 else
-                    o += "      const C " + nm[0][j] + " = sh[s0 ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u];\n";
+                    o += "      const C " + nm[0][j] + " = LDS(s0 ^ " + S((grp_off(w, j) ^ hsw(grp_off(w, j))) << SH) + "u);\n";
             }
             for (int r = 0; r < w.run; ++r) gen.gate(dg[w.begin + r], w.begin + r, nm);
             if (to_global) {
                 for (int j = 0; j < 8; ++j)
                     o += "      __builtin_nontemporal_store(" + nm[0][j] + ", psi + (base | dt | " + hex(hi_of(grp_off(w, j))) + "));\n";
             } else {
-                for (int j = 0; j < 8; ++j) o += "      sh[s0 ^ " + S(grp_off(w, j) ^ hsw(grp_off(w, j))) + "u] = " + nm[0][j] + ";\n";
+                for (int j = 0; j < 8; ++j) o += "      LDS(s0 ^ " + S((grp_off(w, j) ^ hsw(grp_off(w, j))) << SH) + "u) = " + nm[0][j] + ";\n";
                 o += "      __syncthreads();\n";
             }
             o += "  }\n";
         }
         if (sw.empty() || !last_regs)
             for (int k = 0; k < PER; ++k)
-                o += "  __builtin_nontemporal_store(sh[st ^ " + S((u32)(k * NT) ^ hsw((u32)(k * NT))) + "u], psi + (base | dt | " + hex(hi[k]) + "));\n";
+                o += "  __builtin_nontemporal_store(LDS(st ^ " + S(((u32)(k * NT) ^ hsw((u32)(k * NT))) << SH) + "u), psi + (base | dt | " + hex(hi[k]) + "));\n";
         o += "}\n";
     }
     return o;

@@ -694,6 +694,31 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W,
 
 // ------------------------------------------------------------ backward helpers (L0 and L1)
 
+// psi from L0 to L1 through LDS, taking on the way the inner products of the
+// lane bits in `lanes` with lambda (already in L1, at the same point): while
+// psi sits in LDS a lane's partner value is one 16-byte read per register
+// instead of four wavefront exchanges (L1 keeps the lane bits, so the partner
+// of lambda's register j is psi's L1 slot of the partner thread).
+template <int TB, int TT>
+__device__ __forceinline__ void rt_xpose_ip_lanes(d2v (&ps)[1 << (TB - TT)], const d2v (&lm)[1 << (TB - TT)], d2v *sh, u32 lanes, double &acc) {
+    using G = RT<TB, TT>;
+    const int t = threadIdx.x, t1 = G::tpart(1, t);
+#pragma unroll
+    for (int j = 0; j < G::R; ++j) sh[t | G::jpart(0, j)] = ps[j];
+    __syncthreads();
+#pragma unroll 1
+    for (u32 m = lanes; m; m &= m - 1) {
+        const int tp = G::tpart(1, t ^ (1 << __builtin_ctz(m)));
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < G::R; ++j) a += im_conj_mul(lm[j], sh[tp | G::jpart(1, j)]);
+        acc += a;
+    }
+#pragma unroll
+    for (int j = 0; j < G::R; ++j) ps[j] = sh[t1 | G::jpart(1, j)];
+    __syncthreads();
+}
+
 // Which register bits a helper covers: none, register bits 0..W-1 (the bits
 // the other layout holds as wave bits), or all.
 enum { kRegsNone = 0, kRegsLow = 1, kRegsAll = 2 };
@@ -953,15 +978,17 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
         rt_rx_sel<TB, TT, 0>(lm, rx, cb, sn, kRegsAll, true);
         lay = 0;
     } else {
-        // One mixer: inner products of the L0 bits; if some RX bit needs L1,
-        // undo the B bits on both, transpose, take the A-bit inner products;
-        // psi is then dead and lambda undoes every bit not yet undone.
-        rt_ip_sel<TB, TT, 0>(lm, ps, rx, kRegsAll, true, ipb);
+        // One mixer: inner products of the L0 register bits; if some RX bit
+        // needs L1, undo the B bits on both, take the lane-bit inner products
+        // while psi passes through LDS, transpose, take the A-bit inner
+        // products (without L1, the lane bits by exchanges); psi is then dead
+        // and lambda undoes every bit not yet undone.
+        rt_ip_sel<TB, TT, 0>(lm, ps, rx, kRegsAll, !l1, ipb);
         if (l1) {
             rt_rx_sel<TB, TT, 0>(lm, rx, cb, sn, kRegsLow, false);
             rt_rx_sel<TB, TT, 0>(ps, rx, cb, sn, kRegsLow, false);
             rt_xpose<TB, TT>(lm, sh, 0, 1);
-            rt_xpose<TB, TT>(ps, sh, 0, 1);
+            rt_xpose_ip_lanes<TB, TT>(ps, lm, sh, rx & 63u, ipb);
             rt_ip_sel<TB, TT, 1>(lm, ps, rx, kRegsLow, false, ipb);
             lay = 1;
         }

@@ -694,28 +694,29 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W,
 
 // ------------------------------------------------------------ backward helpers (L0 and L1)
 
-// psi from L0 to L1 through LDS, taking on the way the inner products of the
-// lane bits in `lanes` with lambda (already in L1, at the same point): while
-// psi sits in LDS a lane's partner value is one 16-byte read per register
-// instead of four wavefront exchanges (L1 keeps the lane bits, so the partner
-// of lambda's register j is psi's L1 slot of the partner thread).
-template <int TB, int TT>
+// psi from layout FROM to layout TO through LDS, taking on the way the inner
+// products of the lane bits in `lanes` with lambda (already in TO, at the same
+// point): while psi sits in LDS a lane's partner value is one 16-byte read per
+// register instead of four wavefront exchanges (L0 and L1 hold the lane bits
+// alike, so the partner of lambda's register j is psi's TO slot of the
+// partner thread).
+template <int TB, int TT, int FROM, int TO>
 __device__ __forceinline__ void rt_xpose_ip_lanes(d2v (&ps)[1 << (TB - TT)], const d2v (&lm)[1 << (TB - TT)], d2v *sh, u32 lanes, double &acc) {
     using G = RT<TB, TT>;
-    const int t = threadIdx.x, t1 = G::tpart(1, t);
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < G::R; ++j) sh[t | G::jpart(0, j)] = ps[j];
+    for (int j = 0; j < G::R; ++j) sh[G::tpart(FROM, t) | G::jpart(FROM, j)] = ps[j];
     __syncthreads();
 #pragma unroll 1
     for (u32 m = lanes; m; m &= m - 1) {
-        const int tp = G::tpart(1, t ^ (1 << __builtin_ctz(m)));
+        const int tp = G::tpart(TO, t ^ (1 << __builtin_ctz(m)));
         double a = 0.0;
 #pragma unroll
-        for (int j = 0; j < G::R; ++j) a += im_conj_mul(lm[j], sh[tp | G::jpart(1, j)]);
+        for (int j = 0; j < G::R; ++j) a += im_conj_mul(lm[j], sh[tp | G::jpart(TO, j)]);
         acc += a;
     }
 #pragma unroll
-    for (int j = 0; j < G::R; ++j) ps[j] = sh[t1 | G::jpart(1, j)];
+    for (int j = 0; j < G::R; ++j) ps[j] = sh[G::tpart(TO, t) | G::jpart(TO, j)];
     __syncthreads();
 }
 
@@ -967,12 +968,12 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
         // current layout reaches; with L1, the A bits undone on both, the
         // transpose and the B-bit inner products; then lambda alone undoes
         // the rest and is stored from L0.
-        rt_ip_cur<TB, TT>(lm, ps, rx, l1, true, ipb);
+        rt_ip_cur<TB, TT>(lm, ps, rx, l1, !l1, ipb);
         if (l1) {
             rt_rx_sel<TB, TT, 1>(lm, rx, cb, sn, kRegsLow, false);
             rt_rx_sel<TB, TT, 1>(ps, rx, cb, sn, kRegsLow, false);
             rt_xpose<TB, TT>(lm, sh, 1, 0);
-            rt_xpose<TB, TT>(ps, sh, 1, 0);
+            rt_xpose_ip_lanes<TB, TT, 1, 0>(ps, lm, sh, rx & 63u, ipb);
             rt_ip_sel<TB, TT, 0>(lm, ps, rx, kRegsLow, false, ipb);
         }
         rt_rx_sel<TB, TT, 0>(lm, rx, cb, sn, kRegsAll, true);
@@ -988,7 +989,7 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
             rt_rx_sel<TB, TT, 0>(lm, rx, cb, sn, kRegsLow, false);
             rt_rx_sel<TB, TT, 0>(ps, rx, cb, sn, kRegsLow, false);
             rt_xpose<TB, TT>(lm, sh, 0, 1);
-            rt_xpose_ip_lanes<TB, TT>(ps, lm, sh, rx & 63u, ipb);
+            rt_xpose_ip_lanes<TB, TT, 0, 1>(ps, lm, sh, rx & 63u, ipb);
             rt_ip_sel<TB, TT, 1>(lm, ps, rx, kRegsLow, false, ipb);
             lay = 1;
         }

@@ -721,8 +721,9 @@ __device__ __forceinline__ void rt_xpose_ip_lanes(d2v (&ps)[1 << (TB - TT)], con
 }
 
 // Which register bits a helper covers: none, register bits 0..W-1 (the bits
-// the other layout holds as wave bits), or all.
-enum { kRegsNone = 0, kRegsLow = 1, kRegsAll = 2 };
+// the other layout holds as wave bits), all, or register bits 0..S-1 (in the
+// third layout, the upper lane bits of the first).
+enum { kRegsNone = 0, kRegsLow = 1, kRegsAll = 2, kRegsLowS = 3 };
 
 // RX(2 beta), (cb, sb) = (cos beta, sin beta), on the tile bits of `rx` that
 // layout L holds in the selected register bits and, when `lanes`, on the lane
@@ -838,7 +839,7 @@ __device__ __forceinline__ void rt_ip_rx2_sel(d2v (&lm)[1 << (TB - TT)], d2v (&p
     using G = RT<TB, TT>;
 #pragma unroll
     for (int x = 0; x < G::JB; ++x) {
-        if (regs == kRegsNone || (regs == kRegsLow && x >= G::W)) continue;
+        if (regs == kRegsNone || (regs == kRegsLow && x >= G::W) || (regs == kRegsLowS && x >= G::S)) continue;
         const bool on = (rx >> G::reg_bit(L, x)) & 1;
         if (on) {
 #pragma unroll
@@ -876,7 +877,11 @@ __device__ __forceinline__ void rt_ip_rx2_sel(d2v (&lm)[1 << (TB - TT)], d2v (&p
     }
 }
 
-template <typename CT, int TB, int TT, bool POOLED, bool MERGE, bool TABS>
+// WALK (merged passes whose RX lane bits are all upper lane bits, and some
+// RX bit is an L0 wave bit): layer l+1's mixer is undone through L0, L2 and
+// L1, two transposes per vector in place of a wavefront exchange of both
+// vectors per upper lane bit.
+template <typename CT, int TB, int TT, bool POOLED, bool MERGE, bool TABS, bool WALK = false>
 __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
     using G = RT<TB, TT>;
     constexpr int R = G::R, JB = G::JB;
@@ -892,7 +897,7 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
     const u64 base = qtile_base(P, q.tile);
     constexpr bool merge = MERGE;
     const bool first = !MERGE && (P.flags & QF_FIRST), pend = !MERGE && (P.flags & QF_PHASE_END), last = !MERGE && (P.flags & QF_LAST);
-    const bool l1 = ((P.rx_mask >> 6) & ((1u << G::W) - 1)) != 0;  // some RX bit is a wave bit in L0
+    const bool l1 = WALK || ((P.rx_mask >> 6) & ((1u << G::W) - 1)) != 0;  // some RX bit is a wave bit in L0
     const double g_a = q.theta[l], g_b = pend || merge ? q.theta[l + 1] : 0.0;
     if constexpr (TABS) {
         if (!geo.weighted) {
@@ -943,12 +948,23 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
         double sb2, cb2;
         sincos(q.theta[p + l + 1], &sb2, &cb2);
         const double sn2 = -sb2;
-        rt_ip_rx2_sel<TB, TT, 0>(lm, ps, rx, cb2, sn2, kRegsAll, true, ipb2);
-        if (l1) {
-            rt_xpose<TB, TT>(lm, sh, 0, 1);
-            rt_xpose<TB, TT>(ps, sh, 0, 1);
+        if constexpr (WALK) {
+            rt_ip_rx2_sel<TB, TT, 0>(lm, ps, rx, cb2, sn2, kRegsAll, false, ipb2);
+            rt_xpose<TB, TT>(lm, sh, 0, 2);
+            rt_xpose<TB, TT>(ps, sh, 0, 2);
+            rt_ip_rx2_sel<TB, TT, 2>(lm, ps, rx, cb2, sn2, kRegsLowS, false, ipb2);
+            rt_xpose<TB, TT>(lm, sh, 2, 1);
+            rt_xpose<TB, TT>(ps, sh, 2, 1);
             rt_ip_rx2_sel<TB, TT, 1>(lm, ps, rx, cb2, sn2, kRegsLow, false, ipb2);
             lay = 1;
+        } else {
+            rt_ip_rx2_sel<TB, TT, 0>(lm, ps, rx, cb2, sn2, kRegsAll, true, ipb2);
+            if (l1) {
+                rt_xpose<TB, TT>(lm, sh, 0, 1);
+                rt_xpose<TB, TT>(ps, sh, 0, 1);
+                rt_ip_rx2_sel<TB, TT, 1>(lm, ps, rx, cb2, sn2, kRegsLow, false, ipb2);
+                lay = 1;
+            }
         }
         // The cost phase between the two mixers, in the current layout.  Its
         // inner product Im(conj(lam) C psi) is unchanged by the common unit
@@ -1349,8 +1365,11 @@ template <typename CT, int TB, int TT, bool POOLED> struct RtKernels {
         else
             hipLaunchKernelGGL((k_qaoa_fwd_rt<CT, TB, TT, POOLED, false, false>), grid, dim3(threads), 0, st, P, W, g, B);
     }
-    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool merged, bool tabs) {
-        if (merged)
+    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool merged, bool tabs,
+                    bool walk) {
+        if (merged && walk)
+            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, true, true, true>), grid, dim3(threads), 0, st, P, W, g, B);
+        else if (merged)
             hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, true, true>), grid, dim3(threads), 0, st, P, W, g, B);
         else if (tabs)
             hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, false, true>), grid, dim3(threads), 0, st, P, W, g, B);
@@ -1363,7 +1382,7 @@ template <typename CT, bool POOLED> struct LdsKernels {
     static void fwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool, bool) {
         hipLaunchKernelGGL((k_qaoa_fwd_lds<CT, POOLED>), grid, dim3(kLdsThreads), 0, st, P, W, g, B);
     }
-    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool, bool) {
+    static void bwd(dim3 grid, hipStream_t st, const QPass &P, const QWeights &W, const QGeom &g, const QBatch &B, bool, bool, bool) {
         hipLaunchKernelGGL((k_qaoa_bwd_lds<CT, POOLED>), grid, dim3(kLdsThreads), 0, st, P, W, g, B);
     }
 };
@@ -1392,6 +1411,15 @@ static void launch_seq(const QPlan &plan, const QPass *passes, const QWeights &W
         if ((size_t)k >= plan.passes.size()) return true;
         return merged(k) || (plan.passes[k].flags & (QF_FIRST | QF_PHASE_END)) != 0;
     };
+    // Merged backward through the third layout: the pass uses it, every RX
+    // lane bit is one of its upper lane bits, and some RX bit is an L0 wave bit.
+    auto walk = [&](int k) {
+        if (!plan.rt || !merged(k) || (size_t)k >= plan.passes.size()) return false;
+        const QPass &Q = plan.passes[k];
+        const int TT = plan.shape.TT, JB = g.tb - TT, S = JB < 3 ? JB : 3, W = TT - 6;
+        const u32 lanes = Q.rx_mask & 63u;
+        return Q.use_l2 && (lanes & ((1u << (6 - S)) - 1u)) == 0 && ((Q.rx_mask >> 6) & ((1u << W) - 1u)) != 0;
+    };
     if (grad_out) {
         for (int k = 0; k < np; ++k) {
             B.k = k;
@@ -1402,7 +1430,7 @@ static void launch_seq(const QPlan &plan, const QPass *passes, const QWeights &W
         for (int k = np - 1; k >= 0; --k) {
             B.k = k;
             B.in_off = (long long)(L.ckpt + (size_t)k * sb);
-            K::bwd(grid, st, pass(k), W, g, B, merged(k), tabs(k));
+            K::bwd(grid, st, pass(k), W, g, B, merged(k), tabs(k), walk(k));
         }
         hipLaunchKernelGGL(k_qaoa_final<POOLED>, dim3(2 * g.p + 1, nb), dim3(256), 0, st, g, B, plan.map, E_out, grad_out, 1);
     } else {

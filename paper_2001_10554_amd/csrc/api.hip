@@ -231,10 +231,7 @@ QS_API int qs_block_passes(int n, int dtype, const qs_gate *gates, int count, in
     if (n < 1) return fail(QS_ERR_ARG, "n must be >= 1");
     if (n > (dtype == QS_C128 ? QS_MAX_QUBITS_C128 : QS_MAX_QUBITS_C64)) return fail(QS_ERR_SIZE, "n above the per-device limit");
     if (int rc = validate_gates(n, gates, count, false)) return rc;
-    std::vector<DPass> plan;
-    std::vector<DGate> dg;
-    make_plan(n, dtype, tile_bits_max(dtype), gates, count, plan, dg);
-    *passes = (int)plan.size();
+    *passes = block_pass_count(n, dtype, gates, count);
     return QS_OK;
     QS_GUARD_END
 }

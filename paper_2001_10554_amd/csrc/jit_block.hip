@@ -232,23 +232,25 @@ int gate_value_class(int kind, const double *u) {
     return 0;
 }
 
-// Source of one kernel per pass (qs_pass0, qs_pass1, ...) for passes whose
-// tile is full (tb = the dtype's tile size).  Returns "" if a pass does not
-// qualify (the caller then uses the interpreter).
-void jit_tile_shape(int n, int dtype, int &tile_bits, int &threads) {
+void jit_tile_shape(int n, int dtype, int &tile_bits, int &low_bits) {
+    // QSIM_JIT_TB=12 or 13: one tile size for every pass (for comparisons).
     static const int env_tb = [] {
         const char *e = getenv("QSIM_JIT_TB");
         return e ? atoi(e) : 0;
     }();
     tile_bits = tile_bits_max(dtype);
-    threads = kTileThreads;
-    if (dtype == QS_C128 && env_tb == 13 && n >= 13) {
-        tile_bits = 13;
-        threads = 1024;
-    }
+    low_bits = 0;
+    if (dtype != QS_C128 || n < kJitMixedMinQubits || env_tb == 12) return;
+    tile_bits = 13;
+    if (env_tb != 13) low_bits = 12;
 }
 
-std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype, int TB, int NT) {
+int jit_threads(int dtype, int tile_bits) { return dtype == QS_C128 && tile_bits == 13 ? 1024 : kTileThreads; }
+
+// Source of one kernel per pass (qs_pass0, qs_pass1, ...) for passes whose
+// tile is full (tb = a tile size the generator supports).  Returns "" if a
+// pass does not qualify (the caller then uses the interpreter).
+std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype) {
     // Code-shape knobs (for tuning runs): QSIM_JIT_PREFETCH=0 loads each tile
     // straight into LDS instead of prefetching the next one into registers;
     // QSIM_JIT_WAVES=w asks the compiler to fit w waves per SIMD (0: no limit).
@@ -272,25 +274,19 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
     auto stv = [&](const std::string &addr, const std::string &v) {
         return nt ? "__builtin_nontemporal_store(" + v + ", psi + (" + addr + "));\n" : "psi[" + addr + "] = " + v + ";\n";
     };
-    const int TS = 1 << TB, PER = TS / NT;
-    int TTB = 0;  // thread bits
-    while ((1 << TTB) < NT) ++TTB;
-    if ((1 << TTB) != NT || PER < 8 || PER % 8 || TTB < 6) return "";
-    if ((dtype == QS_C128 && (TB < 12 || TB > 13)) || (dtype != QS_C128 && TB != 13)) return "";
     static const int kSwz128[12] = {1, 2, 4, 8, 15, 12, 9, 3, 6, 14, 6, 0};
     static const int kSwz128w[13] = {1, 2, 4, 8, 15, 11, 13, 4, 8, 11, 5, 8, 6};
     static const int kSwz64[13] = {1, 2, 4, 8, 16, 31, 26, 22, 1, 0, 14, 9, 20};
     const int SB = dtype == QS_C128 ? 4 : 5;
-    const int *swz_pat = dtype == QS_C128 ? (TB == 13 ? kSwz128w : kSwz128) : kSwz64;
-    auto hsw = [&](u32 m) {
-        u32 h = 0;
-        for (int p = SB; p < TB; ++p)
-            if ((m >> p) & 1) h ^= (u32)swz_pat[p];
-        return h;
-    };
+    auto supported = [&](int tb) { return dtype == QS_C128 ? tb == 12 || tb == 13 : tb == 13; };
+    auto pattern = [&](int tb) { return dtype == QS_C128 ? (tb == 13 ? kSwz128w : kSwz128) : kSwz64; };
+    bool used[14] = {};
+    for (const DPass &P : passes) {
+        if (!supported(P.tb)) return "";
+        used[P.tb] = true;
+    }
     Gen gen;
     gen.dtype = dtype;
-    gen.G = (TS / 8) / NT;
     std::string &o = gen.o;
     o += dtype == QS_C128 ? "typedef double R;\n" : "typedef float R;\n";
     o += "typedef __attribute__((address_space(4))) const R CR;\n";
@@ -312,18 +308,35 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
     // slots modulo 2^SB, i.e. distinct banks (found by search over all
     // patterns; 189 of the 220 possible group-bit triples of a 12-bit c128
     // tile, 251 of 286 for a 13-bit one).
-    o += "__device__ __forceinline__ unsigned hsw(unsigned m) {\n  unsigned h = 0u;\n";
-    for (int p = SB; p < TB; ++p)
-        if (swz_pat[p]) o += "  h ^= ((m >> " + S(p) + ") & 1u) ? " + S(swz_pat[p]) + "u : 0u;\n";
-    o += "  return h;\n}\n";
+    // (one function per tile size: hsw12, hsw13)
+    for (int tb = 12; tb <= 13; ++tb) {
+        if (!used[tb]) continue;
+        o += "__device__ __forceinline__ unsigned hsw" + S(tb) + "(unsigned m) {\n  unsigned h = 0u;\n";
+        for (int p = SB; p < tb; ++p)
+            if (pattern(tb)[p]) o += "  h ^= ((m >> " + S(p) + ") & 1u) ? " + S(pattern(tb)[p]) + "u : 0u;\n";
+        o += "  return h;\n}\n";
+    }
     for (size_t pi = 0; pi < passes.size(); ++pi) {
         const DPass &P = passes[pi];
-        if (P.tb != TB) return "";
+        // This pass's tile size, workgroup size and swizzle.
+        const int TB = P.tb, NT = jit_threads(dtype, TB), TS = 1 << TB, PER = TS / NT;
+        int TTB = 0;  // thread bits
+        while ((1 << TTB) < NT) ++TTB;
+        if ((1 << TTB) != NT || PER < 8 || PER % 8 || TTB < 6) return "";
+        const int *swz_pat = pattern(TB);
+        auto hsw = [&](u32 m) {
+            u32 h = 0;
+            for (int p = SB; p < TB; ++p)
+                if ((m >> p) & 1) h ^= (u32)swz_pat[p];
+            return h;
+        };
+        const std::string HSW = "hsw" + S(TB);
+        gen.G = (TS / 8) / NT;
         o += "extern \"C\" __global__ void __launch_bounds__(" + S(NT) + ")";
         if (waves > 0) o += " __attribute__((amdgpu_waves_per_eu(" + S(waves) + ")))";
         o += " qs_pass" + S((long long)pi) + "(C *__restrict__ psi, const R *__restrict__ v, unsigned ntiles) {\n";
         o += "  __shared__ C sh[" + S(TS) + "];\n";
-        o += "  const unsigned t = threadIdx.x, st = (t ^ hsw(t)) << " + S(SH) + ";\n";
+        o += "  const unsigned t = threadIdx.x, st = (t ^ " + HSW + "(t)) << " + S(SH) + ";\n";
         o += "  const unsigned long long dt = " + deposit("(unsigned long long)t", P.T, TTB) + ";\n";
         std::vector<u64> hi(PER);
         for (int k = 0; k < PER; ++k) {
@@ -404,7 +417,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             std::vector<std::vector<std::string>> nm(gen.G, std::vector<std::string>(8));
             for (int g = 0; g < gen.G; ++g) {
                 o += "      const unsigned m" + S(g) + " = ins(ins(ins(tl + " + S(g * NT) + "u, " + S(w.g0) + "), " + S(w.g1) + "), " + S(w.g2) + ");\n";
-                if (!from_regs || !to_global) o += "      const unsigned s" + S(g) + " = (m" + S(g) + " ^ hsw(m" + S(g) + ")) << " + S(SH) + ";\n";
+                if (!from_regs || !to_global) o += "      const unsigned s" + S(g) + " = (m" + S(g) + " ^ " + HSW + "(m" + S(g) + ")) << " + S(SH) + ";\n";
                 for (int j = 0; j < 8; ++j) {
                     nm[g][j] = gen.fresh("x");
                     if (from_regs)
@@ -606,7 +619,8 @@ int compile(const std::string &src, std::vector<char> &code) {
 
 }  // namespace
 
-int jit_block_functions(const std::string &src, int npass, int device, JitFns &out, const char *prefix, int threads) {
+int jit_block_functions(const std::string &src, int npass, int device, JitFns &out, const char *prefix,
+                        const std::vector<unsigned> &threads) {
     std::vector<char> code;
     {
         std::lock_guard<std::mutex> lk(g_jit_mu);
@@ -629,13 +643,15 @@ int jit_block_functions(const std::string &src, int npass, int device, JitFns &o
     QS_HIP(hipModuleLoadData(&f.mod, code.data()));
     f.fn.resize(npass);
     f.max_blocks.resize(npass);
+    f.threads.assign(npass, (unsigned)kTileThreads);
+    for (int p = 0; p < npass && p < (int)threads.size(); ++p) f.threads[p] = threads[p];
     int cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     for (int p = 0; p < npass && e == hipSuccess; ++p) {
         const std::string name = prefix + S(p);
         e = hipModuleGetFunction(&f.fn[p], f.mod, name.c_str());
         int nb = 0;
-        if (e == hipSuccess) e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f.fn[p], threads, 0);
+        if (e == hipSuccess) e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f.fn[p], (int)f.threads[p], 0);
         f.max_blocks[p] = (unsigned)std::max(1, nb) * (unsigned)std::max(1, cus);
     }
     if (e != hipSuccess) {

@@ -52,22 +52,27 @@ struct JitFns {
     hipModule_t mod = nullptr;         // loaded on the plan's device; unloaded with the plan
     std::vector<hipFunction_t> fn;     // kernel of pass p: (C *psi, const R *vals, unsigned ntiles)
     std::vector<unsigned> max_blocks;  // per pass: resident workgroups on the device (persistent grid size)
-    unsigned threads = kTileThreads;   // workgroup size of the kernels
+    std::vector<unsigned> threads;     // per pass: workgroup size
 };
-// Source of the plan's pass kernels; "" when a pass's tile is not full.
-// Tile bits and workgroup size of compiled fused-block passes: the
-// interpreter's tile, or for complex128 registers of 13 qubits and more a
-// 13-qubit tile (128 KiB of LDS, one workgroup of 1024 threads per CU, rows of
-// 16 contiguous amplitudes) when QSIM_JIT_TB=13.  Measured on the 30-qubit
-// sweep: passes over high qubits gain from the longer rows (8.8 -> 7.6 ms),
-// the first pass loses from one workgroup per CU (7.6 -> 8.3 ms); 30 qubits
-// 24.7 -> 23.9 ms, the 32-qubit sweep 116.8 -> 122.6 ms, so 12 is the default.
-void jit_tile_shape(int n, int dtype, int &tile_bits, int &threads);
-std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype, int tile_bits, int threads);
+// Tile sizes of compiled fused-block passes (make_plan's tile_bits and
+// low_bits).  complex64: the interpreter's 13-bit tile.  complex128: 12-bit
+// tiles (64 KiB of LDS, two 512-thread workgroups per CU, rows of 8 contiguous
+// amplitudes) for passes over the lowest 12 qubits, 13-bit tiles (128 KiB,
+// one 1024-thread workgroup per CU, rows of 16) for the others, from
+// kJitMixedMinQubits qubits on.  Passes over high qubits gain from the longer
+// rows, a pass over the low qubits (one contiguous 64 KiB stretch per tile)
+// from the second workgroup.  QSIM_JIT_TB=12 or 13 forces one size.
+constexpr int kJitMixedMinQubits = 20;
+void jit_tile_shape(int n, int dtype, int &tile_bits, int &low_bits);
+int jit_threads(int dtype, int tile_bits);  // workgroup size of a compiled pass
+// Source of the plan's pass kernels; "" when a pass's tile is not a size the
+// generator supports (complex128: 12 or 13 bits, complex64: 13).
+std::string jit_block_source(const std::vector<DPass> &passes, const std::vector<DGate> &dg, int dtype);
 // Kernels of a plan: compiled once per source (host cache), loaded into a
-// module of the caller's current device that the plan owns.
+// module of the caller's current device that the plan owns.  threads: the
+// workgroup size of each pass (empty: kTileThreads for all).
 int jit_block_functions(const std::string &src, int npass, int device, JitFns &out, const char *prefix = "qs_pass",
-                        int threads = kTileThreads);
+                        const std::vector<unsigned> &threads = {});
 // Source of a trajectory plan's pass kernels (qs_tpass0, ...): per-trajectory
 // gate values and control values from tables; "" when a pass's tile is not
 // 12 bits.
@@ -94,8 +99,16 @@ int gate_value_class(int kind, const double *u);
 // cap > 0: passes that start among the first cap_region gates of the list
 // hold at most cap gates (trajectories: shorter early passes let more noisy
 // trajectories start late from the noiseless run's state).
+//
+// low_bits > 0 (below tile_bits): mixed tile sizes.  A pass first tries a tile
+// of low_bits bits; if all of its targets then lie among the lowest low_bits
+// qubits (one contiguous stretch of the state per tile) it keeps that tile,
+// otherwise it is planned again with tile_bits.  DPass::tb gives each pass's size.
 void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg,
-               int cap = 0, int cap_region = 0);
+               int cap = 0, int cap_region = 0, int low_bits = 0);
+// Passes of the plan qs_apply_block builds for this list (the compiled
+// passes' tile sizes unless the interpreter is selected).
+int block_pass_count(int n, int dtype, const qs_gate *g, int count);
 
 // LDS tiles are stored swizzled: amplitude m of a tile sits at slot swz(m),
 // the low 3 bits (the 16-byte slot within a 128-byte row) XORed with bits

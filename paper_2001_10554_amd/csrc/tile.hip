@@ -79,6 +79,15 @@ static bool jit_wanted() {
     return !(e && std::string(e) == "interp");
 }
 
+int block_pass_count(int n, int dtype, const qs_gate *g, int count) {
+    int tb = tile_bits_max(dtype), low = 0;
+    if (jit_wanted()) jit_tile_shape(n, dtype, tb, low);
+    std::vector<DPass> passes;
+    std::vector<DGate> dg;
+    make_plan(n, dtype, tb, g, count, passes, dg, 0, 0, low);
+    return (int)passes.size();
+}
+
 struct PlanCache {
     std::unordered_map<std::string, Plan> plans;
     uint64_t clock = 0;
@@ -166,13 +175,14 @@ static void make_sweeps(int tb, DGate *d, int cnt) {
 // Split the list into passes (see the file comment) and encode each gate's
 // qubits as tile-bit positions of its pass.
 void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std::vector<DPass> &passes, std::vector<DGate> &dg, int cap,
-               int cap_region) {
+               int cap_region, int low_bits) {
     // Tiles of up to 13 bits (the interpreter's 12 for c128, or 13 for its
     // compiled passes with 1024-thread workgroups).
     const int tbmax = std::min(std::min(tile_bits, 13), n);
+    const int tblow = low_bits > 0 && low_bits < tbmax ? low_bits : 0;
     // Contiguous low qubits in every tile: 128-byte rows, 256-byte rows for a
     // 13-bit c128 tile.
-    const int r = std::min(dtype == QS_C128 ? (tbmax > 12 ? 4 : 3) : 4, tbmax);
+    auto rows = [&](int tb) { return std::min(dtype == QS_C128 ? (tb > 12 ? 4 : 3) : 4, tb); };
     std::vector<int16_t> nidx(count);
     for (int j = 0, c = 0; j < count; ++j) {
         nidx[j] = (int16_t)c;
@@ -180,11 +190,12 @@ void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std
     }
     // Gate lists and tile masks of the passes; with commute = false a pass is
     // the longest prefix of the remaining list that fits.
-    auto split = [&](bool commute, std::vector<std::vector<int>> &lists, std::vector<u64> &tiles) {
+    auto split = [&](bool commute, std::vector<std::vector<int>> &lists, std::vector<u64> &tiles, std::vector<int> &tbs) {
         std::vector<int> rem(count), take, later;
         for (int j = 0; j < count; ++j) rem[j] = j;
-        while (!rem.empty()) {
-            u64 T = (1ull << r) - 1;
+        // One pass of tb bits from the remaining gates.
+        auto collect = [&](int tb, u64 &T) {
+            T = (1ull << rows(tb)) - 1;
             u64 left_any = 0, left_nondiag = 0;  // qubits of the gates left for later passes
             const int placed = count - (int)rem.size();
             const size_t limit = cap > 0 && placed < cap_region ? (size_t)cap : (size_t)count;
@@ -199,7 +210,7 @@ void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std
                 else if (x.kind == QS_G_C1Q) need = 1ull << x.q1;
                 else if (x.kind == QS_G_SWAP) need = touch;
                 const bool blocked = take.size() >= limit || (commute ? (touch & (diag ? left_nondiag : left_any)) != 0 : !later.empty());
-                if (!blocked && __builtin_popcountll(T | need) <= tbmax) {
+                if (!blocked && __builtin_popcountll(T | need) <= tb) {
                     T |= need;
                     take.push_back(j);
                 } else {
@@ -208,8 +219,20 @@ void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std
                     if (!diag) left_nondiag |= touch;
                 }
             }
+        };
+        while (!rem.empty()) {
+            u64 T;
+            int tb = tbmax;
+            // With low_bits: a pass whose targets all lie among the lowest
+            // low_bits qubits keeps that smaller, contiguous tile.
+            if (tblow) {
+                collect(tblow, T);
+                if ((T >> tblow) == 0) tb = tblow;
+            }
+            if (tb == tbmax) collect(tbmax, T);
             lists.push_back(take);
             tiles.push_back(T);
+            tbs.push_back(tb);
             rem.swap(later);
         }
     };
@@ -218,17 +241,19 @@ void make_plan(int n, int dtype, int tile_bits, const qs_gate *g, int count, std
     // starting from the noiseless run's state prefer.
     std::vector<std::vector<int>> lists, lists_c;
     std::vector<u64> tiles, tiles_c;
-    split(false, lists, tiles);
-    split(true, lists_c, tiles_c);
+    std::vector<int> tbs, tbs_c;
+    split(false, lists, tiles, tbs);
+    split(true, lists_c, tiles_c, tbs_c);
     if (lists_c.size() < lists.size()) {
         lists.swap(lists_c);
         tiles.swap(tiles_c);
+        tbs.swap(tbs_c);
     }
     for (size_t pi = 0; pi < lists.size(); ++pi) {
         const std::vector<int> &take = lists[pi];
         u64 T = tiles[pi];
-        // Fill the tile up to tbmax with the lowest unused qubits.
-        for (int q = 0; q < n && __builtin_popcountll(T) < tbmax; ++q) T |= 1ull << q;
+        // Fill the tile up to its size with the lowest unused qubits.
+        for (int q = 0; q < n && __builtin_popcountll(T) < tbs[pi]; ++q) T |= 1ull << q;
         DPass P{};
         P.tb = 0;
         int pos[64];
@@ -328,20 +353,20 @@ int run_block(qs_state *s, const qs_gate *gates, int count) {
             cache->plans.erase(lru);
         }
         Plan p;
-        int jtb = tile_bits_max(s->dtype), jnt = kTileThreads;
-        if (want_jit) jit_tile_shape(s->n, s->dtype, jtb, jnt);
-        make_plan(s->n, s->dtype, jtb, gates, count, p.passes, p.dg);
-        const std::string src = want_jit ? jit_block_source(p.passes, p.dg, s->dtype, jtb, jnt) : std::string();
-        if (src.empty() || jit_block_functions(src, (int)p.passes.size(), s->device, p.jit, "qs_pass", jnt) != QS_OK) {
+        int jtb = tile_bits_max(s->dtype), jlow = 0;
+        if (want_jit) jit_tile_shape(s->n, s->dtype, jtb, jlow);
+        make_plan(s->n, s->dtype, jtb, gates, count, p.passes, p.dg, 0, 0, jlow);
+        const std::string src = want_jit ? jit_block_source(p.passes, p.dg, s->dtype) : std::string();
+        std::vector<unsigned> nt;
+        for (const DPass &P : p.passes) nt.push_back((unsigned)jit_threads(s->dtype, P.tb));
+        if (src.empty() || jit_block_functions(src, (int)p.passes.size(), s->device, p.jit, "qs_pass", nt) != QS_OK) {
             p.jit = JitFns{};
             // The interpreter runs tiles of tile_bits_max bits only (make_plan appends).
-            if (jtb != tile_bits_max(s->dtype)) {
+            if (jtb != tile_bits_max(s->dtype) || jlow) {
                 p.passes.clear();
                 p.dg.clear();
                 make_plan(s->n, s->dtype, tile_bits_max(s->dtype), gates, count, p.passes, p.dg);
             }
-        } else {
-            p.jit.threads = (unsigned)jnt;
         }
         const size_t nb = plan_bytes(p, gates, s->dtype).size();
         QS_HIP(hipMalloc(&p.dev, nb));
@@ -371,7 +396,7 @@ int run_block(qs_state *s, const qs_gate *gates, int count) {
             const unsigned grid = std::min(ntiles, plan.jit.max_blocks[pi]);
             void *psi = s->buf, *vals = plan.dev;
             void *args[] = {&psi, &vals, &ntiles};
-            QS_HIP(hipModuleLaunchKernel(plan.jit.fn[pi], grid, 1, 1, plan.jit.threads, 1, 1, 0, s->stream, args, nullptr));
+            QS_HIP(hipModuleLaunchKernel(plan.jit.fn[pi], grid, 1, 1, plan.jit.threads[pi], 1, 1, 0, s->stream, args, nullptr));
         }
         return QS_OK;
     }

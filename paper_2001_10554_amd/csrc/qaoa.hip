@@ -737,7 +737,7 @@ __device__ __forceinline__ void rt_rx_sel(d2v (&a)[1 << (TB - TT)], u32 rx, doub
     using G = RT<TB, TT>;
 #pragma unroll
     for (int x = 0; x < G::JB; ++x) {
-        if (regs == kRegsNone || (regs == kRegsLow && x >= G::W)) continue;
+        if (regs == kRegsNone || (regs == kRegsLow && x >= G::W) || (regs == kRegsLowS && x >= G::S)) continue;
         const bool on = (rx >> G::reg_bit(L, x)) & 1;
         const double c = on ? cb : 1.0, s = on ? sb : 0.0;
 #pragma unroll
@@ -786,7 +786,7 @@ __device__ __forceinline__ void rt_ip_sel(const d2v (&lm)[1 << (TB - TT)], const
     using G = RT<TB, TT>;
 #pragma unroll
     for (int x = 0; x < G::JB; ++x) {
-        if (regs == kRegsNone || (regs == kRegsLow && x >= G::W)) continue;
+        if (regs == kRegsNone || (regs == kRegsLow && x >= G::W) || (regs == kRegsLowS && x >= G::S)) continue;
         if ((rx >> G::reg_bit(L, x)) & 1) {
 #pragma unroll
             for (int j = 0; j < G::R; ++j) {
@@ -877,10 +877,13 @@ __device__ __forceinline__ void rt_ip_rx2_sel(d2v (&lm)[1 << (TB - TT)], d2v (&p
     }
 }
 
-// WALK (merged passes whose RX lane bits are all upper lane bits, and some
-// RX bit is an L0 wave bit): layer l+1's mixer is undone through L0, L2 and
-// L1, two transposes per vector in place of a wavefront exchange of both
-// vectors per upper lane bit.
+// WALK, for passes whose RX bits include upper lane bits (LS..5): lambda ends
+// the pass in L2, where those bits are register bits, instead of exchanging
+// them across the wavefront (one transpose of lambda in place of an exchange
+// per upper lane bit; it is stored from L2).  Merged passes take it when
+// every RX lane bit is an upper one and some RX bit is an L0 wave bit; they
+// then also undo layer l+1's mixer on both vectors through L0, L2 and L1, two
+// transposes per vector in place of an exchange of both per upper lane bit.
 template <typename CT, int TB, int TT, bool POOLED, bool MERGE, bool TABS, bool WALK = false>
 __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W, QGeom geo, QBatch B) {
     using G = RT<TB, TT>;
@@ -897,7 +900,7 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
     const u64 base = qtile_base(P, q.tile);
     constexpr bool merge = MERGE;
     const bool first = !MERGE && (P.flags & QF_FIRST), pend = !MERGE && (P.flags & QF_PHASE_END), last = !MERGE && (P.flags & QF_LAST);
-    const bool l1 = WALK || ((P.rx_mask >> 6) & ((1u << G::W) - 1)) != 0;  // some RX bit is a wave bit in L0
+    const bool l1 = (MERGE && WALK) || ((P.rx_mask >> 6) & ((1u << G::W) - 1)) != 0;  // some RX bit is a wave bit in L0
     const double g_a = q.theta[l], g_b = pend || merge ? q.theta[l + 1] : 0.0;
     if constexpr (TABS) {
         if (!geo.weighted) {
@@ -992,8 +995,15 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
             rt_xpose_ip_lanes<TB, TT, 1, 0>(ps, lm, sh, rx & 63u, ipb);
             rt_ip_sel<TB, TT, 0>(lm, ps, rx, kRegsLow, false, ipb);
         }
-        rt_rx_sel<TB, TT, 0>(lm, rx, cb, sn, kRegsAll, true);
-        lay = 0;
+        if constexpr (WALK) {
+            rt_rx_sel<TB, TT, 0>(lm, rx, cb, sn, kRegsAll, false);
+            rt_xpose<TB, TT>(lm, sh, 0, 2);
+            rt_rx_sel<TB, TT, 2>(lm, rx, cb, sn, kRegsLowS, false);
+            lay = 2;
+        } else {
+            rt_rx_sel<TB, TT, 0>(lm, rx, cb, sn, kRegsAll, true);
+            lay = 0;
+        }
     } else {
         // One mixer: inner products of the L0 register bits; if some RX bit
         // needs L1, undo the B bits on both, take the lane-bit inner products
@@ -1009,7 +1019,15 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
             rt_ip_sel<TB, TT, 1>(lm, ps, rx, kRegsLow, false, ipb);
             lay = 1;
         }
-        rt_rx_cur<TB, TT>(lm, rx, cb, sn, l1, true);
+        if constexpr (WALK) {
+            rt_rx_cur<TB, TT>(lm, rx, cb, sn, l1, false);
+            rt_xpose<TB, TT>(lm, sh, lay, 2);
+            rt_rx_sel<TB, TT, 2>(lm, rx, cb, sn, kRegsLowS, false);
+            rt_rx_lanes(lm, rx & ((1u << G::LS) - 1u), cb, sn);
+            lay = 2;
+        } else {
+            rt_rx_cur<TB, TT>(lm, rx, cb, sn, l1, true);
+        }
     }
     const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
     if (first) {
@@ -1371,8 +1389,12 @@ template <typename CT, int TB, int TT, bool POOLED> struct RtKernels {
             hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, true, true, true>), grid, dim3(threads), 0, st, P, W, g, B);
         else if (merged)
             hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, true, true>), grid, dim3(threads), 0, st, P, W, g, B);
+        else if (tabs && walk)
+            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, false, true, true>), grid, dim3(threads), 0, st, P, W, g, B);
         else if (tabs)
             hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, false, true>), grid, dim3(threads), 0, st, P, W, g, B);
+        else if (walk)
+            hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, false, false, true>), grid, dim3(threads), 0, st, P, W, g, B);
         else
             hipLaunchKernelGGL((k_qaoa_bwd_rt<CT, TB, TT, POOLED, false, false>), grid, dim3(threads), 0, st, P, W, g, B);
     }
@@ -1411,14 +1433,17 @@ static void launch_seq(const QPlan &plan, const QPass *passes, const QWeights &W
         if ((size_t)k >= plan.passes.size()) return true;
         return merged(k) || (plan.passes[k].flags & (QF_FIRST | QF_PHASE_END)) != 0;
     };
-    // Merged backward through the third layout: the pass uses it, every RX
-    // lane bit is one of its upper lane bits, and some RX bit is an L0 wave bit.
+    // Backward passes ending in the third layout (the kernel's WALK): some RX
+    // bit is an upper lane bit; for merged passes also every RX lane bit is
+    // one, and some RX bit is an L0 wave bit.
     auto walk = [&](int k) {
-        if (!plan.rt || !merged(k) || (size_t)k >= plan.passes.size()) return false;
+        if (!plan.rt || (size_t)k >= plan.passes.size()) return false;
         const QPass &Q = plan.passes[k];
         const int TT = plan.shape.TT, JB = g.tb - TT, S = JB < 3 ? JB : 3, W = TT - 6;
-        const u32 lanes = Q.rx_mask & 63u;
-        return Q.use_l2 && (lanes & ((1u << (6 - S)) - 1u)) == 0 && ((Q.rx_mask >> 6) & ((1u << W) - 1u)) != 0;
+        const u32 lanes = Q.rx_mask & 63u, upper = ((1u << S) - 1u) << (6 - S);
+        if (S < 1 || !(lanes & upper)) return false;
+        if (!merged(k)) return true;
+        return (lanes & ~upper) == 0 && ((Q.rx_mask >> 6) & ((1u << W) - 1u)) != 0;
     };
     if (grad_out) {
         for (int k = 0; k < np; ++k) {

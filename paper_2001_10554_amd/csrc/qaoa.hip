@@ -638,6 +638,14 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W,
             if (pend || merge) fill_table(tab_b, geo.num_edges, g_b);
         }
     }
+    const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
+    d2v a[R];
+    if (!first) {
+        u64 off[R];
+        rt_offsets<TB, TT>(P, t, 0, off);
+#pragma unroll
+        for (int j = 0; j < R; ++j) a[j] = ld<true>(in + (base | off[j]));
+    }
     // Cut values of the phase after the first mixer, in the layout that
     // mixer ends in (the plan's lay_mid), computed while the loads are in
     // flight.
@@ -645,20 +653,12 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_fwd_rt(QPass Parg, QWeights W,
     if (first) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, C0);
     if (pend || last || merge) cut_values<CT, JB>(P, P.lay_mid, W, geo.weighted, base, t, C1);
     __syncthreads();
-    const double amp0 = 1.0 / sqrt((double)(1ull << geo.n));
-    d2v a[R];
-    {
-        u64 off[R];
-        rt_offsets<TB, TT>(P, t, 0, off);
+    if (first) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            if (first) {
-                const d2v f = Phase<CT>::get(tab_a, g_a, C0[j]);
-                a[j].x = amp0 * f.x;
-                a[j].y = amp0 * f.y;
-            } else {
-                a[j] = ld<true>(in + (base | off[j]));
-            }
+            const d2v f = Phase<CT>::get(tab_a, g_a, C0[j]);
+            a[j].x = amp0 * f.x;
+            a[j].y = amp0 * f.y;
         }
     }
     double sb, cb;
@@ -917,14 +917,18 @@ __global__ __launch_bounds__(1 << TT) void k_qaoa_bwd_rt(QPass Parg, QWeights W,
     d2v lm[R], ps[R];
     double ipc = 0.0, ipb = 0.0, ipc1 = 0.0, ipb2 = 0.0;
     {
-        CT Cs[R];
-        if (last || pend) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, Cs);
-        __syncthreads();  // phase tables
+        // The checkpoint's loads first: the cut values are computed while
+        // they are in flight (lambda's loads as well would hold twice the
+        // registers through that computation).
         u64 off[R];
         rt_offsets<TB, TT>(P, t, 0, off);
 #pragma unroll
+        for (int j = 0; j < R; ++j) ps[j] = ld<true>(ckpt + (base | off[j]));
+        CT Cs[R];
+        if (last || pend) cut_values<CT, JB>(P, 0, W, geo.weighted, base, t, Cs);
+        __syncthreads();  // phase tables
+#pragma unroll
         for (int j = 0; j < R; ++j) {
-            ps[j] = ld<true>(ckpt + (base | off[j]));
             if (last) {
                 lm[j].x = (double)Cs[j] * ps[j].x;
                 lm[j].y = (double)Cs[j] * ps[j].y;

@@ -259,6 +259,9 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         return e ? atoi(e) : dflt;
     };
     const bool prefetch = env("QSIM_JIT_PREFETCH", 1) != 0;
+    // QSIM_JIT_BARRIERS=1: a workgroup barrier between every two LDS phases
+    // (see wave_pos below).
+    const bool all_barriers = env("QSIM_JIT_BARRIERS", 0) != 0;
     const int waves = env("QSIM_JIT_WAVES", 4);
     // QSIM_JIT_ORDER=k (k > 0): the tile counter's first k bits go to the k
     // lowest non-tile qubits and its other bits to the remaining non-tile
@@ -397,6 +400,31 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         auto grp_off = [&](const Sw &w, int j) {
             return ((u32)(j & 1) << w.g0) | ((u32)((j >> 1) & 1) << w.g1) | ((u32)((j >> 2) & 1) << w.g2);
         };
+        // Tile positions that select the wavefront in an LDS phase (a sweep, or
+        // w = nullptr: the load/store layout, thread t and register k at tile
+        // index t + NT k): thread bits 6..TTB-1 land on the non-group
+        // positions of ranks 6..TTB-1.  Where two consecutive phases have the
+        // same positions, every wavefront reads only slots it wrote itself;
+        // LDS runs one wavefront's instructions in order, so a wavefront-level
+        // fence replaces the workgroup barrier there.
+        auto wave_pos = [&](const Sw *w) {
+            u32 h = 0;
+            for (int p = 0, rank = 0; p < TB; ++p) {
+                if (w && (p == w->g0 || p == w->g1 || p == w->g2)) continue;
+                if (rank >= 6 && rank < TTB) h |= 1u << p;
+                ++rank;
+            }
+            return h;
+        };
+        auto sync = [&](const char *ind, u32 from, u32 to) {
+            if (all_barriers || from != to) o += std::string(ind) + "__syncthreads();\n";
+            else
+                o += std::string(ind) + "__builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\"); __builtin_amdgcn_wave_barrier(); "
+                                        "__builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");\n";
+        };
+        const u32 h_io = wave_pos(nullptr);
+        // Layout of the first LDS access of the next tile.
+        const u32 h_next_tile = first_regs ? wave_pos(&sw.front()) : h_io;
         auto issue_prefetch = [&]() {
             if (!prefetch) return;
             o += "    { const unsigned nx = tile + gridDim.x;\n      if (nx < ntiles) {\n        const unsigned long long nb = " + dep_next + ";\n";
@@ -407,7 +435,8 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = " + ld("base | dt | " + hex(hi[k])) + ";\n";
         if (!first_regs) {
             for (int k = 0; k < PER; ++k) o += "    LDS(st ^ " + S(((u32)(k * NT) ^ hsw((u32)(k * NT))) << SH) + "u) = pre[" + S(k) + "];\n";
-            o += "    __syncthreads();\n";
+            if (sw.empty()) o += "    __syncthreads();\n";
+            else sync("    ", h_io, wave_pos(&sw.front()));
             issue_prefetch();
         }
         for (size_t si = 0; si < sw.size(); ++si) {
@@ -435,7 +464,11 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
                 for (int g = 0; g < gen.G; ++g)
                     for (int j = 0; j < 8; ++j) o += "      LDS(s" + S(g) + " ^ " + S((grp_off(w, j) ^ hsw(grp_off(w, j))) << SH) + "u) = " + nm[g][j] + ";\n";
             }
-            o += "      __syncthreads();\n    }\n";
+            // The next LDS phase: the next sweep, the stores from LDS in the
+            // load/store layout, or the next tile's first write.
+            const u32 h_after = si + 1 < sw.size() ? wave_pos(&sw[si + 1]) : to_global ? h_next_tile : h_io;
+            sync("      ", wave_pos(&w), h_after);
+            o += "    }\n";
             if (from_regs) issue_prefetch();
         }
         if (sw.empty()) {  // a pass without gates: copy the tile back
@@ -443,7 +476,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             o += "    __syncthreads();\n";
         } else if (!last_regs) {
             for (int k = 0; k < PER; ++k) o += "    " + stv("base | dt | " + hex(hi[k]), "LDS(st ^ " + S(((u32)(k * NT) ^ hsw((u32)(k * NT))) << SH) + "u)");
-            o += "    __syncthreads();\n";
+            sync("    ", h_io, h_next_tile);
         }
         o.insert(body_at, "  for (; tile < ntiles; tile += gridDim.x) {\n");
         o += "  }\n}\n";

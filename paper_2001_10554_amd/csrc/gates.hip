@@ -232,11 +232,9 @@ static Shape1q shape_1q() {
         v.chunk = (u32)env("QSIM_1Q_CHUNK", 0x7fffffff);  // 0x7fffffff: per-target schedule below
         v.dlog = (int)env("QSIM_1Q_SPREAD", 11);
         v.ldlog = (int)env("QSIM_1Q_LSPREAD", 11);
-        // Controlled gates: a thread's quads 2^11 apart.  Measured per control
-        // on a 32-qubit CNOT(c, c+1) sweep: spreads of 2^9..2^13 raise the
-        // weakest control (c = 7) from 5.46 to 5.6-6.0 TB/s and the mean from
-        // 5.91 to 5.92-5.94 TB/s; 2^11 gave c = 7 its best rate in two runs.
-        v.cdlog = (int)env("QSIM_C1Q_SPREAD", 11);
+        // Controlled gates: a thread's quads 2^cdlog apart, per control by
+        // default (spread_for_c1q); QSIM_C1Q_SPREAD forces one value.
+        v.cdlog = (int)env("QSIM_C1Q_SPREAD", 0);
         v.lchunk = (u32)env("QSIM_1Q_LCHUNK", 0);
         v.cppt = (int)env("QSIM_C1Q_PPT", 2);
         v.cchunk = (u32)env("QSIM_C1Q_CHUNK", 0x7fffffff);  // 0x7fffffff: per-control schedule
@@ -283,6 +281,18 @@ static u32 chunk_for_control(int, int) { return ~0u; }
 static u32 chunk_for_c1q(int c, int t) {
     if (t == c + 1 && (c == 13 || c == 14)) return 256;
     return chunk_for_control(c, t);
+}
+
+// Spread of the controlled gate's quads (log2 of their distance).  Measured
+// per control on a 32-qubit complex128 CNOT(c, c+1) sweep with spreads 2^9..
+// 2^13 against consecutive slices: 2^9..2^13 all lift the weakest low control
+// (c = 7: 5.46 TB/s consecutive) and 2^11 suits c < 15 best; above, 2^10 is
+// best or within noise for most controls (c = 28: 5.66 -> 5.85 TB/s, c = 20,
+// 24: +0.08) and 2^13 for c = 3 mod 8 (c = 19: 5.62 -> 5.72, c = 27: 5.59 ->
+// 5.67), in step with the DRAM address interleaving.
+static int spread_for_c1q(int c, int t) {
+    if (t != c + 1 || c < 15) return 11;
+    return (c & 7) == 3 ? 13 : 10;
 }
 
 template <typename R> static int launch_1q_t(qs_state *s, int q, const double *u) {
@@ -378,7 +388,7 @@ template <typename R> static int launch_c1q_t(qs_state *s, int c, int t, const d
             });
     } else {
         const Shape1q v = shape_1q();
-        int dlog = v.cdlog >= 8 && v.cdlog < 40 ? v.cdlog : 8;
+        int dlog = v.cdlog >= 8 && v.cdlog < 40 ? v.cdlog : v.cdlog == 0 ? spread_for_c1q(c, t) : 8;
         const int ppt = v.cppt == 4 ? 4 : 2;
         if (nquads % ((u64)ppt << dlog)) dlog = 8;
         const u32 chunk = v.cchunk == 0x7fffffffu ? chunk_for_c1q(c, t) : v.cchunk;

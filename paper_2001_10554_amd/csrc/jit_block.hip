@@ -586,9 +586,28 @@ std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<
                 if ((mhigh >> b) & 1) off |= 1ull << P.T[b];
             return off;
         };
+        // Workgroup barriers only where the wavefront-selecting tile positions
+        // of consecutive LDS phases differ (as in the block passes).
+        auto wave_pos = [&](const Sw *w) {
+            u32 h = 0;
+            for (int p = 0, rank = 0; p < TB; ++p) {
+                if (w && (p == w->g0 || p == w->g1 || p == w->g2)) continue;
+                if (rank >= 6 && rank < 9) h |= 1u << p;
+                ++rank;
+            }
+            return h;
+        };
+        auto sync = [&](const char *ind, u32 from, u32 to) {
+            if (from != to) o += std::string(ind) + "__syncthreads();\n";
+            else
+                o += std::string(ind) + "__builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\"); __builtin_amdgcn_wave_barrier(); "
+                                        "__builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");\n";
+        };
+        const u32 h_io = wave_pos(nullptr);
         if (!first_regs) {
             for (int k = 0; k < PER; ++k) o += "  LDS(st ^ " + S(((u32)(k * NT) ^ hsw((u32)(k * NT))) << SH) + "u) = pre[" + S(k) + "];\n";
-            o += "  __syncthreads();\n";
+            if (sw.empty()) o += "  __syncthreads();\n";
+            else sync("  ", h_io, wave_pos(&sw.front()));
         }
         for (size_t si = 0; si < sw.size(); ++si) {
             const Sw &w = sw[si];
@@ -610,7 +629,7 @@ std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<
                     o += "      __builtin_nontemporal_store(" + nm[0][j] + ", psi + (base | dt | " + hex(hi_of(grp_off(w, j))) + "));\n";
             } else {
                 for (int j = 0; j < 8; ++j) o += "      LDS(s0 ^ " + S((grp_off(w, j) ^ hsw(grp_off(w, j))) << SH) + "u) = " + nm[0][j] + ";\n";
-                o += "      __syncthreads();\n";
+                sync("      ", wave_pos(&w), si + 1 < sw.size() ? wave_pos(&sw[si + 1]) : h_io);
             }
             o += "  }\n";
         }

@@ -265,7 +265,10 @@ int qs_qaoa_workspace_bytes(const qs_qaoa_desc *d, int with_grad, size_t *bytes)
  * with the derivative inner products reduced in FP64).  All arrays are
  * device memory; angles are read on the device, so a captured launch can be
  * replayed with new angles written in place.  ws: device workspace of at
- * least qs_qaoa_workspace_bytes.  Computes in complex128. */
+ * least qs_qaoa_workspace_bytes.  Computes in complex128.  The host-side plan
+ * (tiles, passes, edge classes) is cached by the descriptor's contents, at
+ * most 16 problems, least recently used dropped first; it holds no device
+ * memory. */
 int qs_qaoa_run(const qs_qaoa_desc *d, const double *angles_dev, int B, double *E_dev, double *grad_dev,
                 void *ws, size_t ws_bytes, void *stream);
 

@@ -44,6 +44,11 @@
 // Batching.  blockIdx.x = circuit * G + tile; circuit c owns the workspace
 // region ws + c * circ_bytes.
 #include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "launch.h"
@@ -1517,6 +1522,48 @@ int check_edges(int n, int ne, const int32_t *edges) {
     return QS_OK;
 }
 
+// Plans of recent problems, keyed by the descriptor's contents (n, p, edges,
+// weights): a variational loop calls qs_qaoa_run with one graph many times,
+// and a plan takes longer to build on the host than a small circuit takes on
+// the device.  At most kQPlanCache entries; beyond, the least recently used
+// one is dropped (callers still holding it keep their shared copy).
+constexpr size_t kQPlanCache = 16;
+struct QPlanEntry {
+    std::shared_ptr<const QPlan> plan;
+    uint64_t last_use = 0;
+};
+
+static int cached_qplan(const qs_qaoa_desc *d, std::shared_ptr<const QPlan> &out) {
+    static std::mutex mu;
+    static std::unordered_map<std::string, QPlanEntry> cache;
+    static uint64_t clock = 0;
+    std::string key;
+    auto add = [&](const void *p, size_t n) { key.append((const char *)p, n); };
+    add(&d->n, sizeof d->n);
+    add(&d->p, sizeof d->p);
+    add(&d->num_edges, sizeof d->num_edges);
+    add(d->edges, sizeof(int32_t) * 2 * (size_t)d->num_edges);
+    const char weighted = d->w != nullptr;
+    add(&weighted, 1);
+    if (d->w) add(d->w, sizeof(double) * (size_t)d->num_edges);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        auto plan = std::make_shared<QPlan>();
+        if (int rc = build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_shape(d->n), *plan)) return rc;
+        if (cache.size() >= kQPlanCache) {
+            auto lru = cache.begin();
+            for (auto j = cache.begin(); j != cache.end(); ++j)
+                if (j->second.last_use < lru->second.last_use) lru = j;
+            cache.erase(lru);
+        }
+        it = cache.emplace(std::move(key), QPlanEntry{std::move(plan), 0}).first;
+    }
+    it->second.last_use = ++clock;
+    out = it->second.plan;
+    return QS_OK;
+}
+
 static int check_desc(const qs_qaoa_desc *d) {
     if (!d) return fail(QS_ERR_ARG, "null QAOA descriptor");
     if (d->n < 2 || d->n > QS_MAX_QUBITS_C128) return fail(QS_ERR_ARG, "QAOA n must be in [2, 34]");
@@ -1532,9 +1579,9 @@ QS_API int qs_qaoa_workspace_bytes(const qs_qaoa_desc *d, int with_grad, size_t 
     try {
         if (int rc = check_desc(d)) return rc;
         if (!bytes) return fail(QS_ERR_ARG, "null output");
-        QPlan plan;
-        if (int rc = build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_shape(d->n), plan)) return rc;
-        *bytes = qaoa_layout(plan.geo, with_grad).bytes;
+        std::shared_ptr<const QPlan> plan;
+        if (int rc = cached_qplan(d, plan)) return rc;
+        *bytes = qaoa_layout(plan->geo, with_grad).bytes;
         return QS_OK;
     } catch (...) {
         return fail(QS_ERR_UNSUPPORTED, "unexpected internal error");
@@ -1546,9 +1593,9 @@ QS_API int qs_qaoa_run(const qs_qaoa_desc *d, const double *angles_dev, int B, d
     try {
         if (int rc = check_desc(d)) return rc;
         if (!angles_dev || !E_dev || !ws || B < 0) return fail(QS_ERR_ARG, "null angles, energies or workspace");
-        QPlan plan;
-        if (int rc = build_qplan(d->n, d->p, d->num_edges, d->edges, d->w, qaoa_default_shape(d->n), plan)) return rc;
-        const size_t circ = qaoa_layout(plan.geo, grad_dev != nullptr).bytes;
+        std::shared_ptr<const QPlan> plan;
+        if (int rc = cached_qplan(d, plan)) return rc;
+        const size_t circ = qaoa_layout(plan->geo, grad_dev != nullptr).bytes;
         if (ws_bytes < circ) return fail(QS_ERR_SIZE, "QAOA workspace too small");
         // As many angle sets per launch as the workspace holds.
         const u64 fit = ws_bytes / circ;
@@ -1556,7 +1603,7 @@ QS_API int qs_qaoa_run(const qs_qaoa_desc *d, const double *angles_dev, int B, d
         hipStream_t st = (hipStream_t)stream;
         for (int b0 = 0; b0 < B; b0 += per) {
             const int nb = B - b0 < per ? B - b0 : per;
-            const int rc = launch_qaoa_batch(plan, angles_dev + (size_t)b0 * 2 * d->p, nb, E_dev + b0,
+            const int rc = launch_qaoa_batch(*plan, angles_dev + (size_t)b0 * 2 * d->p, nb, E_dev + b0,
                                              grad_dev ? grad_dev + (size_t)b0 * 2 * d->p : nullptr, (char *)ws, circ, st);
             if (rc) return rc;
         }

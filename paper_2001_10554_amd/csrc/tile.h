@@ -61,8 +61,12 @@ struct JitFns {
 // one 1024-thread workgroup per CU, rows of 16) for the others, from
 // kJitMixedMinQubits qubits on.  Passes over high qubits gain from the longer
 // rows, a pass over the low qubits (one contiguous 64 KiB stretch per tile)
-// from the second workgroup.  QSIM_JIT_TB=12 or 13 forces one size.
-constexpr int kJitMixedMinQubits = 20;
+// from the second workgroup.  Measured on the sweep (one-qubit gate on every
+// qubit, CNOT chain) against 12-bit tiles throughout: 20 and 21 qubits 13 %
+// and 7 % slower (too few 13-bit tiles to fill 256 CUs), 22-24 qubits 0-4 %
+// faster, 26 1.5 % slower, 28 / 30 / 32 qubits 5.5 / 10 / 6 % faster.
+// QSIM_JIT_TB=12 or 13 forces one size.
+constexpr int kJitMixedMinQubits = 22;
 void jit_tile_shape(int n, int dtype, int &tile_bits, int &low_bits);
 int jit_threads(int dtype, int tile_bits);  // workgroup size of a compiled pass
 // Source of the plan's pass kernels; "" when a pass's tile is not a size the

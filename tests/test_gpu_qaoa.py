@@ -34,7 +34,11 @@ def _graph(n, seed):
     return W.random_regular_graph(n, 3, seed) if n % 2 == 0 and n >= 4 else W.ring_graph(n)
 
 
-@pytest.mark.parametrize("n,p", [(2, 1), (3, 2), (4, 1), (6, 3), (8, 2), (11, 2), (12, 3), (13, 2), (16, 2), (18, 2), (19, 1), (20, 2), (22, 1)])
+# (13, 1) and (14, 3): plain passes with RX on wave bits but none on the upper
+# lane bits (the backward without the third layout at the end); the other
+# sizes cover the plain and merged passes that end lambda in the third layout.
+@pytest.mark.parametrize("n,p", [(2, 1), (3, 2), (4, 1), (6, 3), (8, 2), (11, 2), (12, 3), (13, 1), (13, 2), (14, 3), (16, 2), (18, 2),
+                                 (19, 1), (20, 2), (22, 1)])
 def test_energy_and_gradient_vs_oracle(n, p):
     import torch
     edges = _graph(n, seed=100 + n)

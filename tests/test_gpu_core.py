@@ -91,7 +91,8 @@ def test_diag2_swap(dt):
 
 
 @pytest.mark.parametrize("dt", DTS)
-@pytest.mark.parametrize("n,count,seed", [(1, 10, 1), (3, 30, 2), (9, 80, 3), (12, 120, 4), (14, 150, 5), (17, 200, 6)])
+# n = 22: complex128 plans mix 12- and 13-bit compiled passes from 22 qubits on.
+@pytest.mark.parametrize("n,count,seed", [(1, 10, 1), (3, 30, 2), (9, 80, 3), (12, 120, 4), (14, 150, 5), (17, 200, 6), (22, 200, 7)])
 def test_block_matches_sequential(n, count, seed, dt):
     gates = W.random_block(n, count, seed) if n > 1 else W.random_block(n, count, seed, kinds=(W.G_1Q,))
     s = _state(n, dt).init_random(seed)

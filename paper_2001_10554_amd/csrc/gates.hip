@@ -247,14 +247,21 @@ static Shape1q shape_1q() {
 }
 
 // Per-XCD run length (in blocks of 512 pairs) for target q.  Measured on a
-// 32-qubit complex128 sweep: up to q = 17 runs of 128-256 blocks (1-2 MiB of
-// each partner stream per XCD) are best; above, the best run length doubles
-// with q mod 4 (16, 32, 64, 128 blocks for q = 0, 1, 2, 3 mod 4), i.e. it
-// tracks the address bits in which the two partner streams differ.
+// 32-qubit complex128 sweep (three alternating runs on one box, pairs spread
+// 2^11 apart): runs of 64 blocks for q = 6..15 (+30..140 GB/s over 128-256),
+// 128 for q = 16 and 256 for q = 17; above, the best length follows q mod 4
+// (the address bits in which the two partner streams differ): 64 for q = 2, 3
+// mod 4, 32 for q = 1 mod 4, and for q = 0 mod 4 16 at q = 20 but 64 at
+// q = 24, 28.
 static u32 chunk_for_target(int q) {
-    if (q <= 12 || q == 17) return 256;
-    if (q <= 16) return 128;
-    return 16u << ((q - 20) & 3);
+    if (q <= 15) return 64;
+    if (q == 16) return 128;
+    if (q == 17) return 256;
+    switch ((q - 20) & 3) {
+    case 0: return q == 20 ? 16 : 64;
+    case 1: return 32;
+    default: return 64;
+    }
 }
 
 // Spread of the two quads of a diagonal / SWAP thread (2^dlog apart; 8 =

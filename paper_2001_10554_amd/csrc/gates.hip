@@ -285,12 +285,17 @@ static int quad_spread(int want, u64 nquads) {
 // at every c >= 3 (runs: 5.1-6.2), CZ 6.5 (6.0), SWAP 6.4 (5.6).
 static u32 chunk_for_control(int, int) { return ~0u; }
 
-// The controlled gate, quads 2^11 apart: CNOT(c, c+1) for c = 13, 14 is
-// faster with runs of 256 blocks per XCD (c = 14: 5.59 -> 6.09 TB/s, c = 13:
-// 5.70 -> 5.95), while the other controls gain nothing or lose (c = 7:
-// 5.95 -> 5.20).
+// Per-XCD run length of the controlled gate (with the spreads of
+// spread_for_c1q below) for CNOT(c, c+1), c = 3..30; 0 stands for contiguous
+// eighths (chunk_for_control).  Measured on a 32-qubit complex128 register,
+// two runs of every control with runs of 64, 256, 1024 blocks and eighths;
+// the entries follow the DRAM address interleaving and were picked where
+// both runs agreed (weakest control 5.67 -> 5.73 TB/s of the touched half;
+// c = 25..28: +85..170 GB/s with runs of 64).
 static u32 chunk_for_c1q(int c, int t) {
-    if (t == c + 1 && (c == 13 || c == 14)) return 256;
+    static const u32 kRun[31] = {0,   0,   0,    64,   256,  1024, 0,  0,  64,  256, 0,  0,   256,  64,  256, 1024,
+                                 0,   0,   0,    1024, 1024, 1024, 0,  256, 256, 64, 64, 64,  64,   1024, 1024};
+    if (t == c + 1 && c >= 3 && c <= 30 && kRun[c]) return kRun[c];
     return chunk_for_control(c, t);
 }
 

@@ -15,7 +15,12 @@
 //
 // Each workgroup is persistent: it walks tiles blockIdx.x, + gridDim.x, ...
 // and prefetches the next tile's amplitudes into registers while the current
-// tile's sweeps run, so the HBM stream overlaps the arithmetic.
+// tile's sweeps run, so the HBM stream overlaps the arithmetic.  Every pass
+// has its own tile size (complex128: 12 bits for a tile of the lowest qubits,
+// 13 bits with longer rows for the others), workgroup size and LDS swizzle;
+// workgroup barriers sit only between LDS phases whose wavefront footprints
+// differ, and a pass over one contiguous stretch of the state streams it
+// non-temporally.
 #include <hip/hiprtc.h>
 
 #include <cstdio>

@@ -267,6 +267,9 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
     // QSIM_JIT_BARRIERS=1: a workgroup barrier between every two LDS phases
     // (see wave_pos below).
     const bool all_barriers = env("QSIM_JIT_BARRIERS", 0) != 0;
+    // QSIM_JIT_INREGS=0: always load tiles with the top three tile bits as
+    // register bits (see in_grp below).
+    const bool in_regs = env("QSIM_JIT_INREGS", 1) != 0;
     const int waves = env("QSIM_JIT_WAVES", 4);
     // QSIM_JIT_ORDER=k (k > 0): the tile counter's first k bits go to the k
     // lowest non-tile qubits and its other bits to the remaining non-tile
@@ -365,6 +368,35 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
                 if (((u64)k << TTB >> b) & 1) off |= 1ull << P.T[b];
             hi[k] = off;
         }
+        // Sweeps of the pass: (first gate, run, group bits).
+        struct Sw {
+            int begin, run, g0, g1, g2;
+        };
+        std::vector<Sw> sw;
+        for (int gi = P.gate_begin; gi < P.gate_begin + P.gate_count; gi += dg[gi].run)
+            sw.push_back({gi, dg[gi].run, dg[gi].g[0], dg[gi].g[1], dg[gi].g[2]});
+        // Load layout.  Stores always use the top three tile bits as register
+        // bits (thread t, register k: tile index t + NT k).  Loads use the
+        // first sweep's group bits instead when they all lie above the tile's
+        // contiguous row (so a wavefront still reads whole rows) and a thread
+        // holds one group: the first sweep then runs on the loaded registers,
+        // without the tile's first trip through LDS and its barrier.
+        const int row_bits = dtype == QS_C128 ? (TB > 12 ? 4 : 3) : 4;
+        const bool in_first = in_regs && gen.G == 1 && !sw.empty() && sw.front().g0 >= row_bits &&
+                              !(sw.front().g0 == TB - 3 && sw.front().g1 == TB - 2 && sw.front().g2 == TB - 1);
+        std::vector<u64> hii = hi;
+        if (in_first) {
+            const Sw &f = sw.front();
+            uint8_t q[16];
+            int nq = 0;
+            for (int p = 0; p < TB; ++p)
+                if (p != f.g0 && p != f.g1 && p != f.g2) q[nq++] = P.T[p];
+            o += "  const unsigned long long dti = " + deposit("(unsigned long long)t", q, nq) + ";\n";
+            for (int k = 0; k < PER; ++k)
+                hii[k] = ((k & 1) ? 1ull << P.T[f.g0] : 0) | ((k & 2) ? 1ull << P.T[f.g1] : 0) | ((k & 4) ? 1ull << P.T[f.g2] : 0);
+        } else {
+            o += "  const unsigned long long dti = dt;\n";
+        }
         uint8_t rest_order[40];
         for (int b = 0; b < P.nrest; ++b) rest_order[b] = P.rest[b];
         if (order_k > 0 && order_k < P.nrest)
@@ -378,7 +410,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
             o += "  unsigned tile = blockIdx.x;\n";
         if (prefetch) {
             o += "  if (tile < ntiles) {\n    const unsigned long long b0 = " + dep_tile + ";\n";
-            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = " + ld("b0 | dt | " + hex(hi[k])) + ";\n";
+            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = " + ld("b0 | dti | " + hex(hii[k])) + ";\n";
             o += "  }\n";
         }
         const size_t body_at = o.size();  // the loop header goes here
@@ -393,20 +425,14 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         o += "    unsigned tl = t; asm volatile(\"\" : \"+v\"(tl));\n";
         o += "    CR *vv; { unsigned long long a_ = (unsigned long long)v; asm volatile(\"\" : \"+s\"(a_)); vv = (CR *)a_; }\n";
         o += "    const unsigned long long base = " + dep_tile + ";\n";
-        // Sweeps of the pass: (first gate, run, group bits).
-        struct Sw {
-            int begin, run, g0, g1, g2;
-        };
-        std::vector<Sw> sw;
-        for (int gi = P.gate_begin; gi < P.gate_begin + P.gate_count; gi += dg[gi].run)
-            sw.push_back({gi, dg[gi].run, dg[gi].g[0], dg[gi].g[1], dg[gi].g[2]});
         // A sweep whose group bits are the tile's top three positions holds
         // exactly the amplitudes of the load/store layout (thread t, register
         // k: tile index t + 512 k): the first such sweep runs on the loaded
         // registers and the last one stores its registers, each saving one
-        // trip through LDS and a barrier.
+        // trip through LDS and a barrier.  (The first sweep also runs on the
+        // loaded registers with the load layout of in_first.)
         auto on_top = [&](const Sw &w) { return w.g0 == TB - 3 && w.g1 == TB - 2 && w.g2 == TB - 1; };
-        const bool first_regs = !sw.empty() && on_top(sw.front());
+        const bool first_regs = !sw.empty() && (on_top(sw.front()) || in_first);
         const bool last_regs = !sw.empty() && on_top(sw.back());
         auto hi_of = [&](u32 mhigh) {  // state offset of the tile bits of mhigh above the thread bits
             u64 off = 0;
@@ -445,11 +471,11 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         auto issue_prefetch = [&]() {
             if (!prefetch) return;
             o += "    { const unsigned nx = tile + gridDim.x;\n      if (nx < ntiles) {\n        const unsigned long long nb = " + dep_next + ";\n";
-            for (int k = 0; k < PER; ++k) o += "        pre[" + S(k) + "] = " + ld("nb | dt | " + hex(hi[k])) + ";\n";
+            for (int k = 0; k < PER; ++k) o += "        pre[" + S(k) + "] = " + ld("nb | dti | " + hex(hii[k])) + ";\n";
             o += "      }\n    }\n";
         };
         if (!prefetch)
-            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = " + ld("base | dt | " + hex(hi[k])) + ";\n";
+            for (int k = 0; k < PER; ++k) o += "    pre[" + S(k) + "] = " + ld("base | dti | " + hex(hii[k])) + ";\n";
         if (!first_regs) {
             for (int k = 0; k < PER; ++k) o += "    LDS(st ^ " + S(((u32)(k * NT) ^ hsw((u32)(k * NT))) << SH) + "u) = pre[" + S(k) + "];\n";
             if (sw.empty()) o += "    __syncthreads();\n";
@@ -466,8 +492,8 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
                 if (!from_regs || !to_global) o += "      const unsigned s" + S(g) + " = (m" + S(g) + " ^ " + HSW + "(m" + S(g) + ")) << " + S(SH) + ";\n";
                 for (int j = 0; j < 8; ++j) {
                     nm[g][j] = gen.fresh("x");
-                    if (from_regs)
-                        o += "      const C " + nm[g][j] + " = pre[" + S((g * NT + grp_off(w, j)) >> TTB) + "];\n";
+                    if (from_regs)  // register k of the load layout holds amplitude k of the group
+                        o += "      const C " + nm[g][j] + " = pre[" + S(in_first ? j : (g * NT + grp_off(w, j)) >> TTB) + "];\n";
                     else
                         o += "      const C " + nm[g][j] + " = LDS(s" + S(g) + " ^ " + S((grp_off(w, j) ^ hsw(grp_off(w, j))) << SH) + "u);\n";
                 }

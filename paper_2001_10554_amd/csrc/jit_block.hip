@@ -375,15 +375,30 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         std::vector<Sw> sw;
         for (int gi = P.gate_begin; gi < P.gate_begin + P.gate_count; gi += dg[gi].run)
             sw.push_back({gi, dg[gi].run, dg[gi].g[0], dg[gi].g[1], dg[gi].g[2]});
-        // Load layout.  Stores always use the top three tile bits as register
-        // bits (thread t, register k: tile index t + NT k).  Loads use the
-        // first sweep's group bits instead when they all lie above the tile's
-        // contiguous row (so a wavefront still reads whole rows) and a thread
-        // holds one group: the first sweep then runs on the loaded registers,
-        // without the tile's first trip through LDS and its barrier.
+        // Load and store layouts.  By default the top three tile bits are the
+        // register bits (thread t, register k: tile index t + NT k).  Loads
+        // use the first sweep's group bits instead when they all lie above
+        // the tile's contiguous row (so a wavefront still reads whole rows)
+        // and a thread holds one group: the first sweep then runs on the
+        // loaded registers, without the tile's first trip through LDS and its
+        // barrier.  Stores use the last sweep's group bits on the same terms.
         const int row_bits = dtype == QS_C128 ? (TB > 12 ? 4 : 3) : 4;
-        const bool in_first = in_regs && gen.G == 1 && !sw.empty() && sw.front().g0 >= row_bits &&
-                              !(sw.front().g0 == TB - 3 && sw.front().g1 == TB - 2 && sw.front().g2 == TB - 1);
+        auto own_layout = [&](const Sw &w) {
+            return in_regs && gen.G == 1 && w.g0 >= row_bits && !(w.g0 == TB - 3 && w.g1 == TB - 2 && w.g2 == TB - 1);
+        };
+        const bool in_first = !sw.empty() && own_layout(sw.front());
+        const bool out_last = !sw.empty() && own_layout(sw.back());
+        std::vector<u64> hio(8, 0);
+        if (out_last) {
+            const Sw &f = sw.back();
+            uint8_t q[16];
+            int nq = 0;
+            for (int p = 0; p < TB; ++p)
+                if (p != f.g0 && p != f.g1 && p != f.g2) q[nq++] = P.T[p];
+            o += "  const unsigned long long dto = " + deposit("(unsigned long long)t", q, nq) + ";\n";
+            for (int k = 0; k < 8; ++k)
+                hio[k] = ((k & 1) ? 1ull << P.T[f.g0] : 0) | ((k & 2) ? 1ull << P.T[f.g1] : 0) | ((k & 4) ? 1ull << P.T[f.g2] : 0);
+        }
         std::vector<u64> hii = hi;
         if (in_first) {
             const Sw &f = sw.front();
@@ -433,7 +448,7 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
         // loaded registers with the load layout of in_first.)
         auto on_top = [&](const Sw &w) { return w.g0 == TB - 3 && w.g1 == TB - 2 && w.g2 == TB - 1; };
         const bool first_regs = !sw.empty() && (on_top(sw.front()) || in_first);
-        const bool last_regs = !sw.empty() && on_top(sw.back());
+        const bool last_regs = !sw.empty() && (on_top(sw.back()) || out_last);
         auto hi_of = [&](u32 mhigh) {  // state offset of the tile bits of mhigh above the thread bits
             u64 off = 0;
             for (int b = TTB; b < TB; ++b)
@@ -499,7 +514,9 @@ std::string jit_block_source(const std::vector<DPass> &passes, const std::vector
                 }
             }
             for (int r = 0; r < w.run; ++r) gen.gate(dg[w.begin + r], w.begin + r, nm);
-            if (to_global) {
+            if (to_global && out_last) {  // register j of the store layout: amplitude j of the group
+                for (int j = 0; j < 8; ++j) o += "      " + stv("base | dto | " + hex(hio[j]), nm[0][j]);
+            } else if (to_global) {
                 for (int g = 0; g < gen.G; ++g)
                     for (int j = 0; j < 8; ++j)
                         o += "      " + stv("base | dt | " + hex(hi_of((u32)(g * NT) + grp_off(w, j))), nm[g][j]);

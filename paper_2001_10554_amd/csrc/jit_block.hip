@@ -610,12 +610,6 @@ std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<
                 if (((u64)k << 9 >> b) & 1) off |= 1ull << P.T[b];
             hi[k] = off;
         }
-        o += "  C pre[" + S(PER) + "];\n";
-        for (int k = 0; k < PER; ++k) {
-            const std::string idx = "(base | dt | " + hex(hi[k]) + ")";
-            o += "  if (fill) { pre[" + S(k) + "].x = " + idx + " == basis ? (R)1 : (R)0; pre[" + S(k) + "].y = (R)0; }\n";
-            o += "  else pre[" + S(k) + "] = __builtin_nontemporal_load(src + " + idx + ");\n";
-        }
         struct Sw {
             int begin, run, g0, g1, g2;
         };
@@ -623,8 +617,35 @@ std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<
         for (int gi = P.gate_begin; gi < P.gate_begin + P.gate_count; gi += dg[gi].run)
             sw.push_back({gi, dg[gi].run, dg[gi].g[0], dg[gi].g[1], dg[gi].g[2]});
         auto on_top = [&](const Sw &w) { return w.g0 == TB - 3 && w.g1 == TB - 2 && w.g2 == TB - 1; };
-        const bool first_regs = !sw.empty() && on_top(sw.front());
-        const bool last_regs = !sw.empty() && on_top(sw.back());
+        // Load and store layouts as in the block passes: the first / last
+        // sweep's group bits serve as register bits when they lie above the
+        // tile's contiguous row.
+        const int row_bits = dtype == QS_C128 ? 3 : 4;
+        auto own_layout = [&](const Sw &w) { return w.g0 >= row_bits && !on_top(w); };
+        const bool in_first = !sw.empty() && own_layout(sw.front());
+        const bool out_last = !sw.empty() && own_layout(sw.back());
+        auto group_layout = [&](const Sw &f, const char *name, std::vector<u64> &h) {
+            uint8_t q[16];
+            int nq = 0;
+            for (int p = 0; p < TB; ++p)
+                if (p != f.g0 && p != f.g1 && p != f.g2) q[nq++] = P.T[p];
+            o += "  const unsigned long long " + std::string(name) + " = " + deposit("(unsigned long long)tl", q, nq) + ";\n";
+            h.assign(8, 0);
+            for (int k = 0; k < 8; ++k)
+                h[k] = ((k & 1) ? 1ull << P.T[f.g0] : 0) | ((k & 2) ? 1ull << P.T[f.g1] : 0) | ((k & 4) ? 1ull << P.T[f.g2] : 0);
+        };
+        std::vector<u64> hii = hi, hio;
+        if (in_first) group_layout(sw.front(), "dti", hii);
+        else o += "  const unsigned long long dti = dt;\n";
+        if (out_last) group_layout(sw.back(), "dto", hio);
+        o += "  C pre[" + S(PER) + "];\n";
+        for (int k = 0; k < PER; ++k) {
+            const std::string idx = "(base | dti | " + hex(hii[k]) + ")";
+            o += "  if (fill) { pre[" + S(k) + "].x = " + idx + " == basis ? (R)1 : (R)0; pre[" + S(k) + "].y = (R)0; }\n";
+            o += "  else pre[" + S(k) + "] = __builtin_nontemporal_load(src + " + idx + ");\n";
+        }
+        const bool first_regs = !sw.empty() && (on_top(sw.front()) || in_first);
+        const bool last_regs = !sw.empty() && (on_top(sw.back()) || out_last);
         auto grp_off = [&](const Sw &w, int j) {
             return ((u32)(j & 1) << w.g0) | ((u32)((j >> 1) & 1) << w.g1) | ((u32)((j >> 2) & 1) << w.g2);
         };
@@ -666,15 +687,16 @@ std::string jit_traj_source(const std::vector<DPass> &passes, const std::vector<
             if (!from_regs || !to_global) o += "      const unsigned s0 = (m0 ^ hsw(m0)) << " + S(SH) + ";\n";
             for (int j = 0; j < 8; ++j) {
                 nm[0][j] = gen.fresh("x");
-                if (from_regs)
-                    o += "      const C " + nm[0][j] + " = pre[" + S(grp_off(w, j) >> 9) + "];\n";
+                if (from_regs)  // register k of the load layout holds amplitude k of the group
+                    o += "      const C " + nm[0][j] + " = pre[" + S(in_first ? j : grp_off(w, j) >> 9) + "];\n";
                 else
                     o += "      const C " + nm[0][j] + " = LDS(s0 ^ " + S((grp_off(w, j) ^ hsw(grp_off(w, j))) << SH) + "u);\n";
             }
             for (int r = 0; r < w.run; ++r) gen.gate(dg[w.begin + r], w.begin + r, nm);
             if (to_global) {
                 for (int j = 0; j < 8; ++j)
-                    o += "      __builtin_nontemporal_store(" + nm[0][j] + ", psi + (base | dt | " + hex(hi_of(grp_off(w, j))) + "));\n";
+                    o += "      __builtin_nontemporal_store(" + nm[0][j] + ", psi + (base | " +
+                         (out_last ? "dto | " + hex(hio[j]) : "dt | " + hex(hi_of(grp_off(w, j)))) + "));\n";
             } else {
                 for (int j = 0; j < 8; ++j) o += "      LDS(s0 ^ " + S((grp_off(w, j) ^ hsw(grp_off(w, j))) << SH) + "u) = " + nm[0][j] + ";\n";
                 sync("      ", wave_pos(&w), si + 1 < sw.size() ? wave_pos(&sw[si + 1]) : h_io);
